@@ -1,0 +1,214 @@
+"""CPU oracle for the 2-forest-sampling Kemeny-constant estimator.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  It shares no
+code with the GPU library (``paper_2511_16356_amd``) and never imports it.
+
+``kc_oracle.c`` (plain C, gcc) holds the sampler and the four forms of
+f(tau); ``exact.py`` (numpy/scipy, FP64) holds the exact Kemeny constant, the
+expected Wilson work, closed forms and spanning-tree enumeration used to pin
+the oracle to the mathematics.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "kc_oracle.c")
+_LIB = os.path.join(_HERE, "libkc_oracle.so")
+_lib = None
+
+F_NAIVE, F_ALG1, F_PEREDGE, F_WALK, F_ALG1_PRINTED = 1, 2, 3, 4, 5
+FORMS = {"naive": F_NAIVE, "alg1": F_ALG1, "peredge": F_PEREDGE, "walk": F_WALK,
+         "alg1_printed": F_ALG1_PRINTED}
+
+ERRORS = {1: "invalid graph", 2: "graph is disconnected", 3: "out of memory", 6: "step limit"}
+
+
+def build(force: bool = False) -> str:
+    """Compile kc_oracle.c into libkc_oracle.so (gcc -O2 -pthread)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-pthread", "-shared", "-fPIC",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        p, i64, i32, u64, u32 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                 ctypes.c_uint64, ctypes.c_uint32)
+        lib.orc_philox.restype = None
+        lib.orc_philox.argtypes = [p, p, p]
+        lib.orc_arrow.restype = u32
+        lib.orc_arrow.argtypes = [u64, u64, u32, u32, u32]
+        lib.orc_prepare.restype = ctypes.c_int
+        lib.orc_prepare.argtypes = [i64, p, p, i32, p, p, p, p, p, p]
+        lib.orc_wilson_order.restype = ctypes.c_int
+        lib.orc_wilson_order.argtypes = [i64, p, p, i32, u64, u64, p, p, p, p]
+        lib.orc_f.restype = ctypes.c_int
+        lib.orc_f.argtypes = [i64, p, i32, p, p, p, p, ctypes.c_int, p]
+        lib.orc_sample.restype = ctypes.c_int
+        lib.orc_sample.argtypes = [i64, p, p, i32, u64, i64, i64, ctypes.c_int, i64, p, p, p]
+        lib.orc_estimate.restype = ctypes.c_int
+        lib.orc_estimate.argtypes = [i64, p, p, i32, p, p, p, u64, i64, i64, ctypes.c_int,
+                                     ctypes.c_int, i64, p, p]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _check(st: int):
+    if st != 0:
+        raise RuntimeError("oracle: " + ERRORS.get(st, "error %d" % st))
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _load().orc_philox(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def arrow(seed: int, s: int, v: int, k: int, deg: int) -> int:
+    return int(_load().orc_arrow(seed, s, v, k, deg))
+
+
+@dataclass
+class Prepared:
+    """Graph with root, BFS tree tau0 and tau0 numbering (oracle side)."""
+
+    n: int
+    offsets: np.ndarray
+    indices: np.ndarray
+    root: int
+    p0: np.ndarray
+    dist: np.ndarray
+    in0: np.ndarray
+    out0: np.ndarray
+    depth0: int
+
+    @property
+    def two_m(self) -> int:
+        return int(self.offsets[-1])
+
+    @property
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.offsets)
+
+
+def prepare(offsets, indices, root: int = -1) -> Prepared:
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    adj = np.ascontiguousarray(indices, dtype=np.int32)
+    n = off.shape[0] - 1
+    p0 = np.zeros(n, np.int32); dist = np.zeros(n, np.int32)
+    in0 = np.zeros(n, np.int32); out0 = np.zeros(n, np.int32)
+    r = ctypes.c_int32(); dep = ctypes.c_int32()
+    _check(_load().orc_prepare(n, _ptr(off), _ptr(adj), root, ctypes.byref(r), _ptr(p0),
+                               _ptr(dist), _ptr(in0), _ptr(out0), ctypes.byref(dep)))
+    return Prepared(n, off, adj, int(r.value), p0, dist, in0, out0, int(dep.value))
+
+
+def prepare_graph(g, root: int = -1) -> Prepared:
+    return prepare(g.offsets, g.indices, root)
+
+
+def with_tau0(P: Prepared, p0) -> Prepared:
+    """Same graph and root, but an arbitrary fixed spanning tree tau0 given by
+    its parent array (root -> -1); recomputes its preorder numbering."""
+    p0 = np.ascontiguousarray(p0, dtype=np.int32)
+    n = P.n
+    children = [[] for _ in range(n)]
+    for v in range(n):
+        if v != P.root:
+            children[int(p0[v])].append(v)
+    in0 = np.zeros(n, np.int32); out0 = np.zeros(n, np.int32)
+    t = 0
+    stack = [(P.root, 0)]
+    in0[P.root] = t; t += 1
+    while stack:
+        x, i = stack.pop()
+        if i < len(children[x]):
+            stack.append((x, i + 1))
+            c = children[x][i]
+            in0[c] = t; t += 1
+            stack.append((c, 0))
+        else:
+            out0[x] = t - 1
+    return Prepared(n, P.offsets, P.indices, P.root, p0, P.dist, in0, out0, P.depth0)
+
+
+def wilson(P: Prepared, seed: int, s: int, order=None):
+    """One Wilson tree: (parent [n] int32 with root -1, draws [n] uint32, total draws)."""
+    n = P.n
+    parent = np.zeros(n, np.int32); cnt = np.zeros(n, np.uint32)
+    steps = ctypes.c_int64()
+    o = None if order is None else np.ascontiguousarray(order, dtype=np.int32)
+    _check(_load().orc_wilson_order(n, _ptr(P.offsets), _ptr(P.indices), P.root, seed, s,
+                                    _ptr(o), _ptr(parent), _ptr(cnt), ctypes.byref(steps)))
+    return parent, cnt, int(steps.value)
+
+
+def f_of_tree(P: Prepared, parent, form: str = "alg1") -> int:
+    par = np.ascontiguousarray(parent, dtype=np.int32)
+    f = ctypes.c_int64()
+    _check(_load().orc_f(P.n, _ptr(P.offsets), P.root, _ptr(P.p0), _ptr(P.in0), _ptr(P.out0),
+                         _ptr(par), FORMS[form], ctypes.byref(f)))
+    return int(f.value)
+
+
+def sample(P: Prepared, seed: int, s0: int, count: int, threads: int = 1, max_steps: int = 0):
+    """Trees for samples s0..s0+count-1: parents [count, n], draws [count, n], totals [count]."""
+    n = P.n
+    parents = np.zeros((count, n), np.int32)
+    cnts = np.zeros((count, n), np.uint32)
+    steps = np.zeros(count, np.int64)
+    _check(_load().orc_sample(n, _ptr(P.offsets), _ptr(P.indices), P.root, seed, s0, count,
+                              threads, max_steps, _ptr(parents), _ptr(cnts), _ptr(steps)))
+    return parents, cnts, steps
+
+
+def estimate_f(P: Prepared, seed: int, s0: int, count: int, threads: int = 1,
+               form: str = "alg1", max_steps: int = 0):
+    """Per-sample f (int64) and total draws for samples s0..s0+count-1."""
+    f = np.zeros(count, np.int64)
+    steps = np.zeros(count, np.int64)
+    _check(_load().orc_estimate(P.n, _ptr(P.offsets), _ptr(P.indices), P.root, _ptr(P.p0),
+                                _ptr(P.in0), _ptr(P.out0), seed, s0, count, threads,
+                                FORMS[form], max_steps, _ptr(f), _ptr(steps)))
+    return f, steps
+
+
+def reduce_estimate(f, two_m: int):
+    """Theorem 3.3's estimator from exact per-sample values.
+
+    Returns (K, stderr, sum_f, sum_f2): sum_f and sum_f2 are exact Python
+    integers; K = float(sum_f) / (2m * count) (one correctly-rounded integer to
+    double conversion, one double division); stderr is the sample standard
+    deviation of f/2m over sqrt(count), from the exact sums."""
+    vals = [int(x) for x in np.asarray(f, dtype=np.int64)]
+    w = len(vals)
+    s1 = sum(vals)
+    s2 = sum(x * x for x in vals)
+    K = float(s1) / float(two_m * w)
+    if w > 1:
+        mean = float(s1) / w
+        var = (float(s2) - w * mean * mean) / (w - 1)
+        se = math.sqrt(max(var, 0.0) / w) / two_m
+    else:
+        se = float("nan")
+    return K, se, s1, s2

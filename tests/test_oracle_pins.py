@@ -1,0 +1,269 @@
+"""Pins of the CPU oracle to the paper and to mathematics (no GPU).
+
+Each test checks the oracle against something other than itself: an
+independent Philox implementation, closed forms, the hitting-time definition
+of the Kemeny constant, exhaustive spanning-tree enumeration, the paper's
+worked triangle example, the cycle-popping order-independence theorem, and
+chi-square uniformity of the sampled trees.
+"""
+import json
+import os
+import shutil
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import stats
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ------------------------------------------------------------------ Philox
+
+@pytest.fixture(scope="module")
+def rocrand_probe(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path_factory.mktemp("probe") / "philox_probe")
+    subprocess.check_call([hipcc, "-O1", "-o", exe, os.path.join(HERE, "rocrand_philox_probe.cpp")],
+                          cwd=str(tmp_path_factory.getbasetemp()))
+    return exe
+
+
+def test_philox_matches_rocrand(oracle_lib, rocrand_probe):
+    rng = np.random.default_rng(7)
+    cases = [[0] * 6, [0xFFFFFFFF] * 6, [1, 2, 3, 4, 5, 6]]
+    cases += rng.integers(0, 2 ** 32, size=(200, 6), dtype=np.uint64).tolist()
+    inp = "\n".join(" ".join(str(int(x)) for x in c) for c in cases) + "\n"
+    out = subprocess.run([rocrand_probe], input=inp, capture_output=True, text=True, check=True).stdout
+    ref = [list(map(int, line.split())) for line in out.strip().splitlines()]
+    assert len(ref) == len(cases)
+    for c, r in zip(cases, ref):
+        got = oracle_lib.philox4x32_10(c[:4], c[4:])
+        assert got.tolist() == r, (c, got, r)
+
+
+def test_arrow_slots_uniform(oracle_lib):
+    """Slots drawn for fixed degree are uniform (chi-square) and in range."""
+    for deg in (2, 3, 7, 13):
+        counts = np.zeros(deg, np.int64)
+        for v in range(400):
+            for k in range(25):
+                j = oracle_lib.arrow(12345, 3, v, k, deg)
+                assert 0 <= j < deg
+                counts[j] += 1
+        p = stats.chisquare(counts).pvalue
+        assert p > 1e-4, (deg, counts)
+
+
+# ------------------------------------------------- exact-K checker pins
+
+def test_closed_forms_match_eigensolve(gen):
+    from oracle import exact as E
+    for n in range(2, 9):
+        g = gen.complete(n)
+        assert E.kemeny_exact(g.offsets, g.indices) == pytest.approx(float(E.kemeny_complete(n)), rel=1e-12)
+    for n in range(3, 12):
+        g = gen.cycle(n)
+        assert E.kemeny_exact(g.offsets, g.indices) == pytest.approx(float(E.kemeny_cycle(n)), rel=1e-12)
+    for n in range(2, 12):
+        g = gen.path(n)
+        assert E.kemeny_exact(g.offsets, g.indices) == pytest.approx(float(E.kemeny_path(n)), rel=1e-12)
+    for n in range(3, 12):
+        g = gen.star(n)
+        assert E.kemeny_exact(g.offsets, g.indices) == pytest.approx(float(E.kemeny_star(n)), rel=1e-12)
+    for a, b in ((6, 8), (5, 7), (3, 3)):
+        g = gen.torus(a, b)
+        assert E.kemeny_exact(g.offsets, g.indices) == pytest.approx(E.kemeny_torus(a, b), rel=1e-12)
+    for d in (3, 5, 8):
+        g = gen.hypercube(d)
+        assert E.kemeny_exact(g.offsets, g.indices) == pytest.approx(float(E.kemeny_hypercube(d)), rel=1e-11)
+
+
+def test_kemeny_equals_hitting_time_definition(gen):
+    """kappa = sum_j pi_j H(i, j) for every start i (the definition), against
+    the spectral form of Eq. (1)."""
+    from oracle import exact as E
+    for g in (gen.gnm(12, 25, 3), gen.barabasi_albert(15, 2, 1), gen.grid(3, 4)):
+        a = g.dense_adjacency()
+        d = a.sum(1)
+        p = a / d[:, None]
+        n = g.n
+        pi = d / d.sum()
+        h = np.zeros((n, n))
+        for j in range(n):
+            keep = [i for i in range(n) if i != j]
+            m = np.eye(n - 1) - p[np.ix_(keep, keep)]
+            h[keep, j] = np.linalg.solve(m, np.ones(n - 1))
+        kem = h @ pi
+        assert np.allclose(kem, kem[0], rtol=1e-10)
+        assert kem[0] == pytest.approx(E.kemeny_exact(g.offsets, g.indices), rel=1e-10)
+
+
+# ------------------------------------------------------- f(tau) pins
+
+def _tiny_graphs(gen):
+    return [gen.complete(3), gen.complete(4), gen.complete(5), gen.cycle(5), gen.cycle(6),
+            gen.path(5), gen.grid(3, 3), gen.grid(2, 4), gen.petersen(), gen.gnm(7, 11, 1)]
+
+
+def test_enumeration_mean_equals_exact_kemeny(gen, oracle_lib):
+    """Theorem 3.3 exactly: the mean of f/2m over ALL spanning trees is kappa;
+    the enumerated tree count matches the matrix-tree theorem."""
+    from oracle import exact as E
+    for g in _tiny_graphs(gen):
+        P = oracle_lib.prepare_graph(g)
+        trees = E.spanning_trees(g.offsets, g.indices, P.root)
+        assert len(trees) == E.tree_count(g.offsets, g.indices)
+        for form in ("naive", "alg1", "peredge", "walk"):
+            fs = [oracle_lib.f_of_tree(P, t, form) for t in trees]
+            mean = Fraction(sum(fs), len(fs) * g.two_m)
+            assert float(mean) == pytest.approx(E.kemeny_exact(g.offsets, g.indices), rel=1e-12), (g.name, form)
+
+
+def test_enumeration_with_non_bfs_tau0(gen, oracle_lib):
+    """Theorems 3.2-3.4 hold for any fixed spanning tree tau0, not only BFS."""
+    from oracle import exact as E
+    for g in (gen.grid(3, 3), gen.petersen(), gen.gnm(7, 11, 1)):
+        P = oracle_lib.prepare_graph(g)
+        trees = E.spanning_trees(g.offsets, g.indices, P.root)
+        K = E.kemeny_exact(g.offsets, g.indices)
+        for t0 in (trees[0], trees[len(trees) // 2], trees[-1]):
+            Q = oracle_lib.with_tau0(P, t0)
+            for form in ("naive", "alg1", "peredge", "walk"):
+                fs = [oracle_lib.f_of_tree(Q, t, form) for t in trees]
+                assert sum(fs) / (len(fs) * g.two_m) == pytest.approx(K, rel=1e-12)
+
+
+def test_worked_triangle_example(gen, oracle_lib):
+    ex = json.load(open(os.path.join(HERE, "golden", "k3_worked_example.json")))
+    g = gen.complete(3)
+    P = oracle_lib.prepare_graph(g)
+    assert P.root == ex["root"]
+    for key, fval in ex["bfs_tau0"]["f"].items():
+        parent = np.array([int(x) for x in key.split(",")], np.int32)
+        for form in ("naive", "alg1", "peredge", "walk"):
+            assert oracle_lib.f_of_tree(P, parent, form) == fval
+    num, den = ex["bfs_tau0"]["kappa"]
+    assert Fraction(sum(ex["bfs_tau0"]["f"].values()), 3 * g.two_m) == Fraction(num, den)
+    Q = oracle_lib.with_tau0(P, ex["path_tau0"]["p0"])
+    tot = 0
+    for key, fval in ex["path_tau0"]["f"].items():
+        parent = np.array([int(x) for x in key.split(",")], np.int32)
+        for form in ("naive", "alg1", "peredge", "walk"):
+            assert oracle_lib.f_of_tree(Q, parent, form) == fval
+        tot += fval
+    assert tot == ex["path_tau0"]["sum_f_equals_2m_trees_kappa"]
+    # the 2-forest side of the same example: sum_u d(u) sum vol(T1) = 2m |trees| kappa
+    tf = ex["two_forests"]
+    s = sum(2 * tf[F]["vol_T1"] for u, Fs in tf["separating"].items() for F in Fs)
+    assert s == tot
+
+
+@pytest.mark.parametrize("name", ["grid8", "grid12", "gnm60", "ba80"])
+def test_forms_agree_on_sampled_trees(gen, oracle_lib, name):
+    g = {"grid8": lambda: gen.grid(8, 8), "grid12": lambda: gen.grid(12, 12),
+         "gnm60": lambda: gen.largest_component(gen.gnm(60, 150, 2)),
+         "ba80": lambda: gen.barabasi_albert(80, 2, 5)}[name]()
+    P = oracle_lib.prepare_graph(g)
+    parents, _, _ = oracle_lib.sample(P, seed=11, s0=0, count=40)
+    for t in parents:
+        vals = {form: oracle_lib.f_of_tree(P, t, form) for form in ("naive", "alg1", "peredge", "walk")}
+        assert len(set(vals.values())) == 1, vals
+        assert vals["naive"] > 0
+
+
+def test_printed_undo_sign_disagrees(gen, oracle_lib):
+    """Algorithm 1's undo for the reverse case, taken with the printed sign,
+    breaks Theorem 3.3 on larger graphs; the corrected sign matches F1."""
+    g = gen.grid(8, 8)
+    P = oracle_lib.prepare_graph(g)
+    parents, _, _ = oracle_lib.sample(P, seed=3, s0=0, count=60)
+    bad = sum(oracle_lib.f_of_tree(P, t, "alg1_printed") != oracle_lib.f_of_tree(P, t, "naive")
+              for t in parents)
+    assert bad > 0
+
+
+# --------------------------------------------------------- sampler pins
+
+def test_root_and_bfs_rules(gen, oracle_lib):
+    g = gen.grid(32, 32)
+    P = oracle_lib.prepare_graph(g)
+    assert P.root == 33          # first degree-4 vertex
+    assert P.depth0 == 60        # eccentricity of (1,1) in the 32x32 grid
+    # BFS parent = smallest-index neighbour one level up
+    for v in range(g.n):
+        if v == P.root:
+            assert P.p0[v] == -1
+            continue
+        nb = g.indices[g.offsets[v]:g.offsets[v + 1]]
+        ups = [u for u in nb if P.dist[u] == P.dist[v] - 1]
+        assert P.p0[v] == min(ups)
+    # preorder intervals nest exactly like subtrees of tau0
+    for v in range(g.n):
+        if v != P.root:
+            u = P.p0[v]
+            assert P.in0[u] < P.in0[v] <= P.out0[v] <= P.out0[u]
+
+
+def test_wilson_order_independent(gen, oracle_lib):
+    """Cycle popping: parents and per-vertex draw counts do not depend on the
+    order in which walks are started."""
+    rng = np.random.default_rng(0)
+    for g in (gen.grid(10, 10), gen.barabasi_albert(60, 2, 3), gen.largest_component(gen.gnm(50, 90, 4))):
+        P = oracle_lib.prepare_graph(g)
+        for s in range(15):
+            base = oracle_lib.wilson(P, 99, s)
+            for _ in range(3):
+                order = rng.permutation(g.n).astype(np.int32)
+                other = oracle_lib.wilson(P, 99, s, order)
+                assert np.array_equal(base[0], other[0])
+                assert np.array_equal(base[1], other[1])
+                assert base[2] == other[2]
+
+
+@pytest.mark.parametrize("name,count", [("K4", 8000), ("grid3", 19200), ("petersen", 60000)])
+def test_tree_uniformity_chi2(gen, oracle_lib, name, count):
+    from oracle import exact as E
+    g = {"K4": lambda: gen.complete(4), "grid3": lambda: gen.grid(3, 3), "petersen": gen.petersen}[name]()
+    P = oracle_lib.prepare_graph(g)
+    trees = E.spanning_trees(g.offsets, g.indices, P.root)
+    index = {t.tobytes(): i for i, t in enumerate(trees)}
+    parents, _, _ = oracle_lib.sample(P, seed=2024, s0=0, count=count, threads=4)
+    hits = np.zeros(len(trees), np.int64)
+    for t in parents:
+        hits[index[t.tobytes()]] += 1
+    assert hits.sum() == count
+    assert stats.chisquare(hits).pvalue > 1e-4
+
+
+def test_mean_draws_equal_phi(gen, oracle_lib):
+    """Expected Wilson work is Tr((I - P_r)^-1) (section 2.2, Theorem 3.5)."""
+    from oracle import exact as E
+    g = gen.grid(32, 32)
+    P = oracle_lib.prepare_graph(g)
+    phi = E.phi_exact(g.offsets, g.indices, P.root)
+    _, steps = oracle_lib.estimate_f(P, seed=0, s0=0, count=2000, threads=8)
+    se = steps.std(ddof=1) / np.sqrt(len(steps))
+    assert abs(steps.mean() - phi) < 4.5 * se, (steps.mean(), phi, se)
+
+
+def test_estimator_close_to_exact_kemeny(gen, oracle_lib):
+    """Unbiasedness at scale: K-hat within 4.5 standard errors of exact K."""
+    from oracle import exact as E
+    for g, count in ((gen.grid(32, 32), 4000), (gen.torus(20, 20), 1000), (gen.hypercube(8), 400)):
+        P = oracle_lib.prepare_graph(g)
+        f, _ = oracle_lib.estimate_f(P, seed=5, s0=0, count=count, threads=8)
+        K, se, _, _ = oracle_lib.reduce_estimate(f, g.two_m)
+        Kx = E.kemeny_exact(g.offsets, g.indices)
+        assert abs(K - Kx) < 4.5 * se, (g.name, K, Kx, se)
+
+
+def test_reduce_estimate_exact_sums(oracle_lib):
+    f = np.array([2 ** 62, 2 ** 62, 2 ** 62, 5], np.int64)
+    K, se, s1, s2 = oracle_lib.reduce_estimate(f, 10)
+    assert s1 == 3 * 2 ** 62 + 5
+    assert s2 == 3 * 2 ** 124 + 25
+    assert K == float(3 * 2 ** 62 + 5) / 40.0
