@@ -1,0 +1,179 @@
+/*
+ * kc.h -- C ABI of the MI355X (gfx950) Kemeny-constant library.
+ *
+ * The library evaluates the 2-forest-sampling estimator of Li, Liao, Li and
+ * Wang, "Scalable and Provable Kemeny Constant Computation on Static and
+ * Dynamic Graphs: A 2-Forest Sampling Approach" (arXiv 2511.16356):
+ *
+ *     kappa(G) ~= (1 / (2 m omega)) * sum_{i=1..omega} f(tau_i)     (Theorem 3.3)
+ *
+ * where tau_i are uniform spanning trees drawn with Wilson's algorithm
+ * (section 2.2; Algorithm 1) and f(tau) is the path-mapping value of
+ * Theorem 3.3, evaluated per tree with the per-edge identity of Theorem 3.4
+ * (subtree volumes over a fixed BFS tree tau0).  Every step after graph
+ * preparation runs in HIP kernels on the GPU.
+ *
+ * Conventions shared by all calls
+ *   - Every call returns a kc_status; nothing throws across the ABI.
+ *     kc_last_error() gives a human-readable detail for the calling thread.
+ *   - A graph is a simple, connected, undirected graph (section 2.1) given
+ *     as CSR: row v lists the neighbours of v in strictly ascending order,
+ *     each undirected edge appears in both rows, no self-loops.
+ *   - "device pointer" means memory on the current HIP device (for example a
+ *     torch CUDA tensor's data_ptr); "host pointer" means ordinary memory.
+ *     The caller owns every array it passes; the library owns kc_graph.
+ *   - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue their kernels on it and return after the stream has
+ *     finished the call's work, so outputs are ready on return.
+ *   - Calls on one kc_graph must not overlap; different graphs are
+ *     independent.
+ *   - A sample is identified by its global index s (not its batch
+ *     position): the tree of sample s is a pure function of (graph, root,
+ *     seed, s), identical alone or in any batch, for any launch shape.
+ */
+#ifndef KC_H
+#define KC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KC_OK = 0,
+    KC_ERR_INVALID = 1,      /* malformed CSR, bad argument, bad root, self-loop, duplicate */
+    KC_ERR_DISCONNECTED = 2, /* the graph is not connected (section 2.1 requires it) */
+    KC_ERR_NOMEM = 3,        /* device or host allocation failed */
+    KC_ERR_DEVICE = 4,       /* a HIP runtime call failed */
+    KC_ERR_OVERFLOW = 5,     /* 4 m^2 depth(tau0) >= 2^63, or 2m >= 2^31 (32-bit volumes) */
+    KC_ERR_LIMIT = 6,        /* a sample exceeded the step limit; its results are discarded */
+    KC_ERR_UNSUPPORTED = 7   /* a size outside what the kernels are built for */
+} kc_status;
+
+typedef struct kc_graph kc_graph;
+
+/* Read-only facts about a prepared graph. */
+typedef struct {
+    int64_t n;          /* vertices */
+    int64_t two_m;      /* sum of degrees = 2 |E| */
+    int32_t root;       /* r: highest degree, smallest index on ties, unless given */
+    int32_t depth0;     /* depth of the BFS tree tau0 = eccentricity of r */
+    int32_t max_degree;
+    int32_t traversal;  /* KC_TRAV_WALK or KC_TRAV_SWEEP, as chosen for this graph */
+    int64_t device_bytes; /* graph arrays resident on the device */
+} kc_graph_info;
+
+/* Traversal variants for f(tau) (Theorem 3.4); results are identical. */
+enum {
+    KC_TRAV_AUTO = 0,
+    KC_TRAV_WALK = 1,  /* per vertex, walk its tau0 ancestors: O(n depth0) per tree */
+    KC_TRAV_SWEEP = 2  /* tau0-preorder sweep with a Fenwick tree over tau's volume-weighted
+                          numbering: O(n log m) per tree (the paper's O(n log n) form) */
+};
+
+/* Options for kc_set_option. */
+enum {
+    KC_OPT_WALKERS = 1,    /* cooperating walkers per sample, 1..64 (default 64) */
+    KC_OPT_SLOTS = 2,      /* samples in flight per launch (0 = sized from free HBM) */
+    KC_OPT_TRAVERSAL = 3,  /* KC_TRAV_* */
+    KC_OPT_STEP_LIMIT = 4, /* per-sample cap on sampler iterations (0 = default 4096 n + 2^20) */
+    KC_OPT_MEM_BUDGET = 5  /* bytes of device workspace the library may allocate (0 = 60% of free) */
+};
+
+/*
+ * Prepare a graph (Algorithm 1, "Generate tau0 using BFS" and the DFN of
+ * tau0; root choice of section 5).  Validates the CSR, checks connectivity,
+ * picks r, builds tau0 (BFS parent = smallest-index neighbour one level
+ * closer to r) and tau0's preorder numbering, and copies everything the
+ * kernels need to the device.
+ *   n        : vertex count, >= 2
+ *   offsets  : HOST pointer, n+1 entries, int64 if offsets_are_i64 else int32
+ *   indices  : HOST pointer, offsets[n] int32 entries
+ *   root     : -1 to choose automatically, else the root vertex
+ *   out      : receives the handle (NULL on failure)
+ * Errors: KC_ERR_INVALID, KC_ERR_DISCONNECTED, KC_ERR_OVERFLOW, KC_ERR_NOMEM,
+ * KC_ERR_DEVICE, KC_ERR_UNSUPPORTED (max degree >= 2^20).
+ */
+kc_status kc_graph_create(int64_t n, const void *offsets, int offsets_are_i64,
+                          const int32_t *indices, int32_t root, void *hip_stream,
+                          kc_graph **out);
+
+/* Free the graph and its device workspace.  NULL is accepted. */
+kc_status kc_graph_destroy(kc_graph *g);
+
+/* Copy the graph's facts into *info (host pointer). */
+kc_status kc_graph_get_info(const kc_graph *g, kc_graph_info *info);
+
+/* Set a KC_OPT_* option.  KC_ERR_INVALID for an unknown option or value. */
+kc_status kc_set_option(kc_graph *g, int option, int64_t value);
+
+/*
+ * Draw the uniform spanning trees of samples first_sample ..
+ * first_sample+count-1 with Wilson's algorithm (section 2.2), each
+ * (sample s, vertex v, k-th draw at v) taking neighbour slot
+ * floor(x * deg(v) / 2^64) of v's row, where x = o0 | o1 << 32 are the first
+ * two words of Philox4x32-10 (Salmon et al., SC'11) with counter
+ * (k, v, s_lo, s_hi) and key (seed_lo, seed_hi).  Many walkers cooperate on
+ * one sample by cycle popping, so the tree and the per-vertex draw counts are
+ * the unique cycle-popping outcome of these arrows.
+ *   parents_out   : DEVICE pointer, count*n int32, row i = sample first+i,
+ *                   parents_out[i*n + v] = parent of v in the tree (root: -1)
+ *   popcounts_out : DEVICE pointer or NULL, count*n uint32, number of draws
+ *                   made at v (0 at the root)
+ *   steps_out     : DEVICE pointer or NULL, count int64, total draws per sample
+ * Errors: KC_ERR_INVALID (count < 0, NULL parents_out with count > 0),
+ * KC_ERR_LIMIT, KC_ERR_NOMEM, KC_ERR_DEVICE.
+ */
+kc_status kc_sample_trees(kc_graph *g, uint64_t seed, int64_t first_sample, int32_t count,
+                          int32_t *parents_out, uint32_t *popcounts_out, int64_t *steps_out,
+                          void *hip_stream);
+
+/* Result of an estimate (host struct). */
+typedef struct {
+    double kappa;        /* (double)(sum f) / (2m * count): one rounding of the exact sum,
+                            one division (Algorithm 1, last line; Theorem 3.3) */
+    double std_error;    /* sample standard deviation of f/2m over sqrt(count) */
+    uint64_t sum_f_lo;   /* exact sum of f as a two's-complement 128-bit integer */
+    int64_t sum_f_hi;
+    uint64_t sum_f2_lo;  /* exact sum of f^2 (unsigned 128-bit) */
+    uint64_t sum_f2_hi;
+    int64_t count;
+    int64_t total_steps; /* Wilson draws over all samples */
+} kc_result;
+
+/*
+ * Sample trees first_sample .. first_sample+count-1 (as kc_sample_trees)
+ * and evaluate f(tau) for each on the device (Theorems 3.3/3.4), then reduce
+ * exactly.  f is an exact int64 per tree.
+ *   result : HOST pointer (required)
+ *   f_out  : DEVICE pointer or NULL, count int64 per-sample f
+ *   steps_out : DEVICE pointer or NULL, count int64 draws per sample
+ * Errors: as kc_sample_trees; KC_ERR_INVALID for count < 1.
+ */
+kc_status kc_estimate(kc_graph *g, uint64_t seed, int64_t first_sample, int32_t count,
+                      kc_result *result, int64_t *f_out, int64_t *steps_out, void *hip_stream);
+
+/*
+ * Evaluate f for caller-supplied rooted spanning trees (no sampling).
+ *   parents : DEVICE pointer, count*n int32 parent arrays rooted at the
+ *             graph's root (root -> -1); every edge (v, parent[v]) must be a
+ *             graph edge and the array must describe a spanning tree
+ *             (not checked on the device: a non-tree gives an undefined f,
+ *             never an out-of-bounds access).
+ *   f_out   : DEVICE pointer, count int64
+ */
+kc_status kc_evaluate_trees(kc_graph *g, const int32_t *parents, int32_t count, int64_t *f_out,
+                            void *hip_stream);
+
+/* Static description of a status code. */
+const char *kc_status_string(kc_status s);
+
+/* Detail message of the calling thread's last failing call ("" if none). */
+const char *kc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KC_H */

@@ -1,0 +1,213 @@
+"""Python binding of the MI355X Kemeny-constant library (``include/kc.h``).
+
+Argument marshalling only: every step of the estimator runs in the HIP
+library ``libkc_mi355x.so`` built from ``csrc/``.  PyTorch provides device
+memory (output tensors) and the current HIP stream.  If the library has not
+been built, importing works but every call raises ``KcError`` -- there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkc_mi355x.so")
+
+KC_OK = 0
+STATUS = {0: "KC_OK", 1: "KC_ERR_INVALID", 2: "KC_ERR_DISCONNECTED", 3: "KC_ERR_NOMEM",
+          4: "KC_ERR_DEVICE", 5: "KC_ERR_OVERFLOW", 6: "KC_ERR_LIMIT", 7: "KC_ERR_UNSUPPORTED"}
+KC_TRAV_AUTO, KC_TRAV_WALK, KC_TRAV_SWEEP = 0, 1, 2
+KC_OPT_WALKERS, KC_OPT_SLOTS, KC_OPT_TRAVERSAL, KC_OPT_STEP_LIMIT, KC_OPT_MEM_BUDGET = 1, 2, 3, 4, 5
+
+# every symbol include/kc.h declares
+EXPORTS = ("kc_graph_create", "kc_graph_destroy", "kc_graph_get_info", "kc_set_option",
+           "kc_sample_trees", "kc_estimate", "kc_evaluate_trees", "kc_status_string",
+           "kc_last_error")
+
+
+class KcError(RuntimeError):
+    def __init__(self, status: int, detail: str = ""):
+        self.status = status
+        self.name = STATUS.get(status, "KC_ERR_%d" % status)
+        super().__init__("%s: %s" % (self.name, detail) if detail else self.name)
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("two_m", ctypes.c_int64), ("root", ctypes.c_int32),
+                ("depth0", ctypes.c_int32), ("max_degree", ctypes.c_int32),
+                ("traversal", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_double), ("std_error", ctypes.c_double),
+                ("sum_f_lo", ctypes.c_uint64), ("sum_f_hi", ctypes.c_int64),
+                ("sum_f2_lo", ctypes.c_uint64), ("sum_f2_hi", ctypes.c_uint64),
+                ("count", ctypes.c_int64), ("total_steps", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """Load libkc_mi355x.so (raises KcError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise KcError(4, "HIP library %s is missing: run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    p, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
+    lib.kc_graph_create.restype = ctypes.c_int
+    lib.kc_graph_create.argtypes = [i64, p, ctypes.c_int, p, i32, p, ctypes.POINTER(p)]
+    lib.kc_graph_destroy.restype = ctypes.c_int
+    lib.kc_graph_destroy.argtypes = [p]
+    lib.kc_graph_get_info.restype = ctypes.c_int
+    lib.kc_graph_get_info.argtypes = [p, ctypes.POINTER(_Info)]
+    lib.kc_set_option.restype = ctypes.c_int
+    lib.kc_set_option.argtypes = [p, ctypes.c_int, i64]
+    lib.kc_sample_trees.restype = ctypes.c_int
+    lib.kc_sample_trees.argtypes = [p, u64, i64, i32, p, p, p, p]
+    lib.kc_estimate.restype = ctypes.c_int
+    lib.kc_estimate.argtypes = [p, u64, i64, i32, ctypes.POINTER(_Result), p, p, p]
+    lib.kc_evaluate_trees.restype = ctypes.c_int
+    lib.kc_evaluate_trees.argtypes = [p, p, i32, p, p]
+    lib.kc_status_string.restype = ctypes.c_char_p
+    lib.kc_status_string.argtypes = [ctypes.c_int]
+    lib.kc_last_error.restype = ctypes.c_char_p
+    lib.kc_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != KC_OK:
+        detail = library().kc_last_error().decode(errors="replace")
+        raise KcError(st, detail)
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Estimate:
+    """Theorem 3.3's estimate over `count` samples (exact integer sums)."""
+
+    kappa: float
+    std_error: float
+    sum_f: int
+    sum_f2: int
+    count: int
+    total_steps: int
+
+
+class Graph:
+    """A prepared graph resident on the current HIP device."""
+
+    def __init__(self, offsets, indices, root: int = -1, stream=None):
+        lib = library()
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        idx = np.ascontiguousarray(indices, dtype=np.int32)
+        n = int(off.shape[0] - 1)
+        h = ctypes.c_void_p()
+        st = lib.kc_graph_create(n, ctypes.c_void_p(off.ctypes.data), 1,
+                                 ctypes.c_void_p(idx.ctypes.data), int(root),
+                                 _stream(stream) if n >= 2 else None, ctypes.byref(h))
+        _check(st)
+        self._h = h
+        self.info = self._info()
+
+    @classmethod
+    def from_graph(cls, g, root: int = -1, stream=None) -> "Graph":
+        return cls(g.offsets, g.indices, root, stream)
+
+    def _info(self) -> dict:
+        inf = _Info()
+        _check(library().kc_graph_get_info(self._h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    @property
+    def n(self) -> int:
+        return self.info["n"]
+
+    @property
+    def two_m(self) -> int:
+        return self.info["two_m"]
+
+    @property
+    def root(self) -> int:
+        return self.info["root"]
+
+    def set_option(self, option: int, value: int):
+        _check(library().kc_set_option(self._h, option, int(value)))
+        self.info = self._info()
+
+    def sample_trees(self, seed: int, first: int, count: int, popcounts: bool = True,
+                     steps: bool = True, stream=None):
+        """(parents [count, n] int32, draws [count, n] int32 or None, steps [count] int64 or None)
+        as CUDA tensors."""
+        import torch
+        n = self.n
+        par = torch.empty((count, n), dtype=torch.int32, device="cuda")
+        cnt = torch.empty((count, n), dtype=torch.int32, device="cuda") if popcounts else None
+        stp = torch.empty((count,), dtype=torch.int64, device="cuda") if steps else None
+        _check(library().kc_sample_trees(self._h, seed, first, count, _dptr(par), _dptr(cnt),
+                                         _dptr(stp), _stream(stream)))
+        return par, cnt, stp
+
+    def estimate(self, seed: int, first: int, count: int, per_sample: bool = False, stream=None):
+        """Estimate (and, if per_sample, the f [count] and draws [count] CUDA tensors)."""
+        import torch
+        f = stp = None
+        if per_sample:
+            f = torch.empty((count,), dtype=torch.int64, device="cuda")
+            stp = torch.empty((count,), dtype=torch.int64, device="cuda")
+        res = _Result()
+        _check(library().kc_estimate(self._h, seed, first, count, ctypes.byref(res), _dptr(f),
+                                     _dptr(stp), _stream(stream)))
+        s1 = (res.sum_f_hi << 64) | res.sum_f_lo
+        s2 = (res.sum_f2_hi << 64) | res.sum_f2_lo
+        est = Estimate(res.kappa, res.std_error, s1, s2, res.count, res.total_steps)
+        return (est, f, stp) if per_sample else est
+
+    def evaluate_trees(self, parents, stream=None):
+        """f for given rooted parent arrays (CUDA int32 tensor [count, n])."""
+        import torch
+        parents = parents.contiguous()
+        count = int(parents.shape[0])
+        f = torch.empty((count,), dtype=torch.int64, device="cuda")
+        _check(library().kc_evaluate_trees(self._h, _dptr(parents), count, _dptr(f),
+                                           _stream(stream)))
+        return f
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().kc_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def kappa_interval(est: Estimate, z: float = 1.959963984540054):
+    """Normal-approximation confidence interval kappa +- z * std_error."""
+    return est.kappa - z * est.std_error, est.kappa + z * est.std_error

@@ -1,0 +1,711 @@
+// kc_device.hip -- gfx950 kernels of the Kemeny-constant estimator.
+//
+// One wavefront (64 lanes, one workgroup) owns one sample at a time and runs
+// its whole hot path in a persistent loop:
+//
+//   1. Uniform spanning tree by Wilson's algorithm (paper section 2.2 and
+//      Algorithm 1), organised as cooperative cycle popping: up to 64 lanes
+//      walk loop-erased random walks of the same sample at once.  The k-th
+//      draw at vertex v of sample s always uses the same Philox4x32-10 arrow,
+//      so the tree and the per-vertex draw counts are the unique cycle-popping
+//      outcome of those arrow stacks, whatever order the lanes pop in.
+//   2. Subtree volumes vol(v) of the sampled tree (Algorithm 1, the loop that
+//      fills vol[]) by bottom-up carriers with one 64-bit atomic per vertex,
+//      and a volume-weighted preorder numbering tin(v) of the tree (top-down,
+//      replaying the bottom-up completion groups in reverse).  A vertex u lies
+//      in Sub(tau, v) iff tin(v) <= tin(u) < tin(v) + vol(v).
+//   3. f(tau) of Theorem 3.3 via Theorem 3.4: every tree edge (v, p(v)) that
+//      is also a tau0 edge contributes +-(2m - vol(v)) to every u in the
+//      intersection of a tau subtree and a tau0 subtree.  Two evaluations:
+//        walk  -- per u, walk u's tau0 ancestors (depth0 steps);
+//        sweep -- visit tau0 in preorder, 64 positions per step, keeping the
+//                 active tau0 ancestors' contributions as range updates in a
+//                 Fenwick tree indexed by tin (O(log m) per update/query).
+//   4. Exact reduction: sum f and sum f^2 in 128-bit integers.
+//
+// Cross-lane communication through global memory uses workgroup-scope
+// relaxed atomics (L2-coherent on gfx950) ordered by workgroup fences; every
+// lane of a sample is in the same wavefront.
+
+#include "kc_internal.h"
+
+namespace kc {
+namespace {
+
+constexpr int WAVE = 64;
+
+// ------------------------------------------------------------ memory helpers
+
+template <typename T>
+__device__ __forceinline__ T aload(const T *p) {
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T>
+__device__ __forceinline__ void astore(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T>
+__device__ __forceinline__ T afetch_add(T *p, T v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T>
+__device__ __forceinline__ T afetch_and(T *p, T v) {
+    return __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T>
+__device__ __forceinline__ T afetch_xor(T *p, T v) {
+    return __hip_atomic_fetch_xor(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T>
+__device__ __forceinline__ T acas(T *p, T expected, T desired) {
+    __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+    return expected;  // value found at *p
+}
+__device__ __forceinline__ void fence_wg() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup"); }
+
+// ------------------------------------------------------------- wave helpers
+
+__device__ __forceinline__ int rank_in(uint64_t mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+__device__ __forceinline__ int64_t wave_sum(int64_t v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ void report_error(int32_t *ctl, int code, int idx) {
+    if (threadIdx.x == 0) {
+        int expected = 0;
+        if (__hip_atomic_compare_exchange_strong(&ctl[1], &expected, code, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            __hip_atomic_store(&ctl[2], idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ------------------------------------------------------------------ arrows
+
+// Philox4x32-10 block function (Salmon, Moraes, Dror, Shaw, SC'11): ten
+// rounds of two 32x32->64 multiplies with the Weyl key schedule.  Counter
+// (k, v, s_lo, s_hi), key (seed_lo, seed_hi).  The neighbour slot is the
+// high word of x * deg with x = out0 | out1 << 32, i.e. floor(x deg / 2^64),
+// computed from two 32x32 products.
+__device__ __forceinline__ uint32_t arrow_slot(uint64_t seed, uint64_t s, uint32_t v, uint32_t k,
+                                               uint32_t deg) {
+    uint32_t x0 = k, x1 = v, x2 = (uint32_t)s, x3 = (uint32_t)(s >> 32);
+    uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t a_lo = 0xD2511F53u * x0, a_hi = __umulhi(0xD2511F53u, x0);
+        const uint32_t b_lo = 0xCD9E8D57u * x2, b_hi = __umulhi(0xCD9E8D57u, x2);
+        const uint32_t y0 = b_hi ^ x1 ^ key0;
+        const uint32_t y2 = a_hi ^ x3 ^ key1;
+        x0 = y0; x1 = b_lo; x2 = y2; x3 = a_lo;
+        key0 += 0x9E3779B9u;
+        key1 += 0xBB67AE85u;
+    }
+    const uint64_t lowprod = (uint64_t)x0 * deg;
+    const uint64_t highprod = (uint64_t)x1 * deg + (lowprod >> 32);
+    return (uint32_t)(highprod >> 32);
+}
+
+// ------------------------------------------------------------ sampler state
+//
+// One 64-bit word per (sample, vertex):
+//   bits  0..31  next   : the vertex's current arrow target (tree parent once
+//                          the vertex is in the tree)
+//   bits 32..39  tag    : 0 = arrow not revealed ("free"), 1 = in the tree,
+//                          2 + L = on the current path of lane L
+//   bits 40..63  draws  : how many arrows the vertex has drawn so far
+constexpr uint32_t TAG_FREE = 0, TAG_TREE = 1, TAG_LANE0 = 2;
+constexpr uint64_t TAG_BITS = 0xFFull << 32;
+constexpr uint32_t DRAW_MAX = (1u << 24) - 1;
+
+__device__ __forceinline__ uint32_t tag_of(uint64_t w) { return (uint32_t)(w >> 32) & 0xFFu; }
+__device__ __forceinline__ uint32_t draws_of(uint64_t w) { return (uint32_t)(w >> 40); }
+__device__ __forceinline__ int32_t next_of(uint64_t w) { return (int32_t)(uint32_t)w; }
+__device__ __forceinline__ uint64_t make_word(int32_t nxt, uint32_t draws, uint32_t tag) {
+    return ((uint64_t)((draws << 8) | tag) << 32) | (uint64_t)(uint32_t)nxt;
+}
+
+// Lane modes of the cooperative sampler.
+enum : int {
+    M_IDLE = 0,    // no work; takes the next start vertex
+    M_PROBE = 1,   // looking at a start vertex (no path yet)
+    M_WAITV = 2,   // start vertex is on another lane's path; wait for it
+    M_WALK = 3,    // at head `cur` (claimed, arrow not revealed): draw and step
+    M_BLOCKED = 4, // head's arrow points at `tgt`, on lane `owner`'s path
+    M_ERASE0 = 5,  // popping a cycle: keep `tgt`, erase its path successors
+    M_ERASE = 6,   // popping: free `tgt`, follow next until `stopv`
+    M_RETRACE = 7  // path reached the tree: mark from `tgt` until `stopv`
+};
+
+// Cooperative cycle popping (Wilson's walks run by up to `walkers` lanes).
+//
+// Each lane runs loop-erased walks exactly as in Wilson's algorithm, with
+// loops popped explicitly (every vertex of a popped cycle becomes free again
+// and will draw its next arrow when revisited).  A lane whose step lands on
+// another lane's current path stops there (its arrow now points into that
+// path) until the vertex joins the tree (the whole path is then retraced
+// into the tree) or is popped (the lane continues from it).  A cycle of
+// such waits is a cycle of revealed arrows spanning several paths; it is
+// found with pointer doubling over the 64 lanes and popped as a whole.
+// Only genuine cycles of current arrows are ever popped, so the result is
+// the cycle-popping outcome: independent of timing and of `walkers`.
+//
+// Returns the total number of draws, or -1 (error recorded in ctl).
+__device__ int64_t sample_tree(const GraphDev &g, uint64_t *__restrict__ st, uint64_t seed,
+                               uint64_t s, int walkers, int64_t iter_cap, int32_t *ctl, int idx) {
+    __shared__ int sh_img[WAVE];
+    __shared__ int sh_ent[WAVE];
+    const int lane = threadIdx.x;
+    const int n = g.n, root = g.root;
+    for (int v = lane; v < n; v += WAVE) astore(&st[v], make_word(-1, 0, v == root ? TAG_TREE : TAG_FREE));
+    fence_wg();
+
+    const uint32_t mytag = TAG_LANE0 + (uint32_t)lane;
+    const bool worker = lane < walkers;
+    int mode = M_IDLE, start = -1, cur = -1, tgt = -1, stopv = -1, owner = -1;
+    uint32_t draws = 0;
+    int next_start = 0;
+    int64_t iters = 0, mysteps = 0;
+    int err = 0;
+
+    while (true) {
+        // hand out start vertices in BFS order to idle lanes
+        const uint64_t idle = __ballot(worker && mode == M_IDLE);
+        if (next_start < n) {
+            if (worker && mode == M_IDLE) {
+                const int pos = next_start + rank_in(idle);
+                if (pos < n) {
+                    start = g.order[pos];
+                    tgt = start;
+                    mode = M_PROBE;
+                }
+            }
+            next_start += __popcll(idle);
+        }
+        if (__ballot(mode != M_IDLE) == 0ull) break;  // all idle and no start left
+        if (++iters > iter_cap) { err = DEV_LIMIT; }
+
+        // ---- phase A: the step of each busy lane
+        bool stepped = false;
+        // every state index is range-checked: a protocol fault becomes an
+        // error code, never an out-of-bounds access
+        if (err == 0 && mode != M_IDLE) {
+            const int chk = (mode == M_WALK) ? cur : tgt;
+            if ((unsigned)chk >= (unsigned)n) err = DEV_PROTOCOL;
+        }
+        if (err == 0) {
+            if (mode == M_WALK) {
+                const int64_t o = g.off[cur];
+                const uint32_t d = (uint32_t)(g.off[cur + 1] - o);
+                const uint32_t j = arrow_slot(seed, s, (uint32_t)cur, draws, d);
+                const int32_t y = g.adj[o + j];
+                draws += 1;
+                if (draws > DRAW_MAX) err = DEV_LIMIT;
+                astore(&st[cur], make_word(y, draws, mytag));
+                tgt = y;
+                stepped = true;
+                mysteps++;
+            } else if (mode == M_ERASE) {
+                const uint64_t old = afetch_and(&st[tgt], ~TAG_BITS);
+                if (tag_of(old) != mytag) err = DEV_PROTOCOL;
+                const int32_t nz = next_of(old);
+                if (nz == stopv) mode = M_WALK; else tgt = nz;
+            } else if (mode == M_ERASE0) {
+                const uint64_t w = aload(&st[tgt]);
+                if (tag_of(w) != mytag) err = DEV_PROTOCOL;
+                cur = tgt;
+                draws = draws_of(w);
+                const int32_t nz = next_of(w);
+                if (nz == stopv) mode = M_WALK;
+                else { mode = M_ERASE; tgt = nz; }
+            } else if (mode == M_RETRACE) {
+                const uint64_t old = afetch_xor(&st[tgt], (uint64_t)(mytag ^ TAG_TREE) << 32);
+                if (tag_of(old) != mytag) err = DEV_PROTOCOL;
+                const int32_t nz = next_of(old);
+                if (nz == stopv) mode = M_IDLE; else tgt = nz;
+            }
+        }
+        fence_wg();
+
+        // ---- phase B/C: look at the target, claim free vertices
+        bool newblock = false;
+        if (err == 0 && (stepped || mode == M_BLOCKED || mode == M_WAITV || mode == M_PROBE) &&
+            (unsigned)tgt >= (unsigned)n)
+            err = DEV_PROTOCOL;
+        if (err == 0 && (stepped || mode == M_BLOCKED || mode == M_WAITV || mode == M_PROBE)) {
+            const bool haspath = stepped || mode == M_BLOCKED;
+            const uint64_t w = aload(&st[tgt]);
+            uint32_t tg = tag_of(w);
+            bool claimed = false;
+            if (tg == TAG_FREE) {
+                const uint64_t want = (w & ~TAG_BITS) | ((uint64_t)mytag << 32);
+                const uint64_t prev = acas(&st[tgt], w, want);
+                if (prev == w) claimed = true;
+                else tg = tag_of(prev);
+            }
+            if (claimed) {
+                if (!haspath) start = tgt;
+                cur = tgt;
+                draws = draws_of(w);
+                mode = M_WALK;
+            } else if (tg == TAG_TREE) {
+                if (haspath) { mode = M_RETRACE; stopv = tgt; tgt = start; }
+                else mode = M_IDLE;
+            } else if (tg == mytag) {
+                // own path: the new arrow closed a loop at tgt; pop it, keep tgt as head
+                if (!stepped) err = DEV_PROTOCOL;
+                cur = tgt;
+                draws = draws_of(w);
+                stopv = tgt;
+                tgt = next_of(w);
+                mode = M_ERASE;
+            } else if (tg >= TAG_LANE0) {
+                const int no = (int)tg - (int)TAG_LANE0;
+                if (haspath) {
+                    newblock = (mode != M_BLOCKED) || (owner != no);
+                    mode = M_BLOCKED;
+                } else {
+                    mode = M_WAITV;
+                }
+                owner = no;
+            } else {
+                err = DEV_PROTOCOL;  // a free vertex cannot lose a race to anything but a claim
+            }
+        }
+        fence_wg();
+
+        // ---- phase D: find cycles among waiting lanes and pop them
+        if (__ballot(newblock) != 0ull) {
+            const int wf = (mode == M_BLOCKED) ? (owner & (WAVE - 1)) : lane;
+            int J = wf;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) J = __shfl(J, J);  // J = wf^64(lane)
+            sh_img[lane] = 0;
+            __syncthreads();
+            sh_img[J] = 1;
+            __syncthreads();
+            const bool onc = (mode == M_BLOCKED) && sh_img[lane] != 0;
+            if (__ballot(onc) != 0ull) {
+                if (onc) sh_ent[owner & (WAVE - 1)] = tgt;  // my arrow enters `owner`'s path at tgt
+                __syncthreads();
+                if (onc) {
+                    stopv = tgt;
+                    tgt = sh_ent[lane];  // where my predecessor entered my path
+                    mode = M_ERASE0;
+                }
+            }
+            __syncthreads();
+        }
+        if (__ballot(err != 0) != 0ull) break;
+    }
+    const int e = wave_max(err);
+    if (e != 0) {
+        report_error(ctl, e, idx);
+        return -1;
+    }
+    return wave_sum(mysteps);
+}
+
+// --------------------------------------------------------- tree traversal
+
+struct SlotPtrs {
+    uint64_t *st, *word, *rec;  // rec: 2 words per vertex {vol<<32 | tin, parent}
+    int32_t *ordr, *grp, *leaves;
+    int64_t *fen;
+};
+
+constexpr uint64_t PEND_ONE = 1ull << 44;
+constexpr uint64_t VOL_MASK = PEND_ONE - 1;
+
+__device__ __forceinline__ uint32_t degree(const GraphDev &g, int v) {
+    return (uint32_t)(g.off[v + 1] - g.off[v]);
+}
+
+// Fenwick tree over positions 0..2m storing a difference array.
+__device__ __forceinline__ void fen_point_add(int64_t *fen, int64_t len, int64_t pos, int64_t val) {
+    if (pos < 0) pos = 0;
+    for (int64_t i = pos + 1; i < len; i += i & (-i)) afetch_add(&fen[i], val);
+}
+__device__ __forceinline__ void fen_range_add(int64_t *fen, int64_t len, int64_t lo, int64_t hi,
+                                              int64_t val) {
+    if (val == 0 || hi <= lo) return;
+    fen_point_add(fen, len, lo, val);
+    fen_point_add(fen, len, hi, -val);
+}
+__device__ __forceinline__ int64_t fen_prefix(const int64_t *fen, int64_t len, int64_t pos) {
+    int64_t i = pos + 1;
+    if (i >= len) i = len - 1;
+    int64_t sum = 0;
+    for (; i > 0; i -= i & (-i)) sum += aload(&fen[i]);
+    return sum;
+}
+
+// The two contributions attached to tau0 vertex x (Theorem 3.4), as
+// ranges of tin with a weight, active for every u in Sub(tau0, x):
+//   forward : p(x) = p0(x)          -> +(2m - vol(x)) on Sub(tau, x)
+//   reverse : p(p0(x)) = x, p0(x)!=r -> -(2m - vol(p0(x))) on Sub(tau, p0(x))
+struct Items {
+    uint32_t flo, fhi, rlo, rhi;
+    int64_t fw, rw;
+};
+__device__ __forceinline__ Items items_of(const GraphDev &g, const uint64_t *rec, int x) {
+    Items it{0u, 0u, 0u, 0u, 0, 0};
+    if (x == g.root) return it;
+    const uint64_t rx = aload(&rec[2 * (size_t)x]);
+    const int32_t px = (int32_t)aload(&rec[2 * (size_t)x + 1]);
+    const int z = g.p0[x];
+    if (px == z) {
+        const uint32_t t = (uint32_t)rx, vol = (uint32_t)(rx >> 32);
+        it.flo = t; it.fhi = t + vol; it.fw = g.two_m - (int64_t)vol;
+    }
+    if (z != g.root) {
+        const uint64_t rz = aload(&rec[2 * (size_t)z]);
+        const int32_t pz = (int32_t)aload(&rec[2 * (size_t)z + 1]);
+        if (pz == x) {
+            const uint32_t t = (uint32_t)rz, vol = (uint32_t)(rz >> 32);
+            it.rlo = t; it.rhi = t + vol; it.rw = (int64_t)vol - g.two_m;
+        }
+    }
+    return it;
+}
+__device__ __forceinline__ int64_t items_at(const Items &it, uint32_t t) {
+    int64_t s = 0;
+    if (it.flo <= t && t < it.fhi) s += it.fw;
+    if (it.rlo <= t && t < it.rhi) s += it.rw;
+    return s;
+}
+
+// Volumes and the volume-weighted preorder of the tree whose parents are in
+// rec[2v+1].  Returns false if the parents do not form a tree rooted at r.
+__device__ bool tree_numbering(const GraphDev &g, const SlotPtrs &sp) {
+    const int lane = threadIdx.x;
+    const int n = g.n, root = g.root;
+    // word[v] = deg(v) (volume so far) + PEND_ONE * (children not yet finished)
+    for (int v = lane; v < n; v += WAVE) astore(&sp.word[v], (uint64_t)degree(g, v));
+    fence_wg();
+    for (int v = lane; v < n; v += WAVE)
+        if (v != root) afetch_add(&sp.word[(int32_t)aload(&sp.rec[2 * (size_t)v + 1])], PEND_ONE);
+    fence_wg();
+    int nleaves = 0;
+    for (int base = 0; base < n; base += WAVE) {
+        const int v = base + lane;
+        const bool leaf = v < n && (aload(&sp.word[v]) >> 44) == 0;
+        const uint64_t m = __ballot(leaf);
+        if (leaf) astore(&sp.leaves[nleaves + rank_in(m)], v);
+        nleaves += __popcll(m);
+    }
+    fence_wg();
+    // bottom-up: a carrier finishes v (volume known) and pushes it into p(v);
+    // the last child to arrive finishes the parent in the next round.
+    int cv = -1;
+    uint64_t cval = 0;
+    int li = 0, nord = 0, ngrp = 0;
+    while (true) {
+        const uint64_t freem = __ballot(cv < 0);
+        if (li < nleaves) {
+            if (cv < 0) {
+                const int k = li + rank_in(freem);
+                if (k < nleaves) {
+                    cv = aload(&sp.leaves[k]);
+                    cval = degree(g, cv);
+                }
+            }
+            li = min(nleaves, li + (int)__popcll(freem));
+        }
+        const uint64_t busy = __ballot(cv >= 0);
+        if (busy == 0ull) break;
+        if (lane == 0) astore(&sp.grp[ngrp], nord);
+        ngrp++;
+        if (cv >= 0) {
+            astore(&sp.ordr[nord + rank_in(busy)], cv);
+            astore(&sp.rec[2 * (size_t)cv], cval << 32);
+        }
+        nord += __popcll(busy);
+        if (cv >= 0) {
+            if (cv == root) {
+                cv = -1;
+            } else {
+                const int p = (int32_t)aload(&sp.rec[2 * (size_t)cv + 1]);
+                const uint64_t old = afetch_add(&sp.word[p], cval - PEND_ONE);
+                if ((old >> 44) == 1) { cv = p; cval = (old & VOL_MASK) + cval; }
+                else cv = -1;
+            }
+        }
+        fence_wg();
+    }
+    if (lane == 0) astore(&sp.grp[ngrp], nord);
+    fence_wg();
+    // top-down: groups in reverse completion order; a parent is always in a
+    // later group than its children.  Siblings take consecutive volume
+    // ranges after the parent's own degree, in the order they reserve them.
+    for (int gi = ngrp - 1; gi >= 0; --gi) {
+        const int a = aload(&sp.grp[gi]), b = aload(&sp.grp[gi + 1]);
+        if (lane < b - a) {
+            const int v = aload(&sp.ordr[a + lane]);
+            const uint64_t rv = aload(&sp.rec[2 * (size_t)v]);
+            const uint64_t vol = rv >> 32;
+            if (v == root) {
+                astore(&sp.rec[2 * (size_t)v], vol << 32);
+            } else {
+                const int p = (int32_t)aload(&sp.rec[2 * (size_t)v + 1]);
+                const uint64_t rp = aload(&sp.rec[2 * (size_t)p]);
+                const uint64_t volp = rp >> 32, tinp = rp & 0xFFFFFFFFull;
+                const uint64_t old = afetch_add(&sp.word[p], vol);
+                const uint64_t tin = tinp + degree(g, p) + (old - volp);
+                astore(&sp.rec[2 * (size_t)v], (vol << 32) | tin);
+            }
+        }
+        fence_wg();
+    }
+    return nord == n;
+}
+
+// f by walking each vertex's tau0 ancestors.
+__device__ int64_t f_walk(const GraphDev &g, const SlotPtrs &sp) {
+    const int lane = threadIdx.x;
+    const int n = g.n, root = g.root;
+    const int64_t two_m = g.two_m;
+    int64_t acc = 0;
+    for (int u = lane; u < n; u += WAVE) {
+        const uint64_t ru = aload(&sp.rec[2 * (size_t)u]);
+        const uint32_t tu = (uint32_t)ru;
+        int64_t q = 0;
+        int x = u;
+        uint64_t rx = ru;
+        int32_t px = (int32_t)aload(&sp.rec[2 * (size_t)u + 1]);
+        while (x != root) {
+            const int z = g.p0[x];
+            if (px == z) {
+                const uint32_t t = (uint32_t)rx, vol = (uint32_t)(rx >> 32);
+                if (t <= tu && tu < t + vol) q += two_m - (int64_t)vol;
+            }
+            if (z == root) break;
+            const uint64_t rz = aload(&sp.rec[2 * (size_t)z]);
+            const int32_t pz = (int32_t)aload(&sp.rec[2 * (size_t)z + 1]);
+            if (pz == x) {
+                const uint32_t t = (uint32_t)rz, vol = (uint32_t)(rz >> 32);
+                if (t <= tu && tu < t + vol) q -= two_m - (int64_t)vol;
+            }
+            x = z;
+            rx = rz;
+            px = pz;
+        }
+        acc += (int64_t)degree(g, u) * q;
+    }
+    return wave_sum(acc);
+}
+
+// f by a tau0-preorder sweep, 64 preorder positions per step.  The Fenwick
+// tree holds the items of every tau0 vertex whose subtree started before the
+// step and is still open; items of the step's own vertices and of subtrees
+// closing inside the step are handled exactly from LDS.  The tree returns
+// to all zeros at the end of the sweep.
+__device__ int64_t f_sweep(const GraphDev &g, const SlotPtrs &sp, int64_t fen_len) {
+    __shared__ Items sh_it[WAVE];
+    __shared__ int32_t sh_out[WAVE];
+    __shared__ Items se_it[WAVE];
+    __shared__ int32_t se_out[WAVE];
+    const int lane = threadIdx.x;
+    const int n = g.n;
+    int64_t acc = 0;
+    int blk = 0;
+    for (int P0 = 0; P0 < n; P0 += WAVE, ++blk) {
+        const int p = P0 + lane;
+        const bool valid = p < n;
+        Items it{0u, 0u, 0u, 0u, 0, 0};
+        int32_t o = -1;
+        uint32_t tu = 0;
+        int u = g.root;
+        if (valid) {
+            u = g.pre0[p];
+            it = items_of(g, sp.rec, u);
+            o = g.out0[u];
+            tu = (uint32_t)aload(&sp.rec[2 * (size_t)u]);
+        }
+        int64_t S = valid ? fen_prefix(sp.fen, fen_len, tu) : 0;
+        sh_it[lane] = it;
+        sh_out[lane] = o;
+        __syncthreads();
+        if (valid) {
+            for (int j = 0; j <= lane; ++j)
+                if (sh_out[j] >= p) S += items_at(sh_it[j], tu);
+        }
+        const int e0 = g.eoff[blk], e1 = g.eoff[blk + 1];
+        for (int c = e0; c < e1; c += WAVE) {
+            const int k = c + lane;
+            Items ex{0u, 0u, 0u, 0u, 0, 0};
+            int32_t xo = -1;
+            if (k < e1) {
+                const int x = g.elist[k];
+                ex = items_of(g, sp.rec, x);
+                xo = g.out0[x];
+            }
+            se_it[lane] = ex;
+            se_out[lane] = xo;
+            __syncthreads();
+            if (valid) {
+                const int cnt = min(WAVE, e1 - c);
+                for (int j = 0; j < cnt; ++j)
+                    if (se_out[j] < p) S -= items_at(se_it[j], tu);
+            }
+            if (k < e1) {
+                fen_range_add(sp.fen, fen_len, ex.flo, ex.fhi, -ex.fw);
+                fen_range_add(sp.fen, fen_len, ex.rlo, ex.rhi, -ex.rw);
+            }
+            __syncthreads();
+        }
+        if (valid) {
+            acc += (int64_t)degree(g, u) * S;
+            if (o >= P0 + WAVE) {
+                fen_range_add(sp.fen, fen_len, it.flo, it.fhi, it.fw);
+                fen_range_add(sp.fen, fen_len, it.rlo, it.rhi, it.rw);
+            }
+        }
+        fence_wg();
+        __syncthreads();
+    }
+    return wave_sum(acc);
+}
+
+// ------------------------------------------------------------ the kernels
+
+__global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd, RunParams rp) {
+    const int lane = threadIdx.x;
+    const size_t n = (size_t)g.n;
+    SlotPtrs sp;
+    sp.st = sd.st + (size_t)blockIdx.x * n;
+    sp.word = sd.word ? sd.word + (size_t)blockIdx.x * n : nullptr;
+    sp.rec = sd.rec ? reinterpret_cast<uint64_t *>(sd.rec) + 2 * (size_t)blockIdx.x * n : nullptr;
+    sp.ordr = sd.ordr ? sd.ordr + (size_t)blockIdx.x * n : nullptr;
+    sp.grp = sd.grp ? sd.grp + (size_t)blockIdx.x * (n + 1) : nullptr;
+    sp.leaves = sd.leaves ? sd.leaves + (size_t)blockIdx.x * n : nullptr;
+    sp.fen = sd.fen ? sd.fen + (size_t)blockIdx.x * (size_t)sd.fen_len : nullptr;
+
+    while (true) {
+        int idx = 0;
+        if (lane == 0) idx = __hip_atomic_fetch_add(&rp.ctl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        idx = __shfl(idx, 0);
+        if (idx >= rp.count) break;
+        if (__hip_atomic_load(&rp.ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+        const uint64_t s = (uint64_t)(rp.first + idx);
+        int64_t steps = 0;
+        if (rp.mode != RUN_EVALUATE) {
+            steps = sample_tree(g, sp.st, rp.seed, s, rp.walkers, rp.iter_cap, rp.ctl, idx);
+            if (steps < 0) break;
+        }
+        if (rp.mode == RUN_SAMPLE) {
+            int32_t *po = rp.parents_out + (size_t)idx * n;
+            uint32_t *co = rp.cnt_out ? rp.cnt_out + (size_t)idx * n : nullptr;
+            for (int v = lane; v < g.n; v += WAVE) {
+                const uint64_t w = aload(&sp.st[v]);
+                po[v] = (v == g.root) ? -1 : next_of(w);
+                if (co) co[v] = draws_of(w);
+            }
+        } else {
+            // parents into rec[2v+1]
+            bool bad = false;
+            for (int v = lane; v < g.n; v += WAVE) {
+                int32_t p;
+                if (v == g.root) {
+                    p = -1;
+                } else {
+                    p = (rp.mode == RUN_EVALUATE) ? rp.parents_in[(size_t)idx * n + v]
+                                                  : next_of(aload(&sp.st[v]));
+                    if (p < 0 || p >= g.n || p == v) { bad = true; p = g.root; }
+                }
+                astore(&sp.rec[2 * (size_t)v + 1], (uint64_t)(uint32_t)p);
+            }
+            fence_wg();
+            bool ok = tree_numbering(g, sp);
+            if (__ballot(bad) != 0ull) ok = false;
+            int64_t f = 0;
+            if (rp.traversal == 2) f = f_sweep(g, sp, sd.fen_len);
+            else f = f_walk(g, sp);
+            if (!ok) report_error(rp.ctl, DEV_BADTREE, idx);
+            if (lane == 0) rp.f_out[idx] = f;
+        }
+        if (rp.steps_out && lane == 0) rp.steps_out[idx] = steps;
+    }
+}
+
+__global__ void reset_ctl_kernel(int32_t *ctl) {
+    if (threadIdx.x < 4) ctl[threadIdx.x] = 0;
+}
+
+__global__ void zero_i64_kernel(int64_t *p, int64_t len) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// Exact sums of f and f^2 (128-bit) and of the draw counts; one block.
+__global__ void __launch_bounds__(256) reduce_kernel(const int64_t *f, const int64_t *steps,
+                                                     int32_t count, ReduceOut *out) {
+    __shared__ unsigned __int128 sh_s[256];
+    __shared__ unsigned __int128 sh_q[256];
+    __shared__ int64_t sh_t[256];
+    unsigned __int128 s = 0, q = 0;
+    int64_t t = 0;
+    for (int i = threadIdx.x; i < count; i += 256) {
+        const __int128 x = f[i];
+        s += (unsigned __int128)x;
+        q += (unsigned __int128)(x * x);
+        if (steps) t += steps[i];
+    }
+    sh_s[threadIdx.x] = s;
+    sh_q[threadIdx.x] = q;
+    sh_t[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh_s[threadIdx.x] += sh_s[threadIdx.x + w];
+            sh_q[threadIdx.x] += sh_q[threadIdx.x + w];
+            sh_t[threadIdx.x] += sh_t[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out->sum_lo = (uint64_t)sh_s[0];
+        out->sum_hi = (int64_t)(uint64_t)(sh_s[0] >> 64);
+        out->sq_lo = (uint64_t)sh_q[0];
+        out->sq_hi = (uint64_t)(sh_q[0] >> 64);
+        out->steps = sh_t[0];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_reset_ctl(int32_t *ctl, hipStream_t stream) {
+    hipLaunchKernelGGL(reset_ctl_kernel, dim3(1), dim3(64), 0, stream, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_persistent(const GraphDev &g, const SlotDev &s, const RunParams &rp, int slots,
+                             hipStream_t stream) {
+    hipLaunchKernelGGL(persistent_kernel, dim3(slots), dim3(WAVE), 0, stream, g, s, rp);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const int64_t *f, const int64_t *steps, int32_t count, ReduceOut *out,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, stream, f, steps, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_i64(int64_t *p, int64_t len, hipStream_t stream) {
+    if (len <= 0) return hipSuccess;
+    int64_t blocks = (len + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(zero_i64_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, len);
+    return hipGetLastError();
+}
+
+}  // namespace kc

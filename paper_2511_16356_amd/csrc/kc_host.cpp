@@ -1,0 +1,536 @@
+// kc_host.cpp -- C ABI (include/kc.h): validation, graph preparation,
+// device workspace and launches.  Graph preparation (root, BFS tree tau0,
+// tau0 preorder) runs once per graph on the host; everything per sample runs
+// in the kernels of kc_device.hip.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/kc.h"
+#include "kc_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+kc_status fail(kc_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(e_ == hipErrorOutOfMemory ? KC_ERR_NOMEM : KC_ERR_DEVICE, "%s: %s", #expr, \
+                        hipGetErrorString(e_));                                                \
+    } while (0)
+
+void dev_free(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+template <typename T>
+hipError_t dev_alloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+}
+
+}  // namespace
+
+struct kc_graph {
+    int64_t n = 0, two_m = 0;
+    int32_t root = -1, depth0 = 0, max_degree = 0;
+    int32_t traversal = KC_TRAV_WALK;
+    int32_t walkers = 64;
+    int32_t slots_opt = 0;
+    int32_t trav_opt = KC_TRAV_AUTO;
+    int64_t step_limit = 0;
+    int64_t mem_budget = 0;
+    int64_t graph_bytes = 0;
+    int32_t nblk = 0;
+    // graph arrays on the device
+    int64_t *d_off = nullptr;
+    int32_t *d_adj = nullptr, *d_p0 = nullptr, *d_order = nullptr, *d_pre0 = nullptr;
+    int32_t *d_out0 = nullptr, *d_eoff = nullptr, *d_elist = nullptr;
+    // workspace
+    int ws_slots = 0;
+    bool ws_trav = false, ws_fen = false;
+    uint64_t *d_st = nullptr, *d_word = nullptr;
+    int4 *d_rec = nullptr;
+    int32_t *d_ordr = nullptr, *d_grp = nullptr, *d_leaves = nullptr;
+    int64_t *d_fen = nullptr;
+    int64_t *d_f = nullptr, *d_steps = nullptr;  // internal per-sample buffers
+    int64_t fbuf_len = 0;
+    int32_t *d_ctl = nullptr;
+    kc::ReduceOut *d_red = nullptr;
+};
+
+namespace {
+
+void free_workspace(kc_graph *g) {
+    dev_free(g->d_st); dev_free(g->d_word); dev_free(g->d_rec); dev_free(g->d_ordr);
+    dev_free(g->d_grp); dev_free(g->d_leaves); dev_free(g->d_fen);
+    g->d_st = g->d_word = nullptr; g->d_rec = nullptr;
+    g->d_ordr = g->d_grp = g->d_leaves = nullptr; g->d_fen = nullptr;
+    g->ws_slots = 0; g->ws_trav = g->ws_fen = false;
+}
+
+void free_all(kc_graph *g) {
+    free_workspace(g);
+    dev_free(g->d_off); dev_free(g->d_adj); dev_free(g->d_p0); dev_free(g->d_order);
+    dev_free(g->d_pre0); dev_free(g->d_out0); dev_free(g->d_eoff); dev_free(g->d_elist);
+    dev_free(g->d_f); dev_free(g->d_steps); dev_free(g->d_ctl); dev_free(g->d_red);
+}
+
+int64_t slot_bytes(const kc_graph *g, bool trav, bool fen) {
+    int64_t b = 8 * g->n;  // sampler state
+    if (trav) b += 8 * g->n + 16 * g->n + 4 * g->n + 4 * (g->n + 1) + 4 * g->n;
+    if (fen) b += 8 * (g->two_m + 2);
+    return b;
+}
+
+// Make sure at least `want` slots of workspace exist; returns the usable count.
+kc_status ensure_workspace(kc_graph *g, int want, bool trav, bool fen, hipStream_t stream, int *got) {
+    if (want < 1) want = 1;
+    if (g->ws_slots >= want && (!trav || g->ws_trav) && (!fen || g->ws_fen)) {
+        *got = want;
+        return KC_OK;
+    }
+    trav = trav || g->ws_trav;
+    fen = fen || g->ws_fen;
+    want = std::max(want, g->ws_slots);
+    free_workspace(g);
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    int64_t budget = g->mem_budget > 0 ? g->mem_budget : (int64_t)(0.6 * (double)free_b);
+    const int64_t per = slot_bytes(g, trav, fen);
+    int64_t fit = budget / per;
+    if (fit < 1) return fail(KC_ERR_NOMEM, "one sample needs %lld bytes of workspace, budget %lld",
+                             (long long)per, (long long)budget);
+    int slots = (int)std::min<int64_t>(want, fit);
+    const size_t n = (size_t)g->n;
+    HIP_TRY(dev_alloc(&g->d_st, (size_t)slots * n));
+    if (trav) {
+        HIP_TRY(dev_alloc(&g->d_word, (size_t)slots * n));
+        HIP_TRY(dev_alloc(&g->d_rec, (size_t)slots * n));
+        HIP_TRY(dev_alloc(&g->d_ordr, (size_t)slots * n));
+        HIP_TRY(dev_alloc(&g->d_grp, (size_t)slots * (n + 1)));
+        HIP_TRY(dev_alloc(&g->d_leaves, (size_t)slots * n));
+    }
+    if (fen) {
+        const int64_t len = (int64_t)slots * (g->two_m + 2);
+        HIP_TRY(dev_alloc(&g->d_fen, (size_t)len));
+        HIP_TRY(kc::launch_zero_i64(g->d_fen, len, stream));
+    }
+    g->ws_slots = slots;
+    g->ws_trav = trav;
+    g->ws_fen = fen;
+    *got = slots;
+    return KC_OK;
+}
+
+kc_status ensure_fbuf(kc_graph *g, int64_t count) {
+    if (g->fbuf_len >= count) return KC_OK;
+    dev_free(g->d_f);
+    dev_free(g->d_steps);
+    g->d_f = g->d_steps = nullptr;
+    g->fbuf_len = 0;
+    HIP_TRY(dev_alloc(&g->d_f, (size_t)count));
+    HIP_TRY(dev_alloc(&g->d_steps, (size_t)count));
+    g->fbuf_len = count;
+    return KC_OK;
+}
+
+int default_slots(const kc_graph *g) {
+    (void)g;
+    return 4096;  // 256 CUs x 16 single-wave workgroups
+}
+
+// Launch the persistent kernel over `count` samples and check its status.
+kc_status run_persistent(kc_graph *g, kc::RunParams rp, hipStream_t stream) {
+    const bool trav = rp.mode != kc::RUN_SAMPLE;
+    const bool fen = trav && g->traversal == KC_TRAV_SWEEP;
+    int want = g->slots_opt > 0 ? g->slots_opt : default_slots(g);
+    want = std::min(want, rp.count);
+    int slots = 0;
+    kc_status st = ensure_workspace(g, want, trav, fen, stream, &slots);
+    if (st != KC_OK) return st;
+    kc::GraphDev gd;
+    gd.n = (int32_t)g->n;
+    gd.root = g->root;
+    gd.two_m = g->two_m;
+    gd.off = g->d_off;
+    gd.adj = g->d_adj;
+    gd.p0 = g->d_p0;
+    gd.order = g->d_order;
+    gd.pre0 = g->d_pre0;
+    gd.out0 = g->d_out0;
+    gd.eoff = g->d_eoff;
+    gd.elist = g->d_elist;
+    kc::SlotDev sd;
+    sd.st = g->d_st;
+    sd.word = g->d_word;
+    sd.rec = g->d_rec;
+    sd.ordr = g->d_ordr;
+    sd.grp = g->d_grp;
+    sd.leaves = g->d_leaves;
+    sd.fen = fen ? g->d_fen : nullptr;
+    sd.fen_len = fen ? g->two_m + 2 : 0;
+    rp.walkers = g->walkers;
+    rp.traversal = g->traversal;
+    rp.iter_cap = g->step_limit > 0 ? g->step_limit : 1024 * g->n + (1 << 22);
+    rp.ctl = g->d_ctl;
+    HIP_TRY(kc::launch_reset_ctl(g->d_ctl, stream));
+    HIP_TRY(kc::launch_persistent(gd, sd, rp, slots, stream));
+    int32_t ctl[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(ctl, g->d_ctl, sizeof(ctl), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (ctl[1] != 0) {
+        if (ctl[1] == kc::DEV_LIMIT)
+            return fail(KC_ERR_LIMIT, "sample %lld exceeded the step limit",
+                        (long long)(rp.first + ctl[2]));
+        if (ctl[1] == kc::DEV_BADTREE)
+            return fail(KC_ERR_INVALID, "parents of tree %d do not form a spanning tree rooted at %d",
+                        ctl[2], g->root);
+        return fail(KC_ERR_DEVICE, "sampler protocol violation (code %d) in sample %lld", ctl[1],
+                    (long long)(rp.first + ctl[2]));
+    }
+    return KC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *kc_status_string(kc_status s) {
+    switch (s) {
+        case KC_OK: return "ok";
+        case KC_ERR_INVALID: return "invalid argument or graph";
+        case KC_ERR_DISCONNECTED: return "graph is not connected";
+        case KC_ERR_NOMEM: return "out of memory";
+        case KC_ERR_DEVICE: return "device error";
+        case KC_ERR_OVERFLOW: return "graph too large for exact 64-bit tree values";
+        case KC_ERR_LIMIT: return "step limit exceeded";
+        case KC_ERR_UNSUPPORTED: return "unsupported size";
+    }
+    return "unknown status";
+}
+
+const char *kc_last_error(void) { return g_last_error.c_str(); }
+
+kc_status kc_graph_create(int64_t n, const void *offsets, int offsets_are_i64, const int32_t *indices,
+                          int32_t root, void *hip_stream, kc_graph **out) {
+    g_last_error.clear();
+    if (!out) return fail(KC_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n < 2) return fail(KC_ERR_INVALID, "need at least 2 vertices (n=%lld)", (long long)n);
+    if (n > (1ll << 31) - 1024) return fail(KC_ERR_UNSUPPORTED, "n=%lld exceeds 32-bit vertex ids", (long long)n);
+    if (!offsets || !indices) return fail(KC_ERR_INVALID, "offsets/indices is NULL");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    std::vector<int64_t> off((size_t)n + 1);
+    if (offsets_are_i64) {
+        std::memcpy(off.data(), offsets, sizeof(int64_t) * ((size_t)n + 1));
+    } else {
+        const int32_t *o32 = static_cast<const int32_t *>(offsets);
+        for (int64_t i = 0; i <= n; ++i) off[(size_t)i] = o32[i];
+    }
+    if (off[0] != 0) return fail(KC_ERR_INVALID, "offsets[0] must be 0");
+    for (int64_t i = 0; i < n; ++i)
+        if (off[(size_t)i + 1] < off[(size_t)i]) return fail(KC_ERR_INVALID, "offsets decrease at row %lld", (long long)i);
+    const int64_t nnz = off[(size_t)n];
+    if (nnz >= (1ll << 31)) return fail(KC_ERR_OVERFLOW, "2m=%lld does not fit 31-bit volumes", (long long)nnz);
+    int32_t maxdeg = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t a = off[(size_t)v], b = off[(size_t)v + 1];
+        maxdeg = (int32_t)std::max<int64_t>(maxdeg, b - a);
+        for (int64_t e = a; e < b; ++e) {
+            const int32_t u = indices[e];
+            if (u < 0 || u >= n) return fail(KC_ERR_INVALID, "neighbour %d of %lld out of range", u, (long long)v);
+            if (u == v) return fail(KC_ERR_INVALID, "self-loop at %lld", (long long)v);
+            if (e > a && indices[e - 1] >= u)
+                return fail(KC_ERR_INVALID, "row %lld not strictly ascending (duplicate or unsorted)", (long long)v);
+        }
+    }
+    if (maxdeg >= (1 << 20)) return fail(KC_ERR_UNSUPPORTED, "max degree %d >= 2^20", maxdeg);
+    for (int64_t v = 0; v < n; ++v) {
+        for (int64_t e = off[(size_t)v]; e < off[(size_t)v + 1]; ++e) {
+            const int32_t u = indices[e];
+            if (!std::binary_search(indices + off[(size_t)u], indices + off[(size_t)u + 1], (int32_t)v))
+                return fail(KC_ERR_INVALID, "edge (%lld,%d) has no reverse entry", (long long)v, u);
+        }
+    }
+    // root: highest degree, smallest index on ties
+    if (root < 0) {
+        int64_t best = -1;
+        for (int64_t v = 0; v < n; ++v) {
+            const int64_t d = off[(size_t)v + 1] - off[(size_t)v];
+            if (d > best) { best = d; root = (int32_t)v; }
+        }
+    }
+    if (root < 0 || root >= n) return fail(KC_ERR_INVALID, "root %d out of range", root);
+    // BFS from the root; the queue order is the walk start order
+    std::vector<int32_t> dist((size_t)n, -1), order;
+    order.reserve((size_t)n);
+    dist[(size_t)root] = 0;
+    order.push_back(root);
+    for (size_t h = 0; h < order.size(); ++h) {
+        const int32_t x = order[h];
+        for (int64_t e = off[(size_t)x]; e < off[(size_t)x + 1]; ++e) {
+            const int32_t y = indices[e];
+            if (dist[(size_t)y] < 0) {
+                dist[(size_t)y] = dist[(size_t)x] + 1;
+                order.push_back(y);
+            }
+        }
+    }
+    if ((int64_t)order.size() != n)
+        return fail(KC_ERR_DISCONNECTED, "only %zu of %lld vertices reachable from the root", order.size(), (long long)n);
+    // tau0: parent = smallest-index neighbour one level up
+    std::vector<int32_t> p0((size_t)n, -1);
+    int32_t depth0 = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        depth0 = std::max(depth0, dist[(size_t)v]);
+        if (v == root) continue;
+        for (int64_t e = off[(size_t)v]; e < off[(size_t)v + 1]; ++e) {
+            const int32_t u = indices[e];
+            if (dist[(size_t)u] == dist[(size_t)v] - 1) { p0[(size_t)v] = u; break; }  // rows ascending
+        }
+    }
+    const unsigned __int128 bound = (unsigned __int128)nnz * (unsigned __int128)nnz * (unsigned __int128)depth0;
+    if (bound >= ((unsigned __int128)1 << 63))
+        return fail(KC_ERR_OVERFLOW, "4 m^2 depth0 = (2m)^2 * %d exceeds 2^63", depth0);
+    // tau0 preorder, children in ascending order
+    std::vector<int64_t> cst((size_t)n + 1, 0);
+    for (int64_t v = 0; v < n; ++v) if (v != root) cst[(size_t)p0[(size_t)v] + 1]++;
+    for (int64_t v = 0; v < n; ++v) cst[(size_t)v + 1] += cst[(size_t)v];
+    std::vector<int32_t> clist((size_t)n);
+    {
+        std::vector<int64_t> fill(cst.begin(), cst.end() - 1);
+        for (int64_t v = 0; v < n; ++v) if (v != root) clist[(size_t)fill[(size_t)p0[(size_t)v]]++] = (int32_t)v;
+    }
+    std::vector<int32_t> pre0((size_t)n), in0((size_t)n), out0((size_t)n);
+    {
+        std::vector<int32_t> stack;
+        std::vector<int64_t> next((size_t)n);
+        int32_t t = 0;
+        stack.push_back(root);
+        next[(size_t)root] = cst[(size_t)root];
+        pre0[(size_t)t] = root;
+        in0[(size_t)root] = t++;
+        while (!stack.empty()) {
+            const int32_t x = stack.back();
+            if (next[(size_t)x] < cst[(size_t)x + 1]) {
+                const int32_t c = clist[(size_t)next[(size_t)x]++];
+                next[(size_t)c] = cst[(size_t)c];
+                pre0[(size_t)t] = c;
+                in0[(size_t)c] = t++;
+                stack.push_back(c);
+            } else {
+                out0[(size_t)x] = t - 1;
+                stack.pop_back();
+            }
+        }
+    }
+    // per 64-position block: tau0 vertices whose subtree opened before the block and closes in it
+    const int32_t nblk = (int32_t)((n + 63) / 64);
+    std::vector<int32_t> eoff((size_t)nblk + 1, 0), elist;
+    for (int64_t x = 0; x < n; ++x) {
+        const int32_t be = out0[(size_t)x] / 64;
+        if (in0[(size_t)x] < be * 64) eoff[(size_t)be + 1]++;
+    }
+    for (int32_t b = 0; b < nblk; ++b) eoff[(size_t)b + 1] += eoff[(size_t)b];
+    elist.resize((size_t)eoff[(size_t)nblk]);
+    {
+        std::vector<int32_t> fill(eoff.begin(), eoff.end() - 1);
+        for (int64_t x = 0; x < n; ++x) {
+            const int32_t be = out0[(size_t)x] / 64;
+            if (in0[(size_t)x] < be * 64) elist[(size_t)fill[(size_t)be]++] = (int32_t)x;
+        }
+    }
+
+    kc_graph *g = new (std::nothrow) kc_graph();
+    if (!g) return fail(KC_ERR_NOMEM, "host allocation failed");
+    g->n = n;
+    g->two_m = nnz;
+    g->root = root;
+    g->depth0 = depth0;
+    g->max_degree = maxdeg;
+    g->nblk = nblk;
+    g->traversal = depth0 <= 12 ? KC_TRAV_WALK : KC_TRAV_SWEEP;
+    auto up = [&](auto **dst, const auto *src, size_t cnt) -> hipError_t {
+        hipError_t e = dev_alloc(dst, cnt);
+        if (e != hipSuccess) return e;
+        g->graph_bytes += (int64_t)(cnt * sizeof(**dst));
+        if (cnt == 0) return hipSuccess;
+        return hipMemcpyAsync(*dst, src, cnt * sizeof(**dst), hipMemcpyHostToDevice, stream);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up(&g->d_off, off.data(), off.size());
+    if (e == hipSuccess) e = up(&g->d_adj, indices, (size_t)nnz);
+    if (e == hipSuccess) e = up(&g->d_p0, p0.data(), p0.size());
+    if (e == hipSuccess) e = up(&g->d_order, order.data(), order.size());
+    if (e == hipSuccess) e = up(&g->d_pre0, pre0.data(), pre0.size());
+    if (e == hipSuccess) e = up(&g->d_out0, out0.data(), out0.size());
+    if (e == hipSuccess) e = up(&g->d_eoff, eoff.data(), eoff.size());
+    if (e == hipSuccess) e = up(&g->d_elist, elist.data(), elist.size());
+    if (e == hipSuccess) e = dev_alloc(&g->d_ctl, 4);
+    if (e == hipSuccess) e = dev_alloc(&g->d_red, 1);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        free_all(g);
+        delete g;
+        return fail(e == hipErrorOutOfMemory ? KC_ERR_NOMEM : KC_ERR_DEVICE, "upload failed: %s",
+                    hipGetErrorString(e));
+    }
+    *out = g;
+    return KC_OK;
+}
+
+kc_status kc_graph_destroy(kc_graph *g) {
+    if (!g) return KC_OK;
+    free_all(g);
+    delete g;
+    return KC_OK;
+}
+
+kc_status kc_graph_get_info(const kc_graph *g, kc_graph_info *info) {
+    if (!g || !info) return fail(KC_ERR_INVALID, "NULL argument");
+    info->n = g->n;
+    info->two_m = g->two_m;
+    info->root = g->root;
+    info->depth0 = g->depth0;
+    info->max_degree = g->max_degree;
+    info->traversal = g->traversal;
+    info->device_bytes = g->graph_bytes;
+    return KC_OK;
+}
+
+kc_status kc_set_option(kc_graph *g, int option, int64_t value) {
+    if (!g) return fail(KC_ERR_INVALID, "NULL graph");
+    switch (option) {
+        case KC_OPT_WALKERS:
+            if (value < 1 || value > 64) return fail(KC_ERR_INVALID, "walkers must be 1..64");
+            g->walkers = (int32_t)value;
+            return KC_OK;
+        case KC_OPT_SLOTS:
+            if (value < 0 || value > (1 << 20)) return fail(KC_ERR_INVALID, "slots must be 0..2^20");
+            g->slots_opt = (int32_t)value;
+            return KC_OK;
+        case KC_OPT_TRAVERSAL:
+            if (value == KC_TRAV_AUTO) g->traversal = g->depth0 <= 12 ? KC_TRAV_WALK : KC_TRAV_SWEEP;
+            else if (value == KC_TRAV_WALK || value == KC_TRAV_SWEEP) g->traversal = (int32_t)value;
+            else return fail(KC_ERR_INVALID, "unknown traversal %lld", (long long)value);
+            g->trav_opt = (int32_t)value;
+            return KC_OK;
+        case KC_OPT_STEP_LIMIT:
+            if (value < 0) return fail(KC_ERR_INVALID, "step limit must be >= 0");
+            g->step_limit = value;
+            return KC_OK;
+        case KC_OPT_MEM_BUDGET:
+            if (value < 0) return fail(KC_ERR_INVALID, "memory budget must be >= 0");
+            g->mem_budget = value;
+            return KC_OK;
+    }
+    return fail(KC_ERR_INVALID, "unknown option %d", option);
+}
+
+kc_status kc_sample_trees(kc_graph *g, uint64_t seed, int64_t first_sample, int32_t count,
+                          int32_t *parents_out, uint32_t *popcounts_out, int64_t *steps_out,
+                          void *hip_stream) {
+    g_last_error.clear();
+    if (!g) return fail(KC_ERR_INVALID, "NULL graph");
+    if (count < 0 || first_sample < 0) return fail(KC_ERR_INVALID, "negative count or first sample");
+    if (count == 0) return KC_OK;
+    if (!parents_out) return fail(KC_ERR_INVALID, "parents_out is NULL");
+    kc::RunParams rp{};
+    rp.seed = seed;
+    rp.first = first_sample;
+    rp.count = count;
+    rp.mode = kc::RUN_SAMPLE;
+    rp.parents_out = parents_out;
+    rp.cnt_out = popcounts_out;
+    rp.steps_out = steps_out;
+    return run_persistent(g, rp, (hipStream_t)hip_stream);
+}
+
+static kc_status finish_reduce(kc_graph *g, int32_t count, const int64_t *f, const int64_t *steps,
+                               kc_result *res, hipStream_t stream) {
+    HIP_TRY(kc::launch_reduce(f, steps, count, g->d_red, stream));
+    kc::ReduceOut ro;
+    HIP_TRY(hipMemcpyAsync(&ro, g->d_red, sizeof(ro), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    const __int128 s1 = (__int128)(((unsigned __int128)(uint64_t)ro.sum_hi << 64) | ro.sum_lo);
+    const unsigned __int128 s2 = ((unsigned __int128)ro.sq_hi << 64) | ro.sq_lo;
+    res->sum_f_lo = ro.sum_lo;
+    res->sum_f_hi = ro.sum_hi;
+    res->sum_f2_lo = ro.sq_lo;
+    res->sum_f2_hi = ro.sq_hi;
+    res->count = count;
+    res->total_steps = ro.steps;
+    // kappa = sum f / (2 m count): one correctly rounded conversion, one division
+    res->kappa = (double)s1 / (double)(g->two_m * (int64_t)count);
+    if (count > 1) {
+        const double mean = (double)s1 / (double)count;
+        const double var = ((double)s2 - (double)count * mean * mean) / (double)(count - 1);
+        res->std_error = std::sqrt(std::max(var, 0.0) / (double)count) / (double)g->two_m;
+    } else {
+        res->std_error = std::nan("");
+    }
+    return KC_OK;
+}
+
+kc_status kc_estimate(kc_graph *g, uint64_t seed, int64_t first_sample, int32_t count,
+                      kc_result *result, int64_t *f_out, int64_t *steps_out, void *hip_stream) {
+    g_last_error.clear();
+    if (!g || !result) return fail(KC_ERR_INVALID, "NULL graph or result");
+    if (count < 1 || first_sample < 0) return fail(KC_ERR_INVALID, "count must be >= 1");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    int64_t *f = f_out, *steps = steps_out;
+    if (!f || !steps) {
+        kc_status st = ensure_fbuf(g, count);
+        if (st != KC_OK) return st;
+        if (!f) f = g->d_f;
+        if (!steps) steps = g->d_steps;
+    }
+    kc::RunParams rp{};
+    rp.seed = seed;
+    rp.first = first_sample;
+    rp.count = count;
+    rp.mode = kc::RUN_ESTIMATE;
+    rp.f_out = f;
+    rp.steps_out = steps;
+    kc_status st = run_persistent(g, rp, stream);
+    if (st != KC_OK) return st;
+    return finish_reduce(g, count, f, steps, result, stream);
+}
+
+kc_status kc_evaluate_trees(kc_graph *g, const int32_t *parents, int32_t count, int64_t *f_out,
+                            void *hip_stream) {
+    g_last_error.clear();
+    if (!g) return fail(KC_ERR_INVALID, "NULL graph");
+    if (count < 0) return fail(KC_ERR_INVALID, "negative count");
+    if (count == 0) return KC_OK;
+    if (!parents || !f_out) return fail(KC_ERR_INVALID, "parents/f_out is NULL");
+    kc::RunParams rp{};
+    rp.count = count;
+    rp.mode = kc::RUN_EVALUATE;
+    rp.parents_in = parents;
+    rp.f_out = f_out;
+    return run_persistent(g, rp, (hipStream_t)hip_stream);
+}
+
+}  // extern "C"

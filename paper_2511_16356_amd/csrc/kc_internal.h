@@ -1,0 +1,76 @@
+// kc_internal.h -- structures shared by the library's host code (kc_host.cpp)
+// and its kernels (kc_device.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kc {
+
+// Graph arrays resident on the device (read-only during sampling/traversal).
+struct GraphDev {
+    int32_t n;
+    int32_t root;
+    int64_t two_m;
+    const int64_t *off;   // [n+1] CSR row offsets
+    const int32_t *adj;   // [2m]  CSR neighbours, ascending per row
+    const int32_t *p0;    // [n]   tau0 parent (-1 at the root)
+    const int32_t *order; // [n]   walk start order: BFS order from the root
+    const int32_t *pre0;  // [n]   vertex at tau0 preorder position
+    const int32_t *out0;  // [n]   last tau0 preorder position inside Sub(tau0, v)
+    const int32_t *eoff;  // [nblk+1] per 64-position block: vertices whose tau0
+    const int32_t *elist; //          subtree started before the block and ends in it
+};
+
+// Per-slot workspace: one slot = one sample in flight = one wavefront.
+struct SlotDev {
+    uint64_t *st;    // [slots*n] sampler state word per vertex
+    uint64_t *word;  // [slots*n] pending-children | volume accumulator
+    int4 *rec;       // [slots*n] {tin_w, vol, parent, unused}
+    int32_t *ordr;   // [slots*n] bottom-up completion order
+    int32_t *grp;    // [slots*(n+1)] completion group boundaries
+    int32_t *leaves; // [slots*n] leaves of the tree
+    int64_t *fen;    // [slots*fen_len] Fenwick tree (sweep traversal only)
+    int64_t fen_len; // 2m + 2 (0 if not allocated)
+};
+
+enum RunMode { RUN_SAMPLE = 0, RUN_ESTIMATE = 1, RUN_EVALUATE = 2 };
+
+struct RunParams {
+    uint64_t seed;
+    int64_t first;
+    int32_t count;
+    int32_t walkers;    // 1..64
+    int32_t mode;       // RunMode
+    int32_t traversal;  // 1 walk, 2 sweep
+    int64_t iter_cap;   // sampler iterations per sample
+    const int32_t *parents_in; // RUN_EVALUATE input [count*n]
+    int32_t *parents_out;      // RUN_SAMPLE  [count*n]
+    uint32_t *cnt_out;         // RUN_SAMPLE  [count*n] (optional)
+    int64_t *steps_out;        // [count] (optional)
+    int64_t *f_out;            // [count] (RUN_ESTIMATE / RUN_EVALUATE)
+    int32_t *ctl;              // [4]: work counter, error code, error sample, spare
+};
+
+// Device result of the exact reduction.
+struct ReduceOut {
+    uint64_t sum_lo;
+    int64_t sum_hi;
+    uint64_t sq_lo;
+    uint64_t sq_hi;
+    int64_t steps;
+    int64_t pad[3];
+};
+
+// Error codes written by kernels into ctl[1] (match kc_status values).
+enum { DEV_OK = 0, DEV_LIMIT = 6, DEV_PROTOCOL = 8, DEV_BADTREE = 9 };
+
+// Launchers (kc_device.hip).  All are asynchronous on `stream`.
+hipError_t launch_reset_ctl(int32_t *ctl, hipStream_t stream);
+hipError_t launch_persistent(const GraphDev &g, const SlotDev &s, const RunParams &rp, int slots,
+                             hipStream_t stream);
+hipError_t launch_reduce(const int64_t *f, const int64_t *steps, int32_t count, ReduceOut *out,
+                         hipStream_t stream);
+hipError_t launch_zero_i64(int64_t *p, int64_t len, hipStream_t stream);
+
+}  // namespace kc

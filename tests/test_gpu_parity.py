@@ -1,0 +1,170 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+Bars (exact integer work, so exactness everywhere):
+  - sampled parent arrays and per-vertex draw counts bit-identical;
+  - per-tree f identical as int64;
+  - K-hat and its standard error bit-identical (both computed from the same
+    exact integer sums with the same double formula);
+  - results independent of walkers per sample, samples in flight, batch
+    split and traversal variant.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_16356_amd as kc
+    kc.library()  # raises if the HIP library is missing: no fallback
+    return kc
+
+
+def small_graphs(gen):
+    return {
+        "K3": gen.complete(3), "K5": gen.complete(5), "C7": gen.cycle(7), "P6": gen.path(6),
+        "star9": gen.star(9), "petersen": gen.petersen(), "grid8": gen.grid(8, 8),
+        "grid32": gen.grid(32, 32), "ba200": gen.barabasi_albert(200, 3, 1),
+        "gnm300": gen.largest_component(gen.gnm(300, 700, 5)),
+        "torus12": gen.torus(12, 12), "Q7": gen.hypercube(7),
+        "road3k": gen.road_like(3000, seed=4), "social3k": gen.chung_lu(3000, 2.2, 10.0, 300.0, seed=6),
+    }
+
+
+@pytest.fixture(scope="module")
+def graphs(gen):
+    return small_graphs(gen)
+
+
+@pytest.mark.parametrize("name", ["K3", "K5", "C7", "P6", "star9", "petersen", "grid8", "grid32",
+                                  "ba200", "gnm300", "torus12", "Q7", "road3k", "social3k"])
+def test_sampled_trees_bit_exact(kc, oracle_lib, graphs, name):
+    g = graphs[name]
+    _say("sample parity", name, g.n)
+    P = oracle_lib.prepare_graph(g)
+    count = 48
+    ref_par, ref_cnt, ref_steps = oracle_lib.sample(P, seed=77, s0=5, count=count, threads=8)
+    with kc.Graph.from_graph(g) as G:
+        assert G.root == P.root
+        par, cnt, stp = G.sample_trees(77, 5, count)
+        assert np.array_equal(par.cpu().numpy(), ref_par)
+        assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ref_cnt)
+        assert np.array_equal(stp.cpu().numpy(), ref_steps)
+
+
+@pytest.mark.parametrize("walkers,slots", [(1, 1), (2, 3), (7, 64), (64, 5), (64, 0)])
+def test_launch_shape_invariance(kc, oracle_lib, graphs, walkers, slots):
+    for name in ("grid32", "road3k", "social3k"):
+        g = graphs[name]
+        _say("invariance", name, walkers, slots)
+        P = oracle_lib.prepare_graph(g)
+        ref_par, ref_cnt, _ = oracle_lib.sample(P, seed=3, s0=100, count=20, threads=8)
+        with kc.Graph.from_graph(g) as G:
+            G.set_option(kc.KC_OPT_WALKERS, walkers)
+            G.set_option(kc.KC_OPT_SLOTS, slots)
+            par, cnt, _ = G.sample_trees(3, 100, 20)
+            assert np.array_equal(par.cpu().numpy(), ref_par)
+            assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ref_cnt)
+
+
+def test_batch_split_invariance(kc, graphs):
+    g = graphs["road3k"]
+    with kc.Graph.from_graph(g) as G:
+        whole, _, _ = G.sample_trees(9, 0, 30)
+        a, _, _ = G.sample_trees(9, 0, 11)
+        b, _, _ = G.sample_trees(9, 11, 19)
+        one, _, _ = G.sample_trees(9, 17, 1)
+        w = whole.cpu().numpy()
+        assert np.array_equal(w[:11], a.cpu().numpy())
+        assert np.array_equal(w[11:], b.cpu().numpy())
+        assert np.array_equal(w[17], one.cpu().numpy()[0])
+
+
+@pytest.mark.parametrize("trav", [1, 2])
+@pytest.mark.parametrize("name", ["K3", "petersen", "grid8", "grid32", "ba200", "gnm300",
+                                  "torus12", "road3k", "social3k"])
+def test_tree_values_exact(kc, oracle_lib, graphs, name, trav):
+    """f(tau) of oracle-sampled trees, evaluated on the GPU (both traversals)."""
+    import torch
+    g = graphs[name]
+    _say("f parity", name, trav)
+    P = oracle_lib.prepare_graph(g)
+    par, _, _ = oracle_lib.sample(P, seed=21, s0=0, count=24, threads=8)
+    ref = np.array([oracle_lib.f_of_tree(P, t, "alg1") for t in par], np.int64)
+    with kc.Graph.from_graph(g) as G:
+        G.set_option(kc.KC_OPT_TRAVERSAL, trav)
+        f = G.evaluate_trees(torch.from_numpy(par).cuda())
+        assert np.array_equal(f.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("trav", [1, 2])
+@pytest.mark.parametrize("name", ["K5", "grid32", "ba200", "road3k", "social3k", "Q7"])
+def test_estimate_exact(kc, oracle_lib, graphs, name, trav):
+    g = graphs[name]
+    _say("estimate parity", name, trav)
+    P = oracle_lib.prepare_graph(g)
+    count = 64
+    ref_f, ref_steps = oracle_lib.estimate_f(P, seed=1234, s0=7, count=count, threads=8)
+    K, se, s1, s2 = oracle_lib.reduce_estimate(ref_f, g.two_m)
+    with kc.Graph.from_graph(g) as G:
+        G.set_option(kc.KC_OPT_TRAVERSAL, trav)
+        est, f, stp = G.estimate(1234, 7, count, per_sample=True)
+        assert np.array_equal(f.cpu().numpy(), ref_f)
+        assert np.array_equal(stp.cpu().numpy(), ref_steps)
+        assert est.sum_f == s1 and est.sum_f2 == s2
+        assert est.kappa == K  # bit-identical
+        assert est.std_error == se
+        assert est.total_steps == int(ref_steps.sum())
+
+
+def test_grid32_full_config(kc, oracle_lib, gen):
+    """32x32 grid, 2,000 samples from seed 0: every f equal to the oracle's,
+    and K-hat within 4.5 standard errors of the exact Kemeny constant."""
+    from oracle import exact as E
+    g = gen.grid(32, 32)
+    P = oracle_lib.prepare_graph(g)
+    ref_f, _ = oracle_lib.estimate_f(P, seed=0, s0=0, count=2000, threads=8)
+    K, se, _, _ = oracle_lib.reduce_estimate(ref_f, g.two_m)
+    with kc.Graph.from_graph(g) as G:
+        est, f, _ = G.estimate(0, 0, 2000, per_sample=True)
+        assert np.array_equal(f.cpu().numpy(), ref_f)
+        assert est.kappa == K and est.std_error == se
+    Kx = E.kemeny_exact(g.offsets, g.indices)
+    assert abs(est.kappa - Kx) < 4.5 * est.std_error
+
+
+def test_step_limit_reports_error(kc, graphs):
+    g = graphs["grid32"]
+    with kc.Graph.from_graph(g) as G:
+        G.set_option(kc.KC_OPT_STEP_LIMIT, 50)
+        with pytest.raises(kc.KcError) as ei:
+            G.sample_trees(0, 0, 4)
+        assert ei.value.status == 6
+        G.set_option(kc.KC_OPT_STEP_LIMIT, 0)
+        par, _, _ = G.sample_trees(0, 0, 4)  # usable again afterwards
+        assert par.shape == (4, g.n)
+
+
+def test_evaluate_rejects_non_tree(kc, graphs):
+    import torch
+    g = graphs["grid8"]
+    with kc.Graph.from_graph(g) as G:
+        par, _, _ = G.sample_trees(1, 0, 2)
+        bad = par.clone()
+        v = 1 if G.root != 1 else 2
+        bad[0, v] = g.n + 5  # out of range parent
+        with pytest.raises(kc.KcError) as ei:
+            G.evaluate_trees(bad)
+        assert ei.value.status == 1
