@@ -1,0 +1,169 @@
+"""Benchmark: spanning-tree samples/s of the full estimator path on one MI355X.
+
+One step = one kc_estimate call over a batch of tree samples of the
+road-like workload (thinned random geometric graph from 1,000,000 points,
+largest component, int32 CSR; 4,096 samples per batch), i.e. the whole hot
+path: Wilson sampling, subtree volumes and numbering, f(tau) per tree and
+the exact reduction.  Inputs (graph and workspace) are resident in HBM before
+the timed region; sample ids advance from step to step.
+
+Prints ONE JSON line (rank 0).  Besides the contract fields it carries
+`roofline` (algorithmic HBM bytes of the persistent kernel per launch over
+its average duration, against the 8 TB/s HBM peak) and `cpu_baseline` (the
+CPU oracle on the host cores, on a bounded prefix of the same samples).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spanning-tree samples/s and K at ε=0.01 vs exact; served query p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+SECTOR = 64
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(draws: int, n: int, depth0: int, samples: int) -> int:
+    """Random 64-byte sectors the method itself must touch: one per Wilson draw
+    (the drawn vertex's per-sample state), one per vertex for the retrace, and
+    n * min(depth0, ceil(log2 n)) for the per-tree path-mapping sums."""
+    per_tree_trav = n * min(depth0, math.ceil(math.log2(max(2, n))))
+    return SECTOR * (draws + samples * (n + per_tree_trav))
+
+
+def cpu_baseline(g, seed: int, first: int, threads: int, per_thread: int):
+    import oracle
+    P = oracle.prepare_graph(g)
+    count = threads * per_thread
+    t0 = time.perf_counter()
+    oracle.estimate_f(P, seed=seed, s0=first, count=count, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": count / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": "samples %d..%d of the same workload (%d per thread), %.1f s" %
+                      (first, first + count - 1, per_thread, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--samples", type=int, default=4096, help="tree samples per step")
+    ap.add_argument("--points", type=int, default=1_000_000)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-per-thread", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(samples shard trivially by index; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import graphgen
+    import paper_2511_16356_amd as kc
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    g = graphgen.road_like(args.points, seed=0)
+    log("graph: n=%d 2m=%d (%.1f s)" % (g.n, g.two_m, time.perf_counter() - t0))
+    G = kc.Graph.from_graph(g)
+    info = G.info
+    stream = torch.cuda.current_stream()
+    # set-up (not a step): allocate the workspace with a tiny batch
+    G.estimate(args.seed, 10 ** 9, 2)
+    torch.cuda.synchronize()
+
+    B = args.samples
+    for w in range(args.warmup):
+        G.estimate(args.seed, (w + 1) * 10 ** 8, B)
+        log("warmup step %d done" % w)
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    draws = iters = 0
+    ests = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    ev0.record(stream)
+    for k in range(args.steps):
+        est = G.estimate(args.seed, k * B, B)
+        ests.append(est)
+        draws += est.total_steps
+        iters += est.sampler_iterations
+        log("step %d: kappa=%.1f +- %.1f draws/sample=%.0f" % (k, est.kappa, est.std_error, est.total_steps / B))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    gpu_ms = ev0.elapsed_time(ev1)
+
+    total = B * args.steps
+    value = total / wall
+    # pooled estimate over all timed steps
+    s1 = sum(e.sum_f for e in ests)
+    s2 = sum(e.sum_f2 for e in ests)
+    kappa = float(s1) / float(g.two_m * total)
+    mean = float(s1) / total
+    var = (float(s2) - total * mean * mean) / max(1, total - 1)
+    se = math.sqrt(max(var, 0.0) / total) / g.two_m
+    alg = algorithmic_bytes(draws, g.n, info["depth0"], total)
+    achieved = alg / (gpu_ms / 1e3) / 1e9  # GB/s: algorithmic bytes over the timed launches
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {
+            "workload": "road-like: thinned random geometric graph, %d uniform points, radius for "
+                        "mean degree 12, edges kept w.p. 0.2055, largest component (n=%d, m=%d, "
+                        "depth0=%d), int32 CSR; %d tree samples per step, Philox seed %d"
+                        % (args.points, g.n, g.two_m // 2, info["depth0"], B, args.seed),
+            "samples_per_step": B,
+            "parallelism": "1 GPU, one wavefront per sample in flight",
+        },
+        "kappa": kappa,
+        "kappa_std_error": se,
+        "kappa_rel_ci95": 1.959963984540054 * se / kappa if kappa else None,
+        "draws_per_sample": draws / total,
+        "draws_per_sampler_round": draws / max(1, iters),
+        "gpu_ms_per_step": gpu_ms / args.steps,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu:
+        threads = min(16, os.cpu_count() or 1)
+        try:
+            out["cpu_baseline"] = cpu_baseline(g, args.seed, 0, threads, args.cpu_per_thread)
+        except Exception as exc:  # the oracle is test infrastructure; report, never fall back
+            out["cpu_baseline"] = {"error": str(exc)}
+    G.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -77,8 +77,11 @@ enum {
     KC_OPT_WALKERS = 1,    /* cooperating walkers per sample, 1..64 (default 64) */
     KC_OPT_SLOTS = 2,      /* samples in flight per launch (0 = sized from free HBM) */
     KC_OPT_TRAVERSAL = 3,  /* KC_TRAV_* */
-    KC_OPT_STEP_LIMIT = 4, /* per-sample cap on sampler iterations (0 = default 4096 n + 2^20) */
-    KC_OPT_MEM_BUDGET = 5  /* bytes of device workspace the library may allocate (0 = 60% of free) */
+    KC_OPT_STEP_LIMIT = 4, /* per-sample cap on sampler rounds (0 = default 1024 n + 2^22) */
+    KC_OPT_MEM_BUDGET = 5, /* bytes of device workspace the library may allocate (0 = 60% of free) */
+    KC_OPT_START_ORDER = 6 /* order in which walks are started (results do not depend on it):
+                              0 = BFS order from the root, 1 = reverse BFS order,
+                              2 = a fixed pseudo-random permutation (default) */
 };
 
 /*
@@ -140,6 +143,8 @@ typedef struct {
     uint64_t sum_f2_hi;
     int64_t count;
     int64_t total_steps; /* Wilson draws over all samples */
+    int64_t sampler_iterations; /* lock-step sampler rounds over all samples; total_steps divided
+                                   by this is the mean number of walkers drawing per round */
 } kc_result;
 
 /*

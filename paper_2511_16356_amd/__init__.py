@@ -22,6 +22,7 @@ STATUS = {0: "KC_OK", 1: "KC_ERR_INVALID", 2: "KC_ERR_DISCONNECTED", 3: "KC_ERR_
           4: "KC_ERR_DEVICE", 5: "KC_ERR_OVERFLOW", 6: "KC_ERR_LIMIT", 7: "KC_ERR_UNSUPPORTED"}
 KC_TRAV_AUTO, KC_TRAV_WALK, KC_TRAV_SWEEP = 0, 1, 2
 KC_OPT_WALKERS, KC_OPT_SLOTS, KC_OPT_TRAVERSAL, KC_OPT_STEP_LIMIT, KC_OPT_MEM_BUDGET = 1, 2, 3, 4, 5
+KC_OPT_START_ORDER = 6
 
 # every symbol include/kc.h declares
 EXPORTS = ("kc_graph_create", "kc_graph_destroy", "kc_graph_get_info", "kc_set_option",
@@ -46,7 +47,8 @@ class _Result(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_double), ("std_error", ctypes.c_double),
                 ("sum_f_lo", ctypes.c_uint64), ("sum_f_hi", ctypes.c_int64),
                 ("sum_f2_lo", ctypes.c_uint64), ("sum_f2_hi", ctypes.c_uint64),
-                ("count", ctypes.c_int64), ("total_steps", ctypes.c_int64)]
+                ("count", ctypes.c_int64), ("total_steps", ctypes.c_int64),
+                ("sampler_iterations", ctypes.c_int64)]
 
 
 _lib = None
@@ -109,6 +111,7 @@ class Estimate:
     sum_f2: int
     count: int
     total_steps: int
+    sampler_iterations: int
 
 
 class Graph:
@@ -177,7 +180,8 @@ class Graph:
                                      _dptr(stp), _stream(stream)))
         s1 = (res.sum_f_hi << 64) | res.sum_f_lo
         s2 = (res.sum_f2_hi << 64) | res.sum_f2_lo
-        est = Estimate(res.kappa, res.std_error, s1, s2, res.count, res.total_steps)
+        est = Estimate(res.kappa, res.std_error, s1, s2, res.count, res.total_steps,
+                       res.sampler_iterations)
         return (est, f, stp) if per_sample else est
 
     def evaluate_trees(self, parents, stream=None):

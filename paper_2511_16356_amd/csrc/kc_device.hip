@@ -5,10 +5,12 @@
 //
 //   1. Uniform spanning tree by Wilson's algorithm (paper section 2.2 and
 //      Algorithm 1), organised as cooperative cycle popping: up to 64 lanes
-//      walk loop-erased random walks of the same sample at once.  The k-th
-//      draw at vertex v of sample s always uses the same Philox4x32-10 arrow,
-//      so the tree and the per-vertex draw counts are the unique cycle-popping
-//      outcome of those arrow stacks, whatever order the lanes pop in.
+//      drive loop-erased walks ("chains") of the same sample at once; a chain
+//      whose arrow lands on another chain's path is parked in an LDS table
+//      and its lane moves on.  The k-th draw at vertex v of sample s always
+//      uses the same Philox4x32-10 arrow, so the tree and the per-vertex draw
+//      counts are the unique cycle-popping outcome of those arrow stacks,
+//      whatever order the pops happen in.
 //   2. Subtree volumes vol(v) of the sampled tree (Algorithm 1, the loop that
 //      fills vol[]) by bottom-up carriers with one 64-bit atomic per vertex,
 //      and a volume-weighted preorder numbering tin(v) of the tree (top-down,
@@ -116,194 +118,357 @@ __device__ __forceinline__ uint32_t arrow_slot(uint64_t seed, uint64_t s, uint32
 
 // ------------------------------------------------------------ sampler state
 //
-// One 64-bit word per (sample, vertex):
-//   bits  0..31  next   : the vertex's current arrow target (tree parent once
-//                          the vertex is in the tree)
-//   bits 32..39  tag    : 0 = arrow not revealed ("free"), 1 = in the tree,
-//                          2 + L = on the current path of lane L
-//   bits 40..63  draws  : how many arrows the vertex has drawn so far
-constexpr uint32_t TAG_FREE = 0, TAG_TREE = 1, TAG_LANE0 = 2;
-constexpr uint64_t TAG_BITS = 0xFFull << 32;
-constexpr uint32_t DRAW_MAX = (1u << 24) - 1;
+// Three arrays per (sample, vertex):
+//   tagw  : bits 0..27 tag (0 = arrow not revealed ("free"), 1 = in the tree,
+//           2 + c = on the path of chain c); bit 28 wait (a parked chain's
+//           arrow points here); bit 29 need (the vertex's turn as a walk
+//           start passed while it was on a path).  A free vertex's word is 0.
+//   nxt   : the vertex's current arrow target (its tree parent at the end)
+//   draws : how many arrows the vertex has drawn
+constexpr uint32_t T_FREE = 0, T_TREE = 1, T_CHAIN0 = 2;
+constexpr uint32_t TW_TAG = (1u << 28) - 1;
+constexpr uint32_t TW_WAIT = 1u << 28;
+constexpr uint32_t TW_NEED = 1u << 29;
 
-__device__ __forceinline__ uint32_t tag_of(uint64_t w) { return (uint32_t)(w >> 32) & 0xFFu; }
-__device__ __forceinline__ uint32_t draws_of(uint64_t w) { return (uint32_t)(w >> 40); }
-__device__ __forceinline__ int32_t next_of(uint64_t w) { return (int32_t)(uint32_t)w; }
-__device__ __forceinline__ uint64_t make_word(int32_t nxt, uint32_t draws, uint32_t tag) {
-    return ((uint64_t)((draws << 8) | tag) << 32) | (uint64_t)(uint32_t)nxt;
-}
+// A chain is a loop-erased path of revealed arrows owned by one walk: from
+// its start vertex to its head.  A lane drives at most one chain at a time.
+// When the head's arrow lands on another chain's path, the chain is parked
+// (the wait bit marks the vertex) and the lane takes other work; the chain is
+// woken when that vertex is popped (resume there) or joins the tree
+// (retrace).  A start vertex that already lies on a path is skipped with its
+// need bit set; if it is popped later its eraser queues it for a restart.
+// Popped vertices are also offered as optional extra starts (a small LIFO):
+// revealing any free vertex is work the cycle-popping order fixes anyway.
+constexpr int CH = 1024;   // chains per sample
+constexpr int HINTS = 256; // optional restart hints
 
-// Lane modes of the cooperative sampler.
+enum : int { CS_FREE = 0, CS_ACTIVE = 1, CS_PARKED = 2, CS_QUEUED = 3 };
+enum : int { T_RESUME = 0, T_RETRACE = 1, T_POP = 2 };
+
+// Lane modes.
 enum : int {
-    M_IDLE = 0,    // no work; takes the next start vertex
-    M_PROBE = 1,   // looking at a start vertex (no path yet)
-    M_WAITV = 2,   // start vertex is on another lane's path; wait for it
+    M_IDLE = 0,    // no work
+    M_PROBE = 1,   // first look at a fresh chain's start vertex
+    M_CLAIM = 2,   // resume: look at (and claim) the vertex the head points to
     M_WALK = 3,    // at head `cur` (claimed, arrow not revealed): draw and step
-    M_BLOCKED = 4, // head's arrow points at `tgt`, on lane `owner`'s path
-    M_ERASE0 = 5,  // popping a cycle: keep `tgt`, erase its path successors
-    M_ERASE = 6,   // popping: free `tgt`, follow next until `stopv`
-    M_RETRACE = 7  // path reached the tree: mark from `tgt` until `stopv`
+    M_ERASE0 = 4,  // popping: keep `tgt` as the new head, erase what follows it
+    M_ERASE = 5,   // popping: free `tgt`, follow next until `stopv`
+    M_RETRACE = 6  // path met the tree: mark from `tgt` until `stopv`
 };
 
-// Cooperative cycle popping (Wilson's walks run by up to `walkers` lanes).
+struct SamplerShared {
+    int32_t start[CH];   // chain start vertex
+    int32_t block[CH];   // parked: vertex the head's arrow points at
+    int16_t up[CH];      // parked: chain owning `block`
+    int8_t state[CH];    // CS_*
+    int16_t freestk[CH]; // free chain ids
+    int32_t hint[HINTS];
+    int32_t wake_v[WAVE];
+    int8_t wake_k[WAVE];
+};
+
+struct SamplerWS {
+    uint32_t *tagw;
+    int32_t *nxt;
+    uint32_t *draws;
+    int32_t *rq;   // restart ring (n entries)
+    int4 *queue;   // ready tasks (CH entries): {chain, kind, e, stop}
+};
+
+// Cooperative cycle popping of one sample by one wavefront.
 //
-// Each lane runs loop-erased walks exactly as in Wilson's algorithm, with
-// loops popped explicitly (every vertex of a popped cycle becomes free again
-// and will draw its next arrow when revisited).  A lane whose step lands on
-// another lane's current path stops there (its arrow now points into that
-// path) until the vertex joins the tree (the whole path is then retraced
-// into the tree) or is popped (the lane continues from it).  A cycle of
-// such waits is a cycle of revealed arrows spanning several paths; it is
-// found with pointer doubling over the 64 lanes and popped as a whole.
-// Only genuine cycles of current arrows are ever popped, so the result is
-// the cycle-popping outcome: independent of timing and of `walkers`.
+// Every chain runs Wilson's loop-erased walk with loops popped explicitly
+// (each vertex of a popped cycle becomes free and draws its next arrow when
+// revisited).  Parked chains form a wait-for forest (chain -> owner of the
+// vertex it points at); when a park closes a cycle in it, that is a cycle of
+// current arrows spanning several chains, and it is popped as a whole.  Only
+// genuine cycles of current arrows are ever popped, so the result is the
+// cycle-popping outcome of the arrow stacks: independent of timing, of
+// `walkers`, of the chain table and of which free vertices are started.
 //
 // Returns the total number of draws, or -1 (error recorded in ctl).
-__device__ int64_t sample_tree(const GraphDev &g, uint64_t *__restrict__ st, uint64_t seed,
-                               uint64_t s, int walkers, int64_t iter_cap, int32_t *ctl, int idx) {
-    __shared__ int sh_img[WAVE];
-    __shared__ int sh_ent[WAVE];
+__device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, uint64_t seed, uint64_t s,
+                               int walkers, int64_t iter_cap, int32_t *ctl, int idx,
+                               int64_t *iters_used) {
+    __shared__ SamplerShared sh;
     const int lane = threadIdx.x;
     const int n = g.n, root = g.root;
-    for (int v = lane; v < n; v += WAVE) astore(&st[v], make_word(-1, 0, v == root ? TAG_TREE : TAG_FREE));
+    uint32_t *__restrict__ tagw = ws.tagw;
+    int32_t *__restrict__ nxt = ws.nxt;
+    uint32_t *__restrict__ drw = ws.draws;
+    for (int v = lane; v < n; v += WAVE) {
+        astore(&tagw[v], v == root ? T_TREE : T_FREE);
+        astore(&nxt[v], (int32_t)-1);
+        astore(&drw[v], 0u);
+    }
+    for (int c = lane; c < CH; c += WAVE) {
+        sh.state[c] = CS_FREE;
+        sh.freestk[c] = (int16_t)(CH - 1 - c);
+    }
     fence_wg();
+    __syncthreads();
 
-    const uint32_t mytag = TAG_LANE0 + (uint32_t)lane;
     const bool worker = lane < walkers;
-    int mode = M_IDLE, start = -1, cur = -1, tgt = -1, stopv = -1, owner = -1;
-    uint32_t draws = 0;
-    int next_start = 0;
+    int mode = M_IDLE, chain = -1, cur = -1, tgt = -1, stopv = -1;
+    uint32_t ctag = 0, dcur = 0, gcur = 0;
+    int64_t ocur = 0;
+    // wave-uniform bookkeeping
+    int next_start = 0, q_head = 0, q_tail = 0, free_top = CH, parked = 0, hint_top = 0;
+    int64_t rq_head = 0, rq_tail = 0;
     int64_t iters = 0, mysteps = 0;
     int err = 0;
 
     while (true) {
-        // hand out start vertices in BFS order to idle lanes
-        const uint64_t idle = __ballot(worker && mode == M_IDLE);
-        if (next_start < n) {
+        // ---- phase 0: idle lanes take tasks, restarts, fresh starts, then hints
+        {
+            const uint64_t idle = __ballot(worker && mode == M_IDLE);
+            const int nidle = __popcll(idle);
+            const int take_q = min(nidle, q_tail - q_head);
+            int left = nidle - take_q, room = free_top;
+            const int take_r = (int)min((int64_t)min(left, room), rq_tail - rq_head);
+            left -= take_r; room -= take_r;
+            const int take_s = min(min(left, room), n - next_start);
+            left -= take_s; room -= take_s;
+            const int take_h = min(min(left, room), hint_top);
             if (worker && mode == M_IDLE) {
-                const int pos = next_start + rank_in(idle);
-                if (pos < n) {
-                    start = g.order[pos];
-                    tgt = start;
+                const int r = rank_in(idle);
+                if (r < take_q) {
+                    const int4 t = ws.queue[(q_head + r) & (CH - 1)];
+                    chain = t.x;
+                    ctag = T_CHAIN0 + (uint32_t)chain;
+                    if (t.y == T_RESUME) {
+                        tgt = t.z;
+                        mode = M_CLAIM;
+                    } else if (t.y == T_RETRACE) {
+                        tgt = sh.start[chain];
+                        stopv = t.z;
+                        mode = M_RETRACE;
+                    } else {
+                        tgt = t.z;
+                        stopv = t.w;
+                        mode = M_ERASE0;
+                    }
+                } else if (r < take_q + take_r + take_s + take_h) {
+                    const int k = r - take_q;
+                    chain = sh.freestk[free_top - 1 - k];
+                    ctag = T_CHAIN0 + (uint32_t)chain;
+                    if (k < take_r) tgt = aload(&ws.rq[(rq_head + k) % n]);
+                    else if (k < take_r + take_s) tgt = g.order[next_start + (k - take_r)];
+                    else tgt = sh.hint[hint_top - 1 - (k - take_r - take_s)];
+                    sh.start[chain] = tgt;
                     mode = M_PROBE;
                 }
+                if (mode != M_IDLE) sh.state[chain] = CS_ACTIVE;
             }
-            next_start += __popcll(idle);
+            q_head += take_q;
+            rq_head += take_r;
+            next_start += take_s;
+            hint_top -= take_h;
+            free_top -= take_r + take_s + take_h;
         }
-        if (__ballot(mode != M_IDLE) == 0ull) break;  // all idle and no start left
-        if (++iters > iter_cap) { err = DEV_LIMIT; }
+        __syncthreads();
+        if (__ballot(mode != M_IDLE) == 0ull) {
+            if (next_start < n || q_tail != q_head || parked != 0 || rq_tail != rq_head)
+                err = DEV_PROTOCOL;
+            break;
+        }
+        if (++iters > iter_cap) err = DEV_LIMIT;
 
-        // ---- phase A: the step of each busy lane
-        bool stepped = false;
-        // every state index is range-checked: a protocol fault becomes an
-        // error code, never an out-of-bounds access
+        // ---- phase A: one step of each busy lane
+        bool stepped = false, retire = false;
+        int wake_kind = -1, wake_vtx = -1, restart_vtx = -1, hint_vtx = -1;
+        int rev_v = -1;  // reveal deferred to phase B (only this chain reads it)
         if (err == 0 && mode != M_IDLE) {
             const int chk = (mode == M_WALK) ? cur : tgt;
             if ((unsigned)chk >= (unsigned)n) err = DEV_PROTOCOL;
         }
         if (err == 0) {
             if (mode == M_WALK) {
-                const int64_t o = g.off[cur];
-                const uint32_t d = (uint32_t)(g.off[cur + 1] - o);
-                const uint32_t j = arrow_slot(seed, s, (uint32_t)cur, draws, d);
-                const int32_t y = g.adj[o + j];
-                draws += 1;
-                if (draws > DRAW_MAX) err = DEV_LIMIT;
-                astore(&st[cur], make_word(y, draws, mytag));
+                const uint32_t j = arrow_slot(seed, s, (uint32_t)cur, dcur, gcur);
+                const int32_t y = g.adj[ocur + j];
+                rev_v = cur;
+                dcur += 1;
                 tgt = y;
                 stepped = true;
                 mysteps++;
             } else if (mode == M_ERASE) {
-                const uint64_t old = afetch_and(&st[tgt], ~TAG_BITS);
-                if (tag_of(old) != mytag) err = DEV_PROTOCOL;
-                const int32_t nz = next_of(old);
+                const uint32_t old = __hip_atomic_exchange(&tagw[tgt], T_FREE, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                const int32_t nz = aload(&nxt[tgt]);
+                if ((old & TW_TAG) != ctag) err = DEV_PROTOCOL;
+                if (old & TW_WAIT) { wake_kind = T_RESUME; wake_vtx = tgt; }
+                if (old & TW_NEED) restart_vtx = tgt;
+                else hint_vtx = tgt;
                 if (nz == stopv) mode = M_WALK; else tgt = nz;
             } else if (mode == M_ERASE0) {
-                const uint64_t w = aload(&st[tgt]);
-                if (tag_of(w) != mytag) err = DEV_PROTOCOL;
+                const uint32_t tw = aload(&tagw[tgt]);
+                const int32_t nz = aload(&nxt[tgt]);
+                dcur = aload(&drw[tgt]);
+                ocur = g.off[tgt];
+                gcur = (uint32_t)(g.off[tgt + 1] - ocur);
+                if ((tw & TW_TAG) != ctag) err = DEV_PROTOCOL;
                 cur = tgt;
-                draws = draws_of(w);
-                const int32_t nz = next_of(w);
                 if (nz == stopv) mode = M_WALK;
                 else { mode = M_ERASE; tgt = nz; }
             } else if (mode == M_RETRACE) {
-                const uint64_t old = afetch_xor(&st[tgt], (uint64_t)(mytag ^ TAG_TREE) << 32);
-                if (tag_of(old) != mytag) err = DEV_PROTOCOL;
-                const int32_t nz = next_of(old);
-                if (nz == stopv) mode = M_IDLE; else tgt = nz;
+                if (tgt == stopv) {
+                    retire = true;  // empty chain: nothing to mark
+                } else {
+                    const uint32_t old = __hip_atomic_exchange(&tagw[tgt], T_TREE, __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                    const int32_t nz = aload(&nxt[tgt]);
+                    if ((old & TW_TAG) != ctag) err = DEV_PROTOCOL;
+                    if (old & TW_WAIT) { wake_kind = T_RETRACE; wake_vtx = tgt; }
+                    if (nz == stopv) retire = true; else tgt = nz;
+                }
             }
         }
-        fence_wg();
-
-        // ---- phase B/C: look at the target, claim free vertices
-        bool newblock = false;
-        if (err == 0 && (stepped || mode == M_BLOCKED || mode == M_WAITV || mode == M_PROBE) &&
-            (unsigned)tgt >= (unsigned)n)
-            err = DEV_PROTOCOL;
-        if (err == 0 && (stepped || mode == M_BLOCKED || mode == M_WAITV || mode == M_PROBE)) {
-            const bool haspath = stepped || mode == M_BLOCKED;
-            const uint64_t w = aload(&st[tgt]);
-            uint32_t tg = tag_of(w);
-            bool claimed = false;
-            if (tg == TAG_FREE) {
-                const uint64_t want = (w & ~TAG_BITS) | ((uint64_t)mytag << 32);
-                const uint64_t prev = acas(&st[tgt], w, want);
-                if (prev == w) claimed = true;
-                else tg = tag_of(prev);
+        // popped vertices: need-restarts to the queue, the rest offered as hints
+        {
+            const uint64_t qm = __ballot(restart_vtx >= 0);
+            if (restart_vtx >= 0) astore(&ws.rq[(rq_tail + rank_in(qm)) % n], (int32_t)restart_vtx);
+            rq_tail += __popcll(qm);
+            const uint64_t hm = __ballot(hint_vtx >= 0);
+            if (hint_vtx >= 0) {
+                const int k = hint_top + rank_in(hm);
+                if (k < HINTS) sh.hint[k] = hint_vtx;
             }
-            if (claimed) {
-                if (!haspath) start = tgt;
+            hint_top = min(HINTS, hint_top + __popcll(hm));
+        }
+        // retired chains return to the free stack
+        {
+            const uint64_t rm = __ballot(retire);
+            if (retire) {
+                sh.freestk[free_top + rank_in(rm)] = (int16_t)chain;
+                sh.state[chain] = CS_FREE;
+                mode = M_IDLE;
+                chain = -1;
+            }
+            free_top += __popcll(rm);
+        }
+        fence_wg();
+        __syncthreads();
+        // wake chains parked on vertices that were popped or joined the tree
+        {
+            const uint64_t wm = __ballot(wake_kind >= 0);
+            if (wm != 0ull) {
+                if (wake_kind >= 0) {
+                    const int k = rank_in(wm);
+                    sh.wake_v[k] = wake_vtx;
+                    sh.wake_k[k] = (int8_t)wake_kind;
+                }
+                __syncthreads();
+                const int nw = __popcll(wm);
+                for (int i = 0; i < CH / WAVE; ++i) {
+                    const int c = lane + i * WAVE;
+                    int kind = -1;
+                    if (sh.state[c] == CS_PARKED) {
+                        const int b = sh.block[c];
+                        for (int k = 0; k < nw; ++k)
+                            if (sh.wake_v[k] == b) kind = sh.wake_k[k];
+                    }
+                    const uint64_t pm = __ballot(kind >= 0);
+                    if (kind >= 0) {
+                        ws.queue[(q_tail + rank_in(pm)) & (CH - 1)] = make_int4(c, kind, sh.block[c], 0);
+                        sh.state[c] = CS_QUEUED;
+                    }
+                    q_tail += __popcll(pm);
+                    parked -= __popcll(pm);
+                }
+                __syncthreads();
+            }
+        }
+
+        // ---- phase B: publish the reveal, look at the target, claim it if free
+        const bool looks = err == 0 && (stepped || mode == M_PROBE || mode == M_CLAIM);
+        if (looks && (unsigned)tgt >= (unsigned)n) err = DEV_PROTOCOL;
+        bool park = false;
+        int park_owner = -1;
+        if (rev_v >= 0 && err == 0) {
+            astore(&nxt[rev_v], tgt);
+            astore(&drw[rev_v], dcur);
+        }
+        if (err == 0 && looks) {
+            const bool haspath = mode != M_PROBE;  // walked or resumed chain
+            const uint32_t old = acas(&tagw[tgt], T_FREE, ctag);
+            const uint32_t dt = aload(&drw[tgt]);
+            const int32_t nt = aload(&nxt[tgt]);
+            const int64_t o_t = g.off[tgt];
+            const uint32_t d_t = (uint32_t)(g.off[tgt + 1] - o_t);
+            const uint32_t tg = old & TW_TAG;
+            if (old == T_FREE) {
                 cur = tgt;
-                draws = draws_of(w);
+                dcur = dt;
+                ocur = o_t;
+                gcur = d_t;
                 mode = M_WALK;
-            } else if (tg == TAG_TREE) {
-                if (haspath) { mode = M_RETRACE; stopv = tgt; tgt = start; }
-                else mode = M_IDLE;
-            } else if (tg == mytag) {
+            } else if (tg == T_TREE) {
+                stopv = tgt;
+                if (haspath) tgt = sh.start[chain];
+                mode = M_RETRACE;  // an empty chain retires at once
+            } else if (tg == ctag) {
                 // own path: the new arrow closed a loop at tgt; pop it, keep tgt as head
                 if (!stepped) err = DEV_PROTOCOL;
                 cur = tgt;
-                draws = draws_of(w);
+                dcur = dt;
+                ocur = o_t;
+                gcur = d_t;
                 stopv = tgt;
-                tgt = next_of(w);
+                tgt = nt;
                 mode = M_ERASE;
-            } else if (tg >= TAG_LANE0) {
-                const int no = (int)tg - (int)TAG_LANE0;
+            } else if (tg >= T_CHAIN0 && tg < T_CHAIN0 + CH) {
                 if (haspath) {
-                    newblock = (mode != M_BLOCKED) || (owner != no);
-                    mode = M_BLOCKED;
+                    park = true;
+                    park_owner = (int)(tg - T_CHAIN0);
                 } else {
-                    mode = M_WAITV;
+                    // start vertex already on a path: skip it, restart it if it is popped
+                    __hip_atomic_fetch_or(&tagw[tgt], TW_NEED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    stopv = tgt;
+                    mode = M_RETRACE;
                 }
-                owner = no;
             } else {
-                err = DEV_PROTOCOL;  // a free vertex cannot lose a race to anything but a claim
+                err = DEV_PROTOCOL;
             }
+        }
+        __syncthreads();
+
+        // ---- parks, one at a time: record, then look for a cycle through the new edge
+        uint64_t pm = __ballot(park);
+        if (park) {
+            __hip_atomic_fetch_or(&tagw[tgt], TW_WAIT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        while (pm != 0ull) {
+            const int L = __ffsll((unsigned long long)pm) - 1;
+            pm &= pm - 1;
+            int ncyc = 0;
+            if (lane == L) {
+                const int c = chain;
+                sh.block[c] = tgt;
+                sh.up[c] = (int16_t)park_owner;
+                sh.state[c] = CS_PARKED;
+                int x = park_owner, len = 0;
+                while (x != c && sh.state[x] == CS_PARKED && len < CH) { x = sh.up[x]; ++len; }
+                if (x == c) {
+                    // the chains c -> up(c) -> ... -> c form a cycle of arrows: pop all of
+                    // them; each keeps the vertex where its predecessor entered it
+                    int prev = c, m;
+                    do {
+                        m = sh.up[prev];
+                        ws.queue[(q_tail + ncyc) & (CH - 1)] = make_int4(m, T_POP, sh.block[prev], sh.block[m]);
+                        sh.state[m] = CS_QUEUED;
+                        ++ncyc;
+                        prev = m;
+                    } while (m != c && ncyc <= CH);
+                }
+                mode = M_IDLE;
+                chain = -1;
+            }
+            ncyc = __shfl(ncyc, L);
+            parked += 1 - ncyc;
+            q_tail += ncyc;
+            __syncthreads();
         }
         fence_wg();
-
-        // ---- phase D: find cycles among waiting lanes and pop them
-        if (__ballot(newblock) != 0ull) {
-            const int wf = (mode == M_BLOCKED) ? (owner & (WAVE - 1)) : lane;
-            int J = wf;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) J = __shfl(J, J);  // J = wf^64(lane)
-            sh_img[lane] = 0;
-            __syncthreads();
-            sh_img[J] = 1;
-            __syncthreads();
-            const bool onc = (mode == M_BLOCKED) && sh_img[lane] != 0;
-            if (__ballot(onc) != 0ull) {
-                if (onc) sh_ent[owner & (WAVE - 1)] = tgt;  // my arrow enters `owner`'s path at tgt
-                __syncthreads();
-                if (onc) {
-                    stopv = tgt;
-                    tgt = sh_ent[lane];  // where my predecessor entered my path
-                    mode = M_ERASE0;
-                }
-            }
-            __syncthreads();
-        }
         if (__ballot(err != 0) != 0ull) break;
     }
     const int e = wave_max(err);
@@ -311,13 +476,15 @@ __device__ int64_t sample_tree(const GraphDev &g, uint64_t *__restrict__ st, uin
         report_error(ctl, e, idx);
         return -1;
     }
+    *iters_used = iters;
     return wave_sum(mysteps);
 }
 
 // --------------------------------------------------------- tree traversal
 
 struct SlotPtrs {
-    uint64_t *st, *word, *rec;  // rec: 2 words per vertex {vol<<32 | tin, parent}
+    SamplerWS ws;
+    uint64_t *word, *rec;  // rec: 2 words per vertex {vol<<32 | tin, parent}
     int32_t *ordr, *grp, *leaves;
     int64_t *fen;
 };
@@ -581,7 +748,11 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
     const int lane = threadIdx.x;
     const size_t n = (size_t)g.n;
     SlotPtrs sp;
-    sp.st = sd.st + (size_t)blockIdx.x * n;
+    sp.ws.tagw = sd.tagw + (size_t)blockIdx.x * n;
+    sp.ws.nxt = sd.nxt + (size_t)blockIdx.x * n;
+    sp.ws.draws = sd.draws + (size_t)blockIdx.x * n;
+    sp.ws.rq = sd.rq + (size_t)blockIdx.x * n;
+    sp.ws.queue = sd.queue + (size_t)blockIdx.x * CH;
     sp.word = sd.word ? sd.word + (size_t)blockIdx.x * n : nullptr;
     sp.rec = sd.rec ? reinterpret_cast<uint64_t *>(sd.rec) + 2 * (size_t)blockIdx.x * n : nullptr;
     sp.ordr = sd.ordr ? sd.ordr + (size_t)blockIdx.x * n : nullptr;
@@ -596,18 +767,17 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
         if (idx >= rp.count) break;
         if (__hip_atomic_load(&rp.ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
         const uint64_t s = (uint64_t)(rp.first + idx);
-        int64_t steps = 0;
+        int64_t steps = 0, iters = 0;
         if (rp.mode != RUN_EVALUATE) {
-            steps = sample_tree(g, sp.st, rp.seed, s, rp.walkers, rp.iter_cap, rp.ctl, idx);
+            steps = sample_tree(g, sp.ws, rp.seed, s, rp.walkers, rp.iter_cap, rp.ctl, idx, &iters);
             if (steps < 0) break;
         }
         if (rp.mode == RUN_SAMPLE) {
             int32_t *po = rp.parents_out + (size_t)idx * n;
             uint32_t *co = rp.cnt_out ? rp.cnt_out + (size_t)idx * n : nullptr;
             for (int v = lane; v < g.n; v += WAVE) {
-                const uint64_t w = aload(&sp.st[v]);
-                po[v] = (v == g.root) ? -1 : next_of(w);
-                if (co) co[v] = draws_of(w);
+                po[v] = (v == g.root) ? -1 : aload(&sp.ws.nxt[v]);
+                if (co) co[v] = aload(&sp.ws.draws[v]);
             }
         } else {
             // parents into rec[2v+1]
@@ -618,7 +788,7 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
                     p = -1;
                 } else {
                     p = (rp.mode == RUN_EVALUATE) ? rp.parents_in[(size_t)idx * n + v]
-                                                  : next_of(aload(&sp.st[v]));
+                                                  : aload(&sp.ws.nxt[v]);
                     if (p < 0 || p >= g.n || p == v) { bad = true; p = g.root; }
                 }
                 astore(&sp.rec[2 * (size_t)v + 1], (uint64_t)(uint32_t)p);
@@ -633,6 +803,7 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
             if (lane == 0) rp.f_out[idx] = f;
         }
         if (rp.steps_out && lane == 0) rp.steps_out[idx] = steps;
+        if (rp.iters_out && lane == 0) rp.iters_out[idx] = iters;
     }
 }
 
@@ -648,27 +819,32 @@ __global__ void zero_i64_kernel(int64_t *p, int64_t len) {
 
 // Exact sums of f and f^2 (128-bit) and of the draw counts; one block.
 __global__ void __launch_bounds__(256) reduce_kernel(const int64_t *f, const int64_t *steps,
-                                                     int32_t count, ReduceOut *out) {
+                                                     const int64_t *iters, int32_t count,
+                                                     ReduceOut *out) {
     __shared__ unsigned __int128 sh_s[256];
     __shared__ unsigned __int128 sh_q[256];
     __shared__ int64_t sh_t[256];
+    __shared__ int64_t sh_i[256];
     unsigned __int128 s = 0, q = 0;
-    int64_t t = 0;
+    int64_t t = 0, it = 0;
     for (int i = threadIdx.x; i < count; i += 256) {
         const __int128 x = f[i];
         s += (unsigned __int128)x;
         q += (unsigned __int128)(x * x);
         if (steps) t += steps[i];
+        if (iters) it += iters[i];
     }
     sh_s[threadIdx.x] = s;
     sh_q[threadIdx.x] = q;
     sh_t[threadIdx.x] = t;
+    sh_i[threadIdx.x] = it;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
             sh_s[threadIdx.x] += sh_s[threadIdx.x + w];
             sh_q[threadIdx.x] += sh_q[threadIdx.x + w];
             sh_t[threadIdx.x] += sh_t[threadIdx.x + w];
+            sh_i[threadIdx.x] += sh_i[threadIdx.x + w];
         }
         __syncthreads();
     }
@@ -678,6 +854,7 @@ __global__ void __launch_bounds__(256) reduce_kernel(const int64_t *f, const int
         out->sq_lo = (uint64_t)sh_q[0];
         out->sq_hi = (uint64_t)(sh_q[0] >> 64);
         out->steps = sh_t[0];
+        out->iters = sh_i[0];
     }
 }
 
@@ -694,9 +871,18 @@ hipError_t launch_persistent(const GraphDev &g, const SlotDev &s, const RunParam
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const int64_t *f, const int64_t *steps, int32_t count, ReduceOut *out,
-                         hipStream_t stream) {
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, stream, f, steps, count, out);
+int sampler_chains() { return CH; }
+
+int persistent_blocks_per_cu() {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, persistent_kernel, WAVE, 0) != hipSuccess)
+        return 0;
+    return blocks;
+}
+
+hipError_t launch_reduce(const int64_t *f, const int64_t *steps, const int64_t *iters, int32_t count,
+                         ReduceOut *out, hipStream_t stream) {
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, stream, f, steps, iters, count, out);
     return hipGetLastError();
 }
 

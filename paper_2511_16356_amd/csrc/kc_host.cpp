@@ -62,6 +62,8 @@ struct kc_graph {
     int64_t mem_budget = 0;
     int64_t graph_bytes = 0;
     int32_t nblk = 0;
+    int32_t start_order = 2;
+    std::vector<int32_t> bfs_order;  // host copy of the BFS order from the root
     // graph arrays on the device
     int64_t *d_off = nullptr;
     int32_t *d_adj = nullptr, *d_p0 = nullptr, *d_order = nullptr, *d_pre0 = nullptr;
@@ -69,11 +71,14 @@ struct kc_graph {
     // workspace
     int ws_slots = 0;
     bool ws_trav = false, ws_fen = false;
-    uint64_t *d_st = nullptr, *d_word = nullptr;
+    uint32_t *d_tagw = nullptr, *d_draws = nullptr;
+    int32_t *d_nxt = nullptr, *d_rq = nullptr;
+    int4 *d_queue = nullptr;
+    uint64_t *d_word = nullptr;
     int4 *d_rec = nullptr;
     int32_t *d_ordr = nullptr, *d_grp = nullptr, *d_leaves = nullptr;
     int64_t *d_fen = nullptr;
-    int64_t *d_f = nullptr, *d_steps = nullptr;  // internal per-sample buffers
+    int64_t *d_f = nullptr, *d_steps = nullptr, *d_iters = nullptr;  // internal per-sample buffers
     int64_t fbuf_len = 0;
     int32_t *d_ctl = nullptr;
     kc::ReduceOut *d_red = nullptr;
@@ -82,9 +87,11 @@ struct kc_graph {
 namespace {
 
 void free_workspace(kc_graph *g) {
-    dev_free(g->d_st); dev_free(g->d_word); dev_free(g->d_rec); dev_free(g->d_ordr);
+    dev_free(g->d_tagw); dev_free(g->d_nxt); dev_free(g->d_draws); dev_free(g->d_rq);
+    dev_free(g->d_queue); dev_free(g->d_word); dev_free(g->d_rec); dev_free(g->d_ordr);
     dev_free(g->d_grp); dev_free(g->d_leaves); dev_free(g->d_fen);
-    g->d_st = g->d_word = nullptr; g->d_rec = nullptr;
+    g->d_tagw = g->d_draws = nullptr; g->d_nxt = g->d_rq = nullptr; g->d_queue = nullptr;
+    g->d_word = nullptr; g->d_rec = nullptr;
     g->d_ordr = g->d_grp = g->d_leaves = nullptr; g->d_fen = nullptr;
     g->ws_slots = 0; g->ws_trav = g->ws_fen = false;
 }
@@ -93,11 +100,32 @@ void free_all(kc_graph *g) {
     free_workspace(g);
     dev_free(g->d_off); dev_free(g->d_adj); dev_free(g->d_p0); dev_free(g->d_order);
     dev_free(g->d_pre0); dev_free(g->d_out0); dev_free(g->d_eoff); dev_free(g->d_elist);
-    dev_free(g->d_f); dev_free(g->d_steps); dev_free(g->d_ctl); dev_free(g->d_red);
+    dev_free(g->d_f); dev_free(g->d_steps); dev_free(g->d_iters); dev_free(g->d_ctl); dev_free(g->d_red);
+}
+
+// Walk start orders.  Wilson's algorithm may start its walks in any order
+// and the cycle-popping outcome is the same; the order only changes how often
+// concurrent walks run into each other.  Walks started at scattered random
+// vertices collide far less than walks started in BFS order around the root.
+std::vector<int32_t> start_order_of(const std::vector<int32_t> &bfs, int kind) {
+    std::vector<int32_t> ord = bfs;
+    if (kind == 1) std::reverse(ord.begin(), ord.end());
+    if (kind == 2) {
+        uint64_t x = 0x9E3779B97F4A7C15ull;
+        for (size_t i = ord.size(); i > 1; --i) {  // Fisher-Yates driven by splitmix64
+            x += 0x9E3779B97F4A7C15ull;
+            uint64_t z = x;
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            z ^= z >> 31;
+            std::swap(ord[i - 1], ord[(size_t)(z % i)]);
+        }
+    }
+    return ord;
 }
 
 int64_t slot_bytes(const kc_graph *g, bool trav, bool fen) {
-    int64_t b = 8 * g->n;  // sampler state
+    int64_t b = 16 * g->n + 16 * (int64_t)kc::sampler_chains();  // sampler arrays + task queue
     if (trav) b += 8 * g->n + 16 * g->n + 4 * g->n + 4 * (g->n + 1) + 4 * g->n;
     if (fen) b += 8 * (g->two_m + 2);
     return b;
@@ -123,7 +151,11 @@ kc_status ensure_workspace(kc_graph *g, int want, bool trav, bool fen, hipStream
                              (long long)per, (long long)budget);
     int slots = (int)std::min<int64_t>(want, fit);
     const size_t n = (size_t)g->n;
-    HIP_TRY(dev_alloc(&g->d_st, (size_t)slots * n));
+    HIP_TRY(dev_alloc(&g->d_tagw, (size_t)slots * n));
+    HIP_TRY(dev_alloc(&g->d_nxt, (size_t)slots * n));
+    HIP_TRY(dev_alloc(&g->d_draws, (size_t)slots * n));
+    HIP_TRY(dev_alloc(&g->d_rq, (size_t)slots * n));
+    HIP_TRY(dev_alloc(&g->d_queue, (size_t)slots * (size_t)kc::sampler_chains()));
     if (trav) {
         HIP_TRY(dev_alloc(&g->d_word, (size_t)slots * n));
         HIP_TRY(dev_alloc(&g->d_rec, (size_t)slots * n));
@@ -147,17 +179,25 @@ kc_status ensure_fbuf(kc_graph *g, int64_t count) {
     if (g->fbuf_len >= count) return KC_OK;
     dev_free(g->d_f);
     dev_free(g->d_steps);
-    g->d_f = g->d_steps = nullptr;
+    dev_free(g->d_iters);
+    g->d_f = g->d_steps = g->d_iters = nullptr;
     g->fbuf_len = 0;
     HIP_TRY(dev_alloc(&g->d_f, (size_t)count));
     HIP_TRY(dev_alloc(&g->d_steps, (size_t)count));
+    HIP_TRY(dev_alloc(&g->d_iters, (size_t)count));
     g->fbuf_len = count;
     return KC_OK;
 }
 
+// One slot per resident single-wave workgroup of the persistent kernel.
 int default_slots(const kc_graph *g) {
     (void)g;
-    return 4096;  // 256 CUs x 16 single-wave workgroups
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1024;
+    per_cu = kc::persistent_blocks_per_cu();
+    if (cus <= 0 || per_cu <= 0) return 1024;
+    return cus * per_cu;
 }
 
 // Launch the persistent kernel over `count` samples and check its status.
@@ -182,7 +222,11 @@ kc_status run_persistent(kc_graph *g, kc::RunParams rp, hipStream_t stream) {
     gd.eoff = g->d_eoff;
     gd.elist = g->d_elist;
     kc::SlotDev sd;
-    sd.st = g->d_st;
+    sd.tagw = g->d_tagw;
+    sd.nxt = g->d_nxt;
+    sd.draws = g->d_draws;
+    sd.rq = g->d_rq;
+    sd.queue = g->d_queue;
     sd.word = g->d_word;
     sd.rec = g->d_rec;
     sd.ordr = g->d_ordr;
@@ -371,6 +415,7 @@ kc_status kc_graph_create(int64_t n, const void *offsets, int offsets_are_i64, c
     g->max_degree = maxdeg;
     g->nblk = nblk;
     g->traversal = depth0 <= 12 ? KC_TRAV_WALK : KC_TRAV_SWEEP;
+    g->bfs_order = order;
     auto up = [&](auto **dst, const auto *src, size_t cnt) -> hipError_t {
         hipError_t e = dev_alloc(dst, cnt);
         if (e != hipSuccess) return e;
@@ -382,7 +427,9 @@ kc_status kc_graph_create(int64_t n, const void *offsets, int offsets_are_i64, c
     if (e == hipSuccess) e = up(&g->d_off, off.data(), off.size());
     if (e == hipSuccess) e = up(&g->d_adj, indices, (size_t)nnz);
     if (e == hipSuccess) e = up(&g->d_p0, p0.data(), p0.size());
-    if (e == hipSuccess) e = up(&g->d_order, order.data(), order.size());
+    const std::vector<int32_t> start_ord = start_order_of(order, 2);
+    g->start_order = 2;
+    if (e == hipSuccess) e = up(&g->d_order, start_ord.data(), start_ord.size());
     if (e == hipSuccess) e = up(&g->d_pre0, pre0.data(), pre0.size());
     if (e == hipSuccess) e = up(&g->d_out0, out0.data(), out0.size());
     if (e == hipSuccess) e = up(&g->d_eoff, eoff.data(), eoff.size());
@@ -444,6 +491,13 @@ kc_status kc_set_option(kc_graph *g, int option, int64_t value) {
             if (value < 0) return fail(KC_ERR_INVALID, "memory budget must be >= 0");
             g->mem_budget = value;
             return KC_OK;
+        case KC_OPT_START_ORDER: {
+            if (value < 0 || value > 2) return fail(KC_ERR_INVALID, "start order must be 0, 1 or 2");
+            const std::vector<int32_t> ord = start_order_of(g->bfs_order, (int)value);
+            HIP_TRY(hipMemcpy(g->d_order, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+            g->start_order = (int32_t)value;
+            return KC_OK;
+        }
     }
     return fail(KC_ERR_INVALID, "unknown option %d", option);
 }
@@ -468,8 +522,8 @@ kc_status kc_sample_trees(kc_graph *g, uint64_t seed, int64_t first_sample, int3
 }
 
 static kc_status finish_reduce(kc_graph *g, int32_t count, const int64_t *f, const int64_t *steps,
-                               kc_result *res, hipStream_t stream) {
-    HIP_TRY(kc::launch_reduce(f, steps, count, g->d_red, stream));
+                               const int64_t *iters, kc_result *res, hipStream_t stream) {
+    HIP_TRY(kc::launch_reduce(f, steps, iters, count, g->d_red, stream));
     kc::ReduceOut ro;
     HIP_TRY(hipMemcpyAsync(&ro, g->d_red, sizeof(ro), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
@@ -481,6 +535,7 @@ static kc_status finish_reduce(kc_graph *g, int32_t count, const int64_t *f, con
     res->sum_f2_hi = ro.sq_hi;
     res->count = count;
     res->total_steps = ro.steps;
+    res->sampler_iterations = ro.iters;
     // kappa = sum f / (2 m count): one correctly rounded conversion, one division
     res->kappa = (double)s1 / (double)(g->two_m * (int64_t)count);
     if (count > 1) {
@@ -500,12 +555,10 @@ kc_status kc_estimate(kc_graph *g, uint64_t seed, int64_t first_sample, int32_t 
     if (count < 1 || first_sample < 0) return fail(KC_ERR_INVALID, "count must be >= 1");
     hipStream_t stream = (hipStream_t)hip_stream;
     int64_t *f = f_out, *steps = steps_out;
-    if (!f || !steps) {
-        kc_status st = ensure_fbuf(g, count);
-        if (st != KC_OK) return st;
-        if (!f) f = g->d_f;
-        if (!steps) steps = g->d_steps;
-    }
+    kc_status st0 = ensure_fbuf(g, count);
+    if (st0 != KC_OK) return st0;
+    if (!f) f = g->d_f;
+    if (!steps) steps = g->d_steps;
     kc::RunParams rp{};
     rp.seed = seed;
     rp.first = first_sample;
@@ -513,9 +566,10 @@ kc_status kc_estimate(kc_graph *g, uint64_t seed, int64_t first_sample, int32_t 
     rp.mode = kc::RUN_ESTIMATE;
     rp.f_out = f;
     rp.steps_out = steps;
+    rp.iters_out = g->d_iters;
     kc_status st = run_persistent(g, rp, stream);
     if (st != KC_OK) return st;
-    return finish_reduce(g, count, f, steps, result, stream);
+    return finish_reduce(g, count, f, steps, g->d_iters, result, stream);
 }
 
 kc_status kc_evaluate_trees(kc_graph *g, const int32_t *parents, int32_t count, int64_t *f_out,

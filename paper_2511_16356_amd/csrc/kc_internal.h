@@ -24,7 +24,11 @@ struct GraphDev {
 
 // Per-slot workspace: one slot = one sample in flight = one wavefront.
 struct SlotDev {
-    uint64_t *st;    // [slots*n] sampler state word per vertex
+    uint32_t *tagw;  // [slots*n] sampler: tag and flag bits per vertex
+    int32_t *nxt;    // [slots*n] sampler: arrow target per vertex
+    uint32_t *draws; // [slots*n] sampler: draws per vertex
+    int32_t *rq;     // [slots*n] sampler: restart queue
+    int4 *queue;     // [slots*chains] sampler: ready tasks
     uint64_t *word;  // [slots*n] pending-children | volume accumulator
     int4 *rec;       // [slots*n] {tin_w, vol, parent, unused}
     int32_t *ordr;   // [slots*n] bottom-up completion order
@@ -49,6 +53,7 @@ struct RunParams {
     uint32_t *cnt_out;         // RUN_SAMPLE  [count*n] (optional)
     int64_t *steps_out;        // [count] (optional)
     int64_t *f_out;            // [count] (RUN_ESTIMATE / RUN_EVALUATE)
+    int64_t *iters_out;        // [count] sampler rounds per sample (optional)
     int32_t *ctl;              // [4]: work counter, error code, error sample, spare
 };
 
@@ -59,7 +64,8 @@ struct ReduceOut {
     uint64_t sq_lo;
     uint64_t sq_hi;
     int64_t steps;
-    int64_t pad[3];
+    int64_t iters;
+    int64_t pad[2];
 };
 
 // Error codes written by kernels into ctl[1] (match kc_status values).
@@ -69,8 +75,10 @@ enum { DEV_OK = 0, DEV_LIMIT = 6, DEV_PROTOCOL = 8, DEV_BADTREE = 9 };
 hipError_t launch_reset_ctl(int32_t *ctl, hipStream_t stream);
 hipError_t launch_persistent(const GraphDev &g, const SlotDev &s, const RunParams &rp, int slots,
                              hipStream_t stream);
-hipError_t launch_reduce(const int64_t *f, const int64_t *steps, int32_t count, ReduceOut *out,
-                         hipStream_t stream);
+hipError_t launch_reduce(const int64_t *f, const int64_t *steps, const int64_t *iters, int32_t count,
+                         ReduceOut *out, hipStream_t stream);
 hipError_t launch_zero_i64(int64_t *p, int64_t len, hipStream_t stream);
+int persistent_blocks_per_cu();  // resident single-wave workgroups per CU
+int sampler_chains();            // chain-table entries per sample
 
 }  // namespace kc

@@ -79,6 +79,20 @@ def test_launch_shape_invariance(kc, oracle_lib, graphs, walkers, slots):
             assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ref_cnt)
 
 
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_start_order_invariance(kc, oracle_lib, graphs, order):
+    """Walk start order changes nothing: trees and draw counts stay bit-exact."""
+    for name in ("grid32", "road3k", "social3k", "torus12"):
+        g = graphs[name]
+        P = oracle_lib.prepare_graph(g)
+        ref_par, ref_cnt, _ = oracle_lib.sample(P, seed=8, s0=40, count=16, threads=8)
+        with kc.Graph.from_graph(g) as G:
+            G.set_option(kc.KC_OPT_START_ORDER, order)
+            par, cnt, _ = G.sample_trees(8, 40, 16)
+            assert np.array_equal(par.cpu().numpy(), ref_par)
+            assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ref_cnt)
+
+
 def test_batch_split_invariance(kc, graphs):
     g = graphs["road3k"]
     with kc.Graph.from_graph(g) as G:
