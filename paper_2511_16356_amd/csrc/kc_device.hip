@@ -103,11 +103,12 @@ __device__ __forceinline__ uint32_t arrow_slot(uint64_t seed, uint64_t s, uint32
     uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t a_lo = 0xD2511F53u * x0, a_hi = __umulhi(0xD2511F53u, x0);
-        const uint32_t b_lo = 0xCD9E8D57u * x2, b_hi = __umulhi(0xCD9E8D57u, x2);
-        const uint32_t y0 = b_hi ^ x1 ^ key0;
-        const uint32_t y2 = a_hi ^ x3 ^ key1;
-        x0 = y0; x1 = b_lo; x2 = y2; x3 = a_lo;
+        // one full 32x32->64 product each (a single v_mad_u64_u32, not mul_lo + mul_hi)
+        const uint64_t a = (uint64_t)0xD2511F53u * x0;
+        const uint64_t b = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t y0 = (uint32_t)(b >> 32) ^ x1 ^ key0;
+        const uint32_t y2 = (uint32_t)(a >> 32) ^ x3 ^ key1;
+        x0 = y0; x1 = (uint32_t)b; x2 = y2; x3 = (uint32_t)a;
         key0 += 0x9E3779B9u;
         key1 += 0xBB67AE85u;
     }
@@ -140,7 +141,7 @@ constexpr uint32_t TW_NEED = 1u << 29;
 // Popped vertices are also offered as optional extra starts (a small LIFO):
 // revealing any free vertex is work the cycle-popping order fixes anyway.
 constexpr int CH = 1024;   // chains per sample
-constexpr int HINTS = 256; // optional restart hints
+constexpr int HINTS = 128; // optional restart hints
 
 enum : int { CS_FREE = 0, CS_ACTIVE = 1, CS_PARKED = 2, CS_QUEUED = 3 };
 enum : int { T_RESUME = 0, T_RETRACE = 1, T_POP = 2 };
@@ -157,7 +158,6 @@ enum : int {
 };
 
 struct SamplerShared {
-    int32_t start[CH];   // chain start vertex
     int32_t block[CH];   // parked: vertex the head's arrow points at
     int16_t up[CH];      // parked: chain owning `block`
     int8_t state[CH];    // CS_*
@@ -173,6 +173,7 @@ struct SamplerWS {
     uint32_t *draws;
     int32_t *rq;   // restart ring (n entries)
     int4 *queue;   // ready tasks (CH entries): {chain, kind, e, stop}
+    int32_t *start; // chain start vertices (CH entries)
 };
 
 // Cooperative cycle popping of one sample by one wavefront.
@@ -187,10 +188,9 @@ struct SamplerWS {
 // `walkers`, of the chain table and of which free vertices are started.
 //
 // Returns the total number of draws, or -1 (error recorded in ctl).
-__device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, uint64_t seed, uint64_t s,
-                               int walkers, int64_t iter_cap, int32_t *ctl, int idx,
-                               int64_t *iters_used) {
-    __shared__ SamplerShared sh;
+__device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerShared &sh,
+                               uint64_t seed, uint64_t s, int walkers, int64_t iter_cap,
+                               int32_t *ctl, int idx, int64_t *iters_used) {
     const int lane = threadIdx.x;
     const int n = g.n, root = g.root;
     uint32_t *__restrict__ tagw = ws.tagw;
@@ -240,7 +240,7 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, uint64_t 
                         tgt = t.z;
                         mode = M_CLAIM;
                     } else if (t.y == T_RETRACE) {
-                        tgt = sh.start[chain];
+                        tgt = aload(&ws.start[chain]);
                         stopv = t.z;
                         mode = M_RETRACE;
                     } else {
@@ -255,7 +255,7 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, uint64_t 
                     if (k < take_r) tgt = aload(&ws.rq[(rq_head + k) % n]);
                     else if (k < take_r + take_s) tgt = g.order[next_start + (k - take_r)];
                     else tgt = sh.hint[hint_top - 1 - (k - take_r - take_s)];
-                    sh.start[chain] = tgt;
+                    astore(&ws.start[chain], tgt);
                     mode = M_PROBE;
                 }
                 if (mode != M_IDLE) sh.state[chain] = CS_ACTIVE;
@@ -359,6 +359,7 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, uint64_t 
                 }
                 __syncthreads();
                 const int nw = __popcll(wm);
+#pragma unroll 1
                 for (int i = 0; i < CH / WAVE; ++i) {
                     const int c = lane + i * WAVE;
                     int kind = -1;
@@ -404,7 +405,7 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, uint64_t 
                 mode = M_WALK;
             } else if (tg == T_TREE) {
                 stopv = tgt;
-                if (haspath) tgt = sh.start[chain];
+                if (haspath) tgt = aload(&ws.start[chain]);
                 mode = M_RETRACE;  // an empty chain retires at once
             } else if (tg == ctag) {
                 // own path: the new arrow closed a loop at tgt; pop it, keep tgt as head
@@ -675,11 +676,18 @@ __device__ int64_t f_walk(const GraphDev &g, const SlotPtrs &sp) {
 // step and is still open; items of the step's own vertices and of subtrees
 // closing inside the step are handled exactly from LDS.  The tree returns
 // to all zeros at the end of the sweep.
-__device__ int64_t f_sweep(const GraphDev &g, const SlotPtrs &sp, int64_t fen_len) {
-    __shared__ Items sh_it[WAVE];
-    __shared__ int32_t sh_out[WAVE];
-    __shared__ Items se_it[WAVE];
-    __shared__ int32_t se_out[WAVE];
+struct SweepShared {
+    Items it[WAVE];
+    int32_t out[WAVE];
+    Items eit[WAVE];
+    int32_t eout[WAVE];
+};
+
+__device__ int64_t f_sweep(const GraphDev &g, const SlotPtrs &sp, int64_t fen_len, SweepShared &ss) {
+    Items *sh_it = ss.it;
+    int32_t *sh_out = ss.out;
+    Items *se_it = ss.eit;
+    int32_t *se_out = ss.eout;
     const int lane = threadIdx.x;
     const int n = g.n;
     int64_t acc = 0;
@@ -744,7 +752,14 @@ __device__ int64_t f_sweep(const GraphDev &g, const SlotPtrs &sp, int64_t fen_le
 
 // ------------------------------------------------------------ the kernels
 
+// The sampler and the sweep run one after the other: one LDS block serves both.
+union KernelShared {
+    SamplerShared samp;
+    SweepShared sweep;
+};
+
 __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd, RunParams rp) {
+    __shared__ KernelShared lds;
     const int lane = threadIdx.x;
     const size_t n = (size_t)g.n;
     SlotPtrs sp;
@@ -753,6 +768,7 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
     sp.ws.draws = sd.draws + (size_t)blockIdx.x * n;
     sp.ws.rq = sd.rq + (size_t)blockIdx.x * n;
     sp.ws.queue = sd.queue + (size_t)blockIdx.x * CH;
+    sp.ws.start = sd.cstart + (size_t)blockIdx.x * CH;
     sp.word = sd.word ? sd.word + (size_t)blockIdx.x * n : nullptr;
     sp.rec = sd.rec ? reinterpret_cast<uint64_t *>(sd.rec) + 2 * (size_t)blockIdx.x * n : nullptr;
     sp.ordr = sd.ordr ? sd.ordr + (size_t)blockIdx.x * n : nullptr;
@@ -769,7 +785,7 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
         const uint64_t s = (uint64_t)(rp.first + idx);
         int64_t steps = 0, iters = 0;
         if (rp.mode != RUN_EVALUATE) {
-            steps = sample_tree(g, sp.ws, rp.seed, s, rp.walkers, rp.iter_cap, rp.ctl, idx, &iters);
+            steps = sample_tree(g, sp.ws, lds.samp, rp.seed, s, rp.walkers, rp.iter_cap, rp.ctl, idx, &iters);
             if (steps < 0) break;
         }
         if (rp.mode == RUN_SAMPLE) {
@@ -797,7 +813,7 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
             bool ok = tree_numbering(g, sp);
             if (__ballot(bad) != 0ull) ok = false;
             int64_t f = 0;
-            if (rp.traversal == 2) f = f_sweep(g, sp, sd.fen_len);
+            if (rp.traversal == 2) f = f_sweep(g, sp, sd.fen_len, lds.sweep);
             else f = f_walk(g, sp);
             if (!ok) report_error(rp.ctl, DEV_BADTREE, idx);
             if (lane == 0) rp.f_out[idx] = f;

@@ -29,6 +29,7 @@ struct SlotDev {
     uint32_t *draws; // [slots*n] sampler: draws per vertex
     int32_t *rq;     // [slots*n] sampler: restart queue
     int4 *queue;     // [slots*chains] sampler: ready tasks
+    int32_t *cstart; // [slots*chains] sampler: chain start vertices
     uint64_t *word;  // [slots*n] pending-children | volume accumulator
     int4 *rec;       // [slots*n] {tin_w, vol, parent, unused}
     int32_t *ordr;   // [slots*n] bottom-up completion order
