@@ -27,6 +27,13 @@ sys.path.insert(0, ROOT)
 METRIC = "spanning-tree samples/s and K at ε=0.01 vs exact; served query p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
 SECTOR = 64
+KERNEL_SRC = os.path.join(ROOT, "paper_2511_16356_amd", "csrc", "kc_device.hip")
+
+# HBM bytes per tree sample of the persistent kernel on this workload, from
+# rocprofv3 FETCH_SIZE + WRITE_SIZE runs (scaled by a plain copy kernel's
+# reading; see profiles/), keyed by the SHA-256 of the kernel source the
+# counters were taken on.  Any other kernel source reports traffic = null.
+MEASURED_TRAFFIC = {}
 
 
 def log(*a):
@@ -53,6 +60,24 @@ def cpu_baseline(g, seed: int, first: int, threads: int, per_thread: int):
                       (first, first + count - 1, per_thread, dt)}
 
 
+def kernel_sha() -> str:
+    import hashlib
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def calibrate_copy(mib: int):
+    """A plain device-to-device copy of known size, for scaling HBM counters."""
+    import torch
+    nbytes = mib << 20
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,7 +88,12 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-per-thread", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(samples shard trivially by index; see DESIGN.md)", file=sys.stderr)
@@ -119,6 +149,8 @@ def main():
     se = math.sqrt(max(var, 0.0) / total) / g.two_m
     alg = algorithmic_bytes(draws, g.n, info["depth0"], total)
     achieved = alg / (gpu_ms / 1e3) / 1e9  # GB/s: algorithmic bytes over the timed launches
+    per_sample_traffic = MEASURED_TRAFFIC.get(kernel_sha())
+    traffic = per_sample_traffic * B if per_sample_traffic else None  # bytes per launch
     out = {
         "metric": METRIC,
         "value": value,
@@ -152,7 +184,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg / args.steps,
         },
     }
     if not args.no_cpu:
