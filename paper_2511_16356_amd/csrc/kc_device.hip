@@ -119,22 +119,32 @@ __device__ __forceinline__ uint32_t arrow_slot(uint64_t seed, uint64_t s, uint32
 
 // ------------------------------------------------------------ sampler state
 //
-// Three arrays per (sample, vertex):
-//   tagw  : bits 0..27 tag (0 = arrow not revealed ("free"), 1 = in the tree,
-//           2 + c = on the path of chain c); bit 28 wait (a parked chain's
-//           arrow points here); bit 29 need (the vertex's turn as a walk
-//           start passed while it was on a path).  A free vertex's word is 0.
-//   nxt   : the vertex's current arrow target (its tree parent at the end)
-//   draws : how many arrows the vertex has drawn
+// Two 8-byte words per (sample, vertex), in two arrays, so that the claim
+// (an atomic on the tag word) and the read of the arrow word go to different
+// cache lines and overlap:
+//   tag word   low half: bits 0..27 tag (0 = arrow not revealed ("free"),
+//              1 = in the tree, 2 + c = on the path of chain c); bit 29 need
+//              (the vertex's turn as a walk start passed while it was on a path)
+//              high half: 1 + the first of the chains parked on this vertex
+//              (their head's arrow points here), 0 if none; the list continues
+//              through the chain table's wnext links
+//   arrow word low half: the current arrow target (the tree parent at the
+//              end); high half: how many arrows the vertex has drawn
+// A free vertex's tag word is 0; a tree vertex's is T_TREE.
 constexpr uint32_t T_FREE = 0, T_TREE = 1, T_CHAIN0 = 2;
+
+__device__ __forceinline__ uint32_t *tag_low(uint64_t *w) { return reinterpret_cast<uint32_t *>(w); }
+__device__ __forceinline__ uint32_t *tag_high(uint64_t *w) { return reinterpret_cast<uint32_t *>(w) + 1; }
+__device__ __forceinline__ uint64_t arrow_of(int32_t nxt, uint32_t drw) {
+    return (uint64_t)(uint32_t)nxt | ((uint64_t)drw << 32);
+}
 constexpr uint32_t TW_TAG = (1u << 28) - 1;
-constexpr uint32_t TW_WAIT = 1u << 28;
 constexpr uint32_t TW_NEED = 1u << 29;
 
 // A chain is a loop-erased path of revealed arrows owned by one walk: from
 // its start vertex to its head.  A lane drives at most one chain at a time.
 // When the head's arrow lands on another chain's path, the chain is parked
-// (the wait bit marks the vertex) and the lane takes other work; the chain is
+// (it joins the vertex's waiter list) and the lane takes other work; the chain is
 // woken when that vertex is popped (resume there) or joins the tree
 // (retrace).  A start vertex that already lies on a path is skipped with its
 // need bit set; if it is popped later its eraser queues it for a restart.
@@ -160,17 +170,16 @@ enum : int {
 struct SamplerShared {
     int32_t block[CH];   // parked: vertex the head's arrow points at
     int16_t up[CH];      // parked: chain owning `block`
+    int16_t wnext[CH];   // parked: next / previous chain parked on the same vertex (-1: none)
+    int16_t wprev[CH];
     int8_t state[CH];    // CS_*
     int16_t freestk[CH]; // free chain ids
     int32_t hint[HINTS];
-    int32_t wake_v[WAVE];
-    int8_t wake_k[WAVE];
 };
 
 struct SamplerWS {
-    uint32_t *tagw;
-    int32_t *nxt;
-    uint32_t *draws;
+    uint64_t *tagw;
+    uint64_t *arrow;
     int32_t *rq;   // restart ring (n entries)
     int4 *queue;   // ready tasks (CH entries): {chain, kind, e, stop}
     int32_t *start; // chain start vertices (CH entries)
@@ -193,13 +202,11 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
                                int32_t *ctl, int idx, int64_t *iters_used) {
     const int lane = threadIdx.x;
     const int n = g.n, root = g.root;
-    uint32_t *__restrict__ tagw = ws.tagw;
-    int32_t *__restrict__ nxt = ws.nxt;
-    uint32_t *__restrict__ drw = ws.draws;
+    uint64_t *__restrict__ tagw = ws.tagw;
+    uint64_t *__restrict__ arw = ws.arrow;
     for (int v = lane; v < n; v += WAVE) {
-        astore(&tagw[v], v == root ? T_TREE : T_FREE);
-        astore(&nxt[v], (int32_t)-1);
-        astore(&drw[v], 0u);
+        astore(&tagw[v], (uint64_t)(v == root ? T_TREE : T_FREE));
+        astore(&arw[v], arrow_of(-1, 0));
     }
     for (int c = lane; c < CH; c += WAVE) {
         sh.state[c] = CS_FREE;
@@ -276,7 +283,7 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
 
         // ---- phase A: one step of each busy lane
         bool stepped = false, retire = false;
-        int wake_kind = -1, wake_vtx = -1, restart_vtx = -1, hint_vtx = -1;
+        int wake_kind = -1, wake_vtx = -1, wake_head = -1, restart_vtx = -1, hint_vtx = -1;
         int rev_v = -1;  // reveal deferred to phase B (only this chain reads it)
         if (err == 0 && mode != M_IDLE) {
             const int chk = (mode == M_WALK) ? cur : tgt;
@@ -292,18 +299,21 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
                 stepped = true;
                 mysteps++;
             } else if (mode == M_ERASE) {
-                const uint32_t old = __hip_atomic_exchange(&tagw[tgt], T_FREE, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                const int32_t nz = aload(&nxt[tgt]);
+                const uint64_t o64 = __hip_atomic_exchange(&tagw[tgt], (uint64_t)T_FREE,
+                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const int32_t nz = (int32_t)(uint32_t)aload(&arw[tgt]);
+                const uint32_t old = (uint32_t)o64;
                 if ((old & TW_TAG) != ctag) err = DEV_PROTOCOL;
-                if (old & TW_WAIT) { wake_kind = T_RESUME; wake_vtx = tgt; }
+                wake_head = (int)(o64 >> 32) - 1;
+                if (wake_head >= 0) { wake_kind = T_RESUME; wake_vtx = tgt; }
                 if (old & TW_NEED) restart_vtx = tgt;
                 else hint_vtx = tgt;
                 if (nz == stopv) mode = M_WALK; else tgt = nz;
             } else if (mode == M_ERASE0) {
-                const uint32_t tw = aload(&tagw[tgt]);
-                const int32_t nz = aload(&nxt[tgt]);
-                dcur = aload(&drw[tgt]);
+                const uint32_t tw = (uint32_t)aload(&tagw[tgt]);
+                const uint64_t ar = aload(&arw[tgt]);
+                const int32_t nz = (int32_t)(uint32_t)ar;
+                dcur = (uint32_t)(ar >> 32);
                 ocur = g.off[tgt];
                 gcur = (uint32_t)(g.off[tgt + 1] - ocur);
                 if ((tw & TW_TAG) != ctag) err = DEV_PROTOCOL;
@@ -314,11 +324,12 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
                 if (tgt == stopv) {
                     retire = true;  // empty chain: nothing to mark
                 } else {
-                    const uint32_t old = __hip_atomic_exchange(&tagw[tgt], T_TREE, __ATOMIC_RELAXED,
-                                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-                    const int32_t nz = aload(&nxt[tgt]);
-                    if ((old & TW_TAG) != ctag) err = DEV_PROTOCOL;
-                    if (old & TW_WAIT) { wake_kind = T_RETRACE; wake_vtx = tgt; }
+                    const uint64_t o64 = __hip_atomic_exchange(&tagw[tgt], (uint64_t)T_TREE,
+                                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    const int32_t nz = (int32_t)(uint32_t)aload(&arw[tgt]);
+                    if (((uint32_t)o64 & TW_TAG) != ctag) err = DEV_PROTOCOL;
+                    wake_head = (int)(o64 >> 32) - 1;
+                    if (wake_head >= 0) { wake_kind = T_RETRACE; wake_vtx = tgt; }
                     if (nz == stopv) retire = true; else tgt = nz;
                 }
             }
@@ -348,52 +359,42 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
         }
         fence_wg();
         __syncthreads();
-        // wake chains parked on vertices that were popped or joined the tree
-        {
-            const uint64_t wm = __ballot(wake_kind >= 0);
-            if (wm != 0ull) {
-                if (wake_kind >= 0) {
-                    const int k = rank_in(wm);
-                    sh.wake_v[k] = wake_vtx;
-                    sh.wake_k[k] = (int8_t)wake_kind;
-                }
-                __syncthreads();
-                const int nw = __popcll(wm);
+        // wake the chains parked on vertices that were popped or joined the tree:
+        // each such lane walks its vertex's waiter list, one chain per pass
+        if ((unsigned)(wake_head + 1) > (unsigned)CH) { err = DEV_PROTOCOL; wake_head = -1; }
 #pragma unroll 1
-                for (int i = 0; i < CH / WAVE; ++i) {
-                    const int c = lane + i * WAVE;
-                    int kind = -1;
-                    if (sh.state[c] == CS_PARKED) {
-                        const int b = sh.block[c];
-                        for (int k = 0; k < nw; ++k)
-                            if (sh.wake_v[k] == b) kind = sh.wake_k[k];
-                    }
-                    const uint64_t pm = __ballot(kind >= 0);
-                    if (kind >= 0) {
-                        ws.queue[(q_tail + rank_in(pm)) & (CH - 1)] = make_int4(c, kind, sh.block[c], 0);
-                        sh.state[c] = CS_QUEUED;
-                    }
-                    q_tail += __popcll(pm);
-                    parked -= __popcll(pm);
-                }
-                __syncthreads();
+        for (int pass = 0;; ++pass) {
+            const uint64_t wm = __ballot(wake_head >= 0);
+            if (wm == 0ull) break;
+            if (pass == CH) {  // longer than the chain table: the lists are broken
+                err = DEV_PROTOCOL;
+                break;
             }
+            if (wake_head >= 0) {
+                const int c = wake_head;
+                if (sh.state[c] != CS_PARKED || sh.block[c] != wake_vtx) err = DEV_PROTOCOL;
+                ws.queue[(q_tail + rank_in(wm)) & (CH - 1)] = make_int4(c, wake_kind, wake_vtx, 0);
+                sh.state[c] = CS_QUEUED;
+                wake_head = sh.wnext[c];
+                if ((unsigned)(wake_head + 1) > (unsigned)CH) { err = DEV_PROTOCOL; wake_head = -1; }
+            }
+            q_tail += __popcll(wm);
+            parked -= __popcll(wm);
         }
 
         // ---- phase B: publish the reveal, look at the target, claim it if free
         const bool looks = err == 0 && (stepped || mode == M_PROBE || mode == M_CLAIM);
         if (looks && (unsigned)tgt >= (unsigned)n) err = DEV_PROTOCOL;
         bool park = false;
-        int park_owner = -1;
-        if (rev_v >= 0 && err == 0) {
-            astore(&nxt[rev_v], tgt);
-            astore(&drw[rev_v], dcur);
-        }
+        int park_owner = -1, park_head = -1;
+        if (rev_v >= 0 && err == 0) astore(&arw[rev_v], arrow_of(tgt, dcur));
         if (err == 0 && looks) {
             const bool haspath = mode != M_PROBE;  // walked or resumed chain
-            const uint32_t old = acas(&tagw[tgt], T_FREE, ctag);
-            const uint32_t dt = aload(&drw[tgt]);
-            const int32_t nt = aload(&nxt[tgt]);
+            const uint64_t o64 = acas(&tagw[tgt], (uint64_t)T_FREE, (uint64_t)ctag);
+            const uint32_t old = (uint32_t)o64;
+            const uint64_t ar = aload(&arw[tgt]);
+            const int32_t nt = (int32_t)(uint32_t)ar;
+            const uint32_t dt = (uint32_t)(ar >> 32);
             const int64_t o_t = g.off[tgt];
             const uint32_t d_t = (uint32_t)(g.off[tgt + 1] - o_t);
             const uint32_t tg = old & TW_TAG;
@@ -421,9 +422,10 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
                 if (haspath) {
                     park = true;
                     park_owner = (int)(tg - T_CHAIN0);
+                    park_head = (int)(o64 >> 32) - 1;
                 } else {
                     // start vertex already on a path: skip it, restart it if it is popped
-                    __hip_atomic_fetch_or(&tagw[tgt], TW_NEED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_or(tag_low(&tagw[tgt]), TW_NEED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     stopv = tgt;
                     mode = M_RETRACE;
                 }
@@ -433,17 +435,23 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
         }
         __syncthreads();
 
-        // ---- parks, one at a time: record, then look for a cycle through the new edge
+        // ---- parks, one at a time: join the vertex's waiter list, then look for a
+        // cycle through the new edge.  The list head comes with the claim attempt;
+        // after an earlier park of the same round it is read again.
         uint64_t pm = __ballot(park);
-        if (park) {
-            __hip_atomic_fetch_or(&tagw[tgt], TW_WAIT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
+        bool reread = false;
         while (pm != 0ull) {
             const int L = __ffsll((unsigned long long)pm) - 1;
             pm &= pm - 1;
             int ncyc = 0;
             if (lane == L) {
                 const int c = chain;
+                int h = reread ? (int)aload(tag_high(&tagw[tgt])) - 1 : park_head;
+                if ((unsigned)(h + 1) > (unsigned)CH) { err = DEV_PROTOCOL; h = -1; }
+                sh.wnext[c] = (int16_t)h;
+                sh.wprev[c] = -1;
+                if (h >= 0) sh.wprev[h] = (int16_t)c;
+                astore(tag_high(&tagw[tgt]), (uint32_t)(c + 1));
                 sh.block[c] = tgt;
                 sh.up[c] = (int16_t)park_owner;
                 sh.state[c] = CS_PARKED;
@@ -451,10 +459,15 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
                 while (x != c && sh.state[x] == CS_PARKED && len < CH) { x = sh.up[x]; ++len; }
                 if (x == c) {
                     // the chains c -> up(c) -> ... -> c form a cycle of arrows: pop all of
-                    // them; each keeps the vertex where its predecessor entered it
+                    // them; each keeps the vertex where its predecessor entered it and
+                    // leaves the waiter list of the vertex it was parked on
                     int prev = c, m;
                     do {
                         m = sh.up[prev];
+                        const int wp = sh.wprev[m], wn = sh.wnext[m];
+                        if (wp >= 0) sh.wnext[wp] = (int16_t)wn;
+                        else astore(tag_high(&tagw[sh.block[m]]), (uint32_t)(wn + 1));
+                        if (wn >= 0) sh.wprev[wn] = (int16_t)wp;
                         ws.queue[(q_tail + ncyc) & (CH - 1)] = make_int4(m, T_POP, sh.block[prev], sh.block[m]);
                         sh.state[m] = CS_QUEUED;
                         ++ncyc;
@@ -467,6 +480,8 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             ncyc = __shfl(ncyc, L);
             parked += 1 - ncyc;
             q_tail += ncyc;
+            reread = true;
+            fence_wg();
             __syncthreads();
         }
         fence_wg();
@@ -764,8 +779,7 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
     const size_t n = (size_t)g.n;
     SlotPtrs sp;
     sp.ws.tagw = sd.tagw + (size_t)blockIdx.x * n;
-    sp.ws.nxt = sd.nxt + (size_t)blockIdx.x * n;
-    sp.ws.draws = sd.draws + (size_t)blockIdx.x * n;
+    sp.ws.arrow = sd.arrow + (size_t)blockIdx.x * n;
     sp.ws.rq = sd.rq + (size_t)blockIdx.x * n;
     sp.ws.queue = sd.queue + (size_t)blockIdx.x * CH;
     sp.ws.start = sd.cstart + (size_t)blockIdx.x * CH;
@@ -792,8 +806,9 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
             int32_t *po = rp.parents_out + (size_t)idx * n;
             uint32_t *co = rp.cnt_out ? rp.cnt_out + (size_t)idx * n : nullptr;
             for (int v = lane; v < g.n; v += WAVE) {
-                po[v] = (v == g.root) ? -1 : aload(&sp.ws.nxt[v]);
-                if (co) co[v] = aload(&sp.ws.draws[v]);
+                const uint64_t ar = aload(&sp.ws.arrow[v]);
+                po[v] = (v == g.root) ? -1 : (int32_t)(uint32_t)ar;
+                if (co) co[v] = (uint32_t)(ar >> 32);
             }
         } else {
             // parents into rec[2v+1]
@@ -804,7 +819,7 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
                     p = -1;
                 } else {
                     p = (rp.mode == RUN_EVALUATE) ? rp.parents_in[(size_t)idx * n + v]
-                                                  : aload(&sp.ws.nxt[v]);
+                                                  : (int32_t)(uint32_t)aload(&sp.ws.arrow[v]);
                     if (p < 0 || p >= g.n || p == v) { bad = true; p = g.root; }
                 }
                 astore(&sp.rec[2 * (size_t)v + 1], (uint64_t)(uint32_t)p);

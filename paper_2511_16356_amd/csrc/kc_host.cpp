@@ -71,8 +71,8 @@ struct kc_graph {
     // workspace
     int ws_slots = 0;
     bool ws_trav = false, ws_fen = false;
-    uint32_t *d_tagw = nullptr, *d_draws = nullptr;
-    int32_t *d_nxt = nullptr, *d_rq = nullptr;
+    uint64_t *d_tagw = nullptr, *d_arrow = nullptr;
+    int32_t *d_rq = nullptr;
     int4 *d_queue = nullptr;
     int32_t *d_cstart = nullptr;
     uint64_t *d_word = nullptr;
@@ -88,10 +88,10 @@ struct kc_graph {
 namespace {
 
 void free_workspace(kc_graph *g) {
-    dev_free(g->d_tagw); dev_free(g->d_nxt); dev_free(g->d_draws); dev_free(g->d_rq);
+    dev_free(g->d_tagw); dev_free(g->d_arrow); dev_free(g->d_rq);
     dev_free(g->d_queue); dev_free(g->d_cstart); dev_free(g->d_word); dev_free(g->d_rec); dev_free(g->d_ordr);
     dev_free(g->d_grp); dev_free(g->d_leaves); dev_free(g->d_fen);
-    g->d_tagw = g->d_draws = nullptr; g->d_nxt = g->d_rq = nullptr; g->d_queue = nullptr;
+    g->d_tagw = g->d_arrow = nullptr; g->d_rq = nullptr; g->d_queue = nullptr;
     g->d_cstart = nullptr;
     g->d_word = nullptr; g->d_rec = nullptr;
     g->d_ordr = g->d_grp = g->d_leaves = nullptr; g->d_fen = nullptr;
@@ -127,7 +127,7 @@ std::vector<int32_t> start_order_of(const std::vector<int32_t> &bfs, int kind) {
 }
 
 int64_t slot_bytes(const kc_graph *g, bool trav, bool fen) {
-    int64_t b = 16 * g->n + 20 * (int64_t)kc::sampler_chains();  // sampler arrays + task queue
+    int64_t b = 20 * g->n + 20 * (int64_t)kc::sampler_chains();  // state records, restart ring, tasks
     if (trav) b += 8 * g->n + 16 * g->n + 4 * g->n + 4 * (g->n + 1) + 4 * g->n;
     if (fen) b += 8 * (g->two_m + 2);
     return b;
@@ -154,8 +154,7 @@ kc_status ensure_workspace(kc_graph *g, int want, bool trav, bool fen, hipStream
     int slots = (int)std::min<int64_t>(want, fit);
     const size_t n = (size_t)g->n;
     HIP_TRY(dev_alloc(&g->d_tagw, (size_t)slots * n));
-    HIP_TRY(dev_alloc(&g->d_nxt, (size_t)slots * n));
-    HIP_TRY(dev_alloc(&g->d_draws, (size_t)slots * n));
+    HIP_TRY(dev_alloc(&g->d_arrow, (size_t)slots * n));
     HIP_TRY(dev_alloc(&g->d_rq, (size_t)slots * n));
     HIP_TRY(dev_alloc(&g->d_queue, (size_t)slots * (size_t)kc::sampler_chains()));
     HIP_TRY(dev_alloc(&g->d_cstart, (size_t)slots * (size_t)kc::sampler_chains()));
@@ -226,8 +225,7 @@ kc_status run_persistent(kc_graph *g, kc::RunParams rp, hipStream_t stream) {
     gd.elist = g->d_elist;
     kc::SlotDev sd;
     sd.tagw = g->d_tagw;
-    sd.nxt = g->d_nxt;
-    sd.draws = g->d_draws;
+    sd.arrow = g->d_arrow;
     sd.rq = g->d_rq;
     sd.queue = g->d_queue;
     sd.cstart = g->d_cstart;

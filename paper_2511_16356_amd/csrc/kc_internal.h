@@ -24,9 +24,8 @@ struct GraphDev {
 
 // Per-slot workspace: one slot = one sample in flight = one wavefront.
 struct SlotDev {
-    uint32_t *tagw;  // [slots*n] sampler: tag and flag bits per vertex
-    int32_t *nxt;    // [slots*n] sampler: arrow target per vertex
-    uint32_t *draws; // [slots*n] sampler: draws per vertex
+    uint64_t *tagw;  // [slots*n] sampler: tag/flag bits | first parked chain + 1 << 32
+    uint64_t *arrow; // [slots*n] sampler: arrow target | draws << 32
     int32_t *rq;     // [slots*n] sampler: restart queue
     int4 *queue;     // [slots*chains] sampler: ready tasks
     int32_t *cstart; // [slots*chains] sampler: chain start vertices
