@@ -110,8 +110,8 @@ def main():
     G = kc.Graph.from_graph(g)
     info = G.info
     stream = torch.cuda.current_stream()
-    # set-up (not a step): allocate the workspace with a tiny batch
-    G.estimate(args.seed, 10 ** 9, 2)
+    # set-up (not a step): allocate the workspace for the batch
+    G.reserve(args.samples)
     torch.cuda.synchronize()
 
     B = args.samples

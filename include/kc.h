@@ -112,6 +112,18 @@ kc_status kc_graph_get_info(const kc_graph *g, kc_graph_info *info);
 kc_status kc_set_option(kc_graph *g, int option, int64_t value);
 
 /*
+ * Allocate, ahead of time, the device workspace that kc_estimate needs for
+ * batches of up to `count` samples (per-sample sampler and traversal state
+ * for the samples in flight, and the per-sample result buffers), so that a
+ * later call allocates nothing.  Calls also allocate on first use when this
+ * is skipped.  The workspace lives until kc_graph_destroy.
+ * Errors: KC_ERR_INVALID (count < 1), KC_ERR_NOMEM (the budget of
+ * KC_OPT_MEM_BUDGET, or 60% of free device memory, cannot hold one sample),
+ * KC_ERR_DEVICE.
+ */
+kc_status kc_reserve(kc_graph *g, int32_t count, void *hip_stream);
+
+/*
  * Draw the uniform spanning trees of samples first_sample ..
  * first_sample+count-1 with Wilson's algorithm (section 2.2), each
  * (sample s, vertex v, k-th draw at v) taking neighbour slot

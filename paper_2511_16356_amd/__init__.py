@@ -25,7 +25,7 @@ KC_OPT_WALKERS, KC_OPT_SLOTS, KC_OPT_TRAVERSAL, KC_OPT_STEP_LIMIT, KC_OPT_MEM_BU
 KC_OPT_START_ORDER = 6
 
 # every symbol include/kc.h declares
-EXPORTS = ("kc_graph_create", "kc_graph_destroy", "kc_graph_get_info", "kc_set_option",
+EXPORTS = ("kc_graph_create", "kc_graph_destroy", "kc_graph_get_info", "kc_set_option", "kc_reserve",
            "kc_sample_trees", "kc_estimate", "kc_evaluate_trees", "kc_status_string",
            "kc_last_error")
 
@@ -71,6 +71,8 @@ def library() -> ctypes.CDLL:
     lib.kc_graph_get_info.argtypes = [p, ctypes.POINTER(_Info)]
     lib.kc_set_option.restype = ctypes.c_int
     lib.kc_set_option.argtypes = [p, ctypes.c_int, i64]
+    lib.kc_reserve.restype = ctypes.c_int
+    lib.kc_reserve.argtypes = [p, i32, p]
     lib.kc_sample_trees.restype = ctypes.c_int
     lib.kc_sample_trees.argtypes = [p, u64, i64, i32, p, p, p, p]
     lib.kc_estimate.restype = ctypes.c_int
@@ -154,6 +156,10 @@ class Graph:
     def set_option(self, option: int, value: int):
         _check(library().kc_set_option(self._h, option, int(value)))
         self.info = self._info()
+
+    def reserve(self, count: int, stream=None):
+        """Allocate the workspace for estimates of up to `count` samples now."""
+        _check(library().kc_reserve(self._h, count, _stream(stream)))
 
     def sample_trees(self, seed: int, first: int, count: int, popcounts: bool = True,
                      steps: bool = True, stream=None):

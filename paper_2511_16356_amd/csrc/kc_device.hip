@@ -118,6 +118,9 @@ __device__ __forceinline__ uint32_t arrow_slot(uint64_t seed, uint64_t s, uint32
 }
 
 // ------------------------------------------------------------ sampler state
+
+// Neighbours kept inline in a vertex's 32-byte graph record (see GraphDev::vrec).
+constexpr int VREC_INLINE = 6;
 //
 // Two 8-byte words per (sample, vertex), in two arrays, so that the claim
 // (an atomic on the tag word) and the read of the arrow word go to different
@@ -130,10 +133,11 @@ __device__ __forceinline__ uint32_t arrow_slot(uint64_t seed, uint64_t s, uint32
 //              through the chain table's wnext links
 //   arrow word low half: the current arrow target (the tree parent at the
 //              end); high half: how many arrows the vertex has drawn
-// A free vertex's tag word is 0; a tree vertex's is T_TREE.
+// A free vertex's tag word is 0; a tree vertex's is T_TREE.  Every change of
+// a tag word is one atomic operation, so claims, parks, need marks, erases
+// and retraces of the same round may meet on a vertex in any order.
 constexpr uint32_t T_FREE = 0, T_TREE = 1, T_CHAIN0 = 2;
 
-__device__ __forceinline__ uint32_t *tag_low(uint64_t *w) { return reinterpret_cast<uint32_t *>(w); }
 __device__ __forceinline__ uint32_t *tag_high(uint64_t *w) { return reinterpret_cast<uint32_t *>(w) + 1; }
 __device__ __forceinline__ uint64_t arrow_of(int32_t nxt, uint32_t drw) {
     return (uint64_t)(uint32_t)nxt | ((uint64_t)drw << 32);
@@ -156,15 +160,18 @@ constexpr int HINTS = 128; // optional restart hints
 enum : int { CS_FREE = 0, CS_ACTIVE = 1, CS_PARKED = 2, CS_QUEUED = 3 };
 enum : int { T_RESUME = 0, T_RETRACE = 1, T_POP = 2 };
 
-// Lane modes.
+// Lane modes.  Each issues exactly one round of memory operations per sampler
+// round, and all lanes' operations are in flight together.
 enum : int {
     M_IDLE = 0,    // no work
-    M_PROBE = 1,   // first look at a fresh chain's start vertex
-    M_CLAIM = 2,   // resume: look at (and claim) the vertex the head points to
-    M_WALK = 3,    // at head `cur` (claimed, arrow not revealed): draw and step
-    M_ERASE0 = 4,  // popping: keep `tgt` as the new head, erase what follows it
-    M_ERASE = 5,   // popping: free `tgt`, follow next until `stopv`
-    M_RETRACE = 6  // path met the tree: mark from `tgt` until `stopv`
+    M_LOOK = 1,    // look at `tgt` and claim it if free (first publishing the head's
+                   // new arrow if one was drawn)
+    M_PARK = 2,    // join the waiter list of `tgt` if its tag word is still `seen`
+    M_NEED = 3,    // set the need bit of start vertex `tgt` if its tag word is still `seen`
+    M_ADJ = 4,     // the drawn neighbour lies beyond the inline ones: fetch it
+    M_ERASE0 = 5,  // popping: load the kept vertex `tgt` (the new head)
+    M_ERASE = 6,   // popping: free `tgt`, follow next until `stopv`
+    M_RETRACE = 7  // path met the tree: mark from `tgt` until `stopv`
 };
 
 struct SamplerShared {
@@ -196,6 +203,11 @@ struct SamplerWS {
 // cycle-popping outcome of the arrow stacks: independent of timing, of
 // `walkers`, of the chain table and of which free vertices are started.
 //
+// A round: idle lanes take work; every busy lane issues its memory operations
+// (one dependent round trip); the results are applied (draws from the head's
+// inline neighbours, wakes, pushes); newly parked chains are checked for a
+// cycle one at a time.
+//
 // Returns the total number of draws, or -1 (error recorded in ctl).
 __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerShared &sh,
                                uint64_t seed, uint64_t s, int walkers, int64_t iter_cap,
@@ -217,13 +229,44 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
 
     const bool worker = lane < walkers;
     int mode = M_IDLE, chain = -1, cur = -1, tgt = -1, stopv = -1;
-    uint32_t ctag = 0, dcur = 0, gcur = 0;
-    int64_t ocur = 0;
+    uint32_t ctag = 0, dcur = 0;
+    bool haspath = false;  // M_LOOK: the chain has a path (not a fresh start)
+    bool pend = false;     // M_LOOK: publish arrow (cur -> tgt, dcur) first
+    uint64_t seen = 0;     // M_PARK / M_NEED: expected tag word
+    int adjpos = 0;        // M_ADJ: CSR position of the drawn neighbour
+    // graph record of the head `cur`: CSR offset, degree, first neighbours (plain scalars,
+    // so that the record stays in registers)
+    int hoff = 0, hdeg = 0, hn0 = -1, hn1 = -1, hn2 = -1, hn3 = -1, hn4 = -1, hn5 = -1;
     // wave-uniform bookkeeping
     int next_start = 0, q_head = 0, q_tail = 0, free_top = CH, parked = 0, hint_top = 0;
     int64_t rq_head = 0, rq_tail = 0;
     int64_t iters = 0, mysteps = 0;
     int err = 0;
+
+    // the head `cur` (its graph record in registers, dcur draws so far) draws its next arrow;
+    // called once per round for the lanes that set `drawing`
+    auto draw = [&]() __attribute__((always_inline)) {
+        const uint32_t deg = (uint32_t)hdeg;
+        const uint32_t j = arrow_slot(seed, s, (uint32_t)cur, dcur, deg);
+        mysteps++;
+        dcur += 1;
+        haspath = true;
+        if (j < (uint32_t)VREC_INLINE) {
+            // select in registers: pairs first, then the pair (an indexed read of the
+            // record would place it in scratch memory)
+            const bool odd = (j & 1u) != 0u;
+            int p01 = odd ? hn1 : hn0;
+            int p23 = odd ? hn3 : hn2;
+            int p45 = odd ? hn5 : hn4;
+            asm volatile("" : "+v"(p01), "+v"(p23), "+v"(p45));
+            tgt = j < 2u ? p01 : (j < 4u ? p23 : p45);
+            pend = true;
+            mode = M_LOOK;
+        } else {
+            adjpos = hoff + (int)j;
+            mode = M_ADJ;
+        }
+    };
 
     while (true) {
         // ---- phase 0: idle lanes take tasks, restarts, fresh starts, then hints
@@ -239,13 +282,15 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             const int take_h = min(min(left, room), hint_top);
             if (worker && mode == M_IDLE) {
                 const int r = rank_in(idle);
+                pend = false;
                 if (r < take_q) {
                     const int4 t = ws.queue[(q_head + r) & (CH - 1)];
                     chain = t.x;
                     ctag = T_CHAIN0 + (uint32_t)chain;
                     if (t.y == T_RESUME) {
                         tgt = t.z;
-                        mode = M_CLAIM;
+                        haspath = true;
+                        mode = M_LOOK;
                     } else if (t.y == T_RETRACE) {
                         tgt = aload(&ws.start[chain]);
                         stopv = t.z;
@@ -263,7 +308,8 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
                     else if (k < take_r + take_s) tgt = g.order[next_start + (k - take_r)];
                     else tgt = sh.hint[hint_top - 1 - (k - take_r - take_s)];
                     astore(&ws.start[chain], tgt);
-                    mode = M_PROBE;
+                    haspath = false;
+                    mode = M_LOOK;
                 }
                 if (mode != M_IDLE) sh.state[chain] = CS_ACTIVE;
             }
@@ -273,68 +319,152 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             hint_top -= take_h;
             free_top -= take_r + take_s + take_h;
         }
-        __syncthreads();
         if (__ballot(mode != M_IDLE) == 0ull) {
             if (next_start < n || q_tail != q_head || parked != 0 || rq_tail != rq_head)
                 err = DEV_PROTOCOL;
             break;
         }
         if (++iters > iter_cap) err = DEV_LIMIT;
+        if (err == 0 && mode != M_IDLE && mode != M_ADJ && (unsigned)tgt >= (unsigned)n) err = DEV_PROTOCOL;
+        if (err == 0 && mode == M_ADJ && (unsigned)adjpos >= (unsigned)g.two_m) err = DEV_PROTOCOL;
+        const int m0 = err == 0 ? mode : M_IDLE;
 
-        // ---- phase A: one step of each busy lane
-        bool stepped = false, retire = false;
-        int wake_kind = -1, wake_vtx = -1, wake_head = -1, restart_vtx = -1, hint_vtx = -1;
-        int rev_v = -1;  // reveal deferred to phase B (only this chain reads it)
-        if (err == 0 && mode != M_IDLE) {
-            const int chk = (mode == M_WALK) ? cur : tgt;
-            if ((unsigned)chk >= (unsigned)n) err = DEV_PROTOCOL;
+        // ---- memory: every lane issues its operations before any result is used
+        const bool do_cas = m0 == M_LOOK || m0 == M_PARK || m0 == M_NEED;
+        const bool do_xchg = m0 == M_ERASE || (m0 == M_RETRACE && tgt != stopv);
+        const bool do_arrow = m0 == M_LOOK || m0 == M_ERASE0 || do_xchg;
+        const bool do_rec = m0 == M_LOOK || m0 == M_ERASE0;
+        if (m0 == M_LOOK && pend) astore(&arw[cur], arrow_of(tgt, dcur));
+        uint64_t o64 = 0;
+        if (do_cas) {
+            const uint64_t expect = m0 == M_LOOK ? (uint64_t)T_FREE : seen;
+            const uint64_t want = m0 == M_LOOK ? (uint64_t)ctag
+                                : m0 == M_PARK ? ((seen & 0xffffffffull) | ((uint64_t)(chain + 1) << 32))
+                                               : (seen | TW_NEED);
+            o64 = acas(&tagw[tgt], expect, want);
         }
-        if (err == 0) {
-            if (mode == M_WALK) {
-                const uint32_t j = arrow_slot(seed, s, (uint32_t)cur, dcur, gcur);
-                const int32_t y = g.adj[ocur + j];
-                rev_v = cur;
-                dcur += 1;
-                tgt = y;
-                stepped = true;
-                mysteps++;
-            } else if (mode == M_ERASE) {
-                const uint64_t o64 = __hip_atomic_exchange(&tagw[tgt], (uint64_t)T_FREE,
-                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                const int32_t nz = (int32_t)(uint32_t)aload(&arw[tgt]);
-                const uint32_t old = (uint32_t)o64;
-                if ((old & TW_TAG) != ctag) err = DEV_PROTOCOL;
-                wake_head = (int)(o64 >> 32) - 1;
-                if (wake_head >= 0) { wake_kind = T_RESUME; wake_vtx = tgt; }
-                if (old & TW_NEED) restart_vtx = tgt;
-                else hint_vtx = tgt;
-                if (nz == stopv) mode = M_WALK; else tgt = nz;
-            } else if (mode == M_ERASE0) {
-                const uint32_t tw = (uint32_t)aload(&tagw[tgt]);
-                const uint64_t ar = aload(&arw[tgt]);
-                const int32_t nz = (int32_t)(uint32_t)ar;
-                dcur = (uint32_t)(ar >> 32);
-                ocur = g.off[tgt];
-                gcur = (uint32_t)(g.off[tgt + 1] - ocur);
-                if ((tw & TW_TAG) != ctag) err = DEV_PROTOCOL;
+        if (do_xchg)
+            o64 = __hip_atomic_exchange(&tagw[tgt], (uint64_t)(m0 == M_ERASE ? T_FREE : T_TREE),
+                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (m0 == M_ERASE0) o64 = aload(&tagw[tgt]);
+        uint64_t ar = 0;
+        if (do_arrow) ar = aload(&arw[tgt]);
+        int4 r0 = make_int4(0, 0, 0, 0), r1 = make_int4(0, 0, 0, 0);
+        if (do_rec) {
+            r0 = g.vrec[2 * (size_t)tgt];
+            r1 = g.vrec[2 * (size_t)tgt + 1];
+        }
+        auto take_record = [&]() __attribute__((always_inline)) {
+            hoff = r0.x; hdeg = r0.y; hn0 = r0.z; hn1 = r0.w;
+            hn2 = r1.x; hn3 = r1.y; hn4 = r1.z; hn5 = r1.w;
+        };
+        int32_t y = -1;
+        if (m0 == M_ADJ) y = g.adj[adjpos];
+
+        // ---- apply the results
+        bool retire = false, park = false, drawing = false;
+        int park_head = -1;
+        int wake_kind = -1, wake_vtx = -1, wake_head = -1, restart_vtx = -1, hint_vtx = -1;
+        const uint32_t old = (uint32_t)o64;
+        const uint32_t tg = old & TW_TAG;
+        const int32_t nt = (int32_t)(uint32_t)ar;
+        const uint32_t dt = (uint32_t)(ar >> 32);
+        if (m0 == M_LOOK) {
+            const bool drew = pend;  // the arrow into tgt was just published
+            pend = false;
+            if (old == T_FREE) {
+                // claimed: the new head draws at once
                 cur = tgt;
-                if (nz == stopv) mode = M_WALK;
-                else { mode = M_ERASE; tgt = nz; }
-            } else if (mode == M_RETRACE) {
-                if (tgt == stopv) {
-                    retire = true;  // empty chain: nothing to mark
+                dcur = dt;
+                take_record();
+                drawing = true;
+            } else if (tg == T_TREE) {
+                if (haspath) {
+                    stopv = tgt;
+                    tgt = aload(&ws.start[chain]);
+                    mode = M_RETRACE;
                 } else {
-                    const uint64_t o64 = __hip_atomic_exchange(&tagw[tgt], (uint64_t)T_TREE,
-                                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    const int32_t nz = (int32_t)(uint32_t)aload(&arw[tgt]);
-                    if (((uint32_t)o64 & TW_TAG) != ctag) err = DEV_PROTOCOL;
-                    wake_head = (int)(o64 >> 32) - 1;
-                    if (wake_head >= 0) { wake_kind = T_RETRACE; wake_vtx = tgt; }
-                    if (nz == stopv) retire = true; else tgt = nz;
+                    retire = true;  // a fresh chain whose start is already in the tree
                 }
+            } else if (tg == ctag) {
+                // own path: the new arrow closed a loop at tgt; pop it, keep tgt as head
+                if (!drew) err = DEV_PROTOCOL;
+                cur = tgt;
+                dcur = dt;
+                take_record();
+                stopv = tgt;
+                tgt = nt;
+                mode = M_ERASE;
+            } else if (tg >= T_CHAIN0 && tg < T_CHAIN0 + CH) {
+                seen = o64;
+                mode = haspath ? M_PARK : M_NEED;
+            } else {
+                err = DEV_PROTOCOL;
+            }
+        } else if (m0 == M_PARK || m0 == M_NEED) {
+            if (o64 == seen) {
+                if (m0 == M_PARK) {
+                    park = true;  // joined the list; recorded below
+                    park_head = (int)(seen >> 32) - 1;
+                } else {
+                    retire = true;  // need mark set: the fresh chain has nothing to retrace
+                }
+            } else if (o64 == (uint64_t)T_FREE) {
+                mode = M_LOOK;  // popped meanwhile: look again
+            } else if (tg == T_TREE) {
+                if (m0 == M_PARK) {
+                    stopv = tgt;
+                    tgt = aload(&ws.start[chain]);
+                    mode = M_RETRACE;
+                } else {
+                    retire = true;
+                }
+            } else if (tg >= T_CHAIN0 && tg < T_CHAIN0 + CH && tg != ctag) {
+                seen = o64;  // another park or a new owner: try again
+            } else {
+                err = DEV_PROTOCOL;
+            }
+        } else if (m0 == M_ADJ) {
+            tgt = y;
+            pend = true;
+            mode = M_LOOK;
+        } else if (m0 == M_ERASE) {
+            if (tg != ctag) err = DEV_PROTOCOL;
+            wake_head = (int)(o64 >> 32) - 1;
+            if (wake_head >= 0) { wake_kind = T_RESUME; wake_vtx = tgt; }
+            if (old & TW_NEED) restart_vtx = tgt;
+            else hint_vtx = tgt;
+            if (nt == stopv) drawing = true; else tgt = nt;
+        } else if (m0 == M_ERASE0) {
+            if (tg != ctag) err = DEV_PROTOCOL;
+            cur = tgt;
+            dcur = dt;
+            take_record();
+            if (nt == stopv) drawing = true;
+            else { mode = M_ERASE; tgt = nt; }
+        } else if (m0 == M_RETRACE) {
+            if (tgt == stopv) {
+                retire = true;  // empty chain: nothing to mark
+            } else {
+                if (tg != ctag) err = DEV_PROTOCOL;
+                wake_head = (int)(o64 >> 32) - 1;
+                if (wake_head >= 0) { wake_kind = T_RETRACE; wake_vtx = tgt; }
+                if (nt == stopv) retire = true; else tgt = nt;
             }
         }
-        // popped vertices: need-restarts to the queue, the rest offered as hints
+        if (drawing) draw();
+        // new parks join their vertex's list before any wake walks a list
+        if (park) {
+            int h = park_head;
+            if ((unsigned)(h + 1) > (unsigned)CH) { err = DEV_PROTOCOL; h = -1; }
+            sh.wnext[chain] = (int16_t)h;
+            sh.wprev[chain] = -1;
+            if (h >= 0) sh.wprev[h] = (int16_t)chain;
+            sh.block[chain] = tgt;
+            sh.up[chain] = (int16_t)(tg - T_CHAIN0);
+            sh.state[chain] = CS_PARKED;
+        }
+        // popped vertices: need-restarts to the restart ring, the rest offered as hints
         {
             const uint64_t qm = __ballot(restart_vtx >= 0);
             if (restart_vtx >= 0) astore(&ws.rq[(rq_tail + rank_in(qm)) % n], (int32_t)restart_vtx);
@@ -357,10 +487,11 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             }
             free_top += __popcll(rm);
         }
-        fence_wg();
+        const uint64_t pm0 = __ballot(park);
+        parked += __popcll(pm0);
         __syncthreads();
         // wake the chains parked on vertices that were popped or joined the tree:
-        // each such lane walks its vertex's waiter list, one chain per pass
+        // each such lane walks the list its atomic detached, one chain per pass
         if ((unsigned)(wake_head + 1) > (unsigned)CH) { err = DEV_PROTOCOL; wake_head = -1; }
 #pragma unroll 1
         for (int pass = 0;; ++pass) {
@@ -381,107 +512,44 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             q_tail += __popcll(wm);
             parked -= __popcll(wm);
         }
-
-        // ---- phase B: publish the reveal, look at the target, claim it if free
-        const bool looks = err == 0 && (stepped || mode == M_PROBE || mode == M_CLAIM);
-        if (looks && (unsigned)tgt >= (unsigned)n) err = DEV_PROTOCOL;
-        bool park = false;
-        int park_owner = -1, park_head = -1;
-        if (rev_v >= 0 && err == 0) astore(&arw[rev_v], arrow_of(tgt, dcur));
-        if (err == 0 && looks) {
-            const bool haspath = mode != M_PROBE;  // walked or resumed chain
-            const uint64_t o64 = acas(&tagw[tgt], (uint64_t)T_FREE, (uint64_t)ctag);
-            const uint32_t old = (uint32_t)o64;
-            const uint64_t ar = aload(&arw[tgt]);
-            const int32_t nt = (int32_t)(uint32_t)ar;
-            const uint32_t dt = (uint32_t)(ar >> 32);
-            const int64_t o_t = g.off[tgt];
-            const uint32_t d_t = (uint32_t)(g.off[tgt + 1] - o_t);
-            const uint32_t tg = old & TW_TAG;
-            if (old == T_FREE) {
-                cur = tgt;
-                dcur = dt;
-                ocur = o_t;
-                gcur = d_t;
-                mode = M_WALK;
-            } else if (tg == T_TREE) {
-                stopv = tgt;
-                if (haspath) tgt = aload(&ws.start[chain]);
-                mode = M_RETRACE;  // an empty chain retires at once
-            } else if (tg == ctag) {
-                // own path: the new arrow closed a loop at tgt; pop it, keep tgt as head
-                if (!stepped) err = DEV_PROTOCOL;
-                cur = tgt;
-                dcur = dt;
-                ocur = o_t;
-                gcur = d_t;
-                stopv = tgt;
-                tgt = nt;
-                mode = M_ERASE;
-            } else if (tg >= T_CHAIN0 && tg < T_CHAIN0 + CH) {
-                if (haspath) {
-                    park = true;
-                    park_owner = (int)(tg - T_CHAIN0);
-                    park_head = (int)(o64 >> 32) - 1;
-                } else {
-                    // start vertex already on a path: skip it, restart it if it is popped
-                    __hip_atomic_fetch_or(tag_low(&tagw[tgt]), TW_NEED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    stopv = tgt;
-                    mode = M_RETRACE;
-                }
-            } else {
-                err = DEV_PROTOCOL;
-            }
-        }
         __syncthreads();
 
-        // ---- parks, one at a time: join the vertex's waiter list, then look for a
-        // cycle through the new edge.  The list head comes with the claim attempt;
-        // after an earlier park of the same round it is read again.
-        uint64_t pm = __ballot(park);
-        bool reread = false;
+        // ---- new parks, one at a time: look for a cycle of parked chains through
+        // the new edge (a chain woken above is no longer parked)
+        uint64_t pm = pm0;
         while (pm != 0ull) {
             const int L = __ffsll((unsigned long long)pm) - 1;
             pm &= pm - 1;
             int ncyc = 0;
             if (lane == L) {
                 const int c = chain;
-                int h = reread ? (int)aload(tag_high(&tagw[tgt])) - 1 : park_head;
-                if ((unsigned)(h + 1) > (unsigned)CH) { err = DEV_PROTOCOL; h = -1; }
-                sh.wnext[c] = (int16_t)h;
-                sh.wprev[c] = -1;
-                if (h >= 0) sh.wprev[h] = (int16_t)c;
-                astore(tag_high(&tagw[tgt]), (uint32_t)(c + 1));
-                sh.block[c] = tgt;
-                sh.up[c] = (int16_t)park_owner;
-                sh.state[c] = CS_PARKED;
-                int x = park_owner, len = 0;
-                while (x != c && sh.state[x] == CS_PARKED && len < CH) { x = sh.up[x]; ++len; }
-                if (x == c) {
-                    // the chains c -> up(c) -> ... -> c form a cycle of arrows: pop all of
-                    // them; each keeps the vertex where its predecessor entered it and
-                    // leaves the waiter list of the vertex it was parked on
-                    int prev = c, m;
-                    do {
-                        m = sh.up[prev];
-                        const int wp = sh.wprev[m], wn = sh.wnext[m];
-                        if (wp >= 0) sh.wnext[wp] = (int16_t)wn;
-                        else astore(tag_high(&tagw[sh.block[m]]), (uint32_t)(wn + 1));
-                        if (wn >= 0) sh.wprev[wn] = (int16_t)wp;
-                        ws.queue[(q_tail + ncyc) & (CH - 1)] = make_int4(m, T_POP, sh.block[prev], sh.block[m]);
-                        sh.state[m] = CS_QUEUED;
-                        ++ncyc;
-                        prev = m;
-                    } while (m != c && ncyc <= CH);
+                if (sh.state[c] == CS_PARKED) {
+                    int x = sh.up[c], len = 0;
+                    while (x != c && sh.state[x] == CS_PARKED && len < CH) { x = sh.up[x]; ++len; }
+                    if (x == c) {
+                        // the chains c -> up(c) -> ... -> c form a cycle of arrows: pop all
+                        // of them; each keeps the vertex where its predecessor entered it
+                        // and leaves the waiter list of the vertex it was parked on
+                        int prev = c, m;
+                        do {
+                            m = sh.up[prev];
+                            const int wp = sh.wprev[m], wn = sh.wnext[m];
+                            if (wp >= 0) sh.wnext[wp] = (int16_t)wn;
+                            else astore(tag_high(&tagw[sh.block[m]]), (uint32_t)(wn + 1));
+                            if (wn >= 0) sh.wprev[wn] = (int16_t)wp;
+                            ws.queue[(q_tail + ncyc) & (CH - 1)] = make_int4(m, T_POP, sh.block[prev], sh.block[m]);
+                            sh.state[m] = CS_QUEUED;
+                            ++ncyc;
+                            prev = m;
+                        } while (m != c && ncyc <= CH);
+                    }
                 }
                 mode = M_IDLE;
                 chain = -1;
             }
             ncyc = __shfl(ncyc, L);
-            parked += 1 - ncyc;
+            parked -= ncyc;
             q_tail += ncyc;
-            reread = true;
-            fence_wg();
             __syncthreads();
         }
         fence_wg();

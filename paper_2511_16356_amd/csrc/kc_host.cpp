@@ -68,6 +68,7 @@ struct kc_graph {
     int64_t *d_off = nullptr;
     int32_t *d_adj = nullptr, *d_p0 = nullptr, *d_order = nullptr, *d_pre0 = nullptr;
     int32_t *d_out0 = nullptr, *d_eoff = nullptr, *d_elist = nullptr;
+    int4 *d_vrec = nullptr;
     // workspace
     int ws_slots = 0;
     bool ws_trav = false, ws_fen = false;
@@ -100,6 +101,7 @@ void free_workspace(kc_graph *g) {
 
 void free_all(kc_graph *g) {
     free_workspace(g);
+    dev_free(g->d_vrec);
     dev_free(g->d_off); dev_free(g->d_adj); dev_free(g->d_p0); dev_free(g->d_order);
     dev_free(g->d_pre0); dev_free(g->d_out0); dev_free(g->d_eoff); dev_free(g->d_elist);
     dev_free(g->d_f); dev_free(g->d_steps); dev_free(g->d_iters); dev_free(g->d_ctl); dev_free(g->d_red);
@@ -223,6 +225,7 @@ kc_status run_persistent(kc_graph *g, kc::RunParams rp, hipStream_t stream) {
     gd.out0 = g->d_out0;
     gd.eoff = g->d_eoff;
     gd.elist = g->d_elist;
+    gd.vrec = g->d_vrec;
     kc::SlotDev sd;
     sd.tagw = g->d_tagw;
     sd.arrow = g->d_arrow;
@@ -408,6 +411,16 @@ kc_status kc_graph_create(int64_t n, const void *offsets, int offsets_are_i64, c
         }
     }
 
+    // per-vertex graph record for the sampler: offset, degree, first six neighbours
+    std::vector<int32_t> vrec((size_t)n * 8, -1);
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t a = off[(size_t)v], b = off[(size_t)v + 1];
+        int32_t *r = &vrec[(size_t)v * 8];
+        r[0] = (int32_t)a;
+        r[1] = (int32_t)(b - a);
+        for (int64_t k = 0; k < 6 && a + k < b; ++k) r[2 + k] = indices[a + k];
+    }
+
     kc_graph *g = new (std::nothrow) kc_graph();
     if (!g) return fail(KC_ERR_NOMEM, "host allocation failed");
     g->n = n;
@@ -436,6 +449,7 @@ kc_status kc_graph_create(int64_t n, const void *offsets, int offsets_are_i64, c
     if (e == hipSuccess) e = up(&g->d_out0, out0.data(), out0.size());
     if (e == hipSuccess) e = up(&g->d_eoff, eoff.data(), eoff.size());
     if (e == hipSuccess) e = up(&g->d_elist, elist.data(), elist.size());
+    if (e == hipSuccess) e = up(&g->d_vrec, reinterpret_cast<const int4 *>(vrec.data()), (size_t)n * 2);
     if (e == hipSuccess) e = dev_alloc(&g->d_ctl, 4);
     if (e == hipSuccess) e = dev_alloc(&g->d_red, 1);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -502,6 +516,21 @@ kc_status kc_set_option(kc_graph *g, int option, int64_t value) {
         }
     }
     return fail(KC_ERR_INVALID, "unknown option %d", option);
+}
+
+kc_status kc_reserve(kc_graph *g, int32_t count, void *hip_stream) {
+    g_last_error.clear();
+    if (!g) return fail(KC_ERR_INVALID, "NULL graph");
+    if (count < 1) return fail(KC_ERR_INVALID, "count must be >= 1");
+    int want = g->slots_opt > 0 ? g->slots_opt : default_slots(g);
+    want = std::min(want, count);
+    int slots = 0;
+    kc_status st = ensure_workspace(g, want, true, g->traversal == KC_TRAV_SWEEP, (hipStream_t)hip_stream, &slots);
+    if (st != KC_OK) return st;
+    st = ensure_fbuf(g, count);
+    if (st != KC_OK) return st;
+    HIP_TRY(hipStreamSynchronize((hipStream_t)hip_stream));
+    return KC_OK;
 }
 
 kc_status kc_sample_trees(kc_graph *g, uint64_t seed, int64_t first_sample, int32_t count,

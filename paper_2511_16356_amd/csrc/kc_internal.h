@@ -20,6 +20,8 @@ struct GraphDev {
     const int32_t *out0;  // [n]   last tau0 preorder position inside Sub(tau0, v)
     const int32_t *eoff;  // [nblk+1] per 64-position block: vertices whose tau0
     const int32_t *elist; //          subtree started before the block and ends in it
+    const int4 *vrec;     // [2n]  32-byte record per vertex: {offset, degree, first six
+                          //       neighbours (-1 past the degree)}
 };
 
 // Per-slot workspace: one slot = one sample in flight = one wavefront.

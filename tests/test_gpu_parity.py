@@ -159,6 +159,19 @@ def test_grid32_full_config(kc, oracle_lib, gen):
     assert abs(est.kappa - Kx) < 4.5 * est.std_error
 
 
+def test_reserve_then_estimate(kc, oracle_lib, graphs):
+    """Workspace reserved ahead of time gives the same results."""
+    g = graphs["road3k"]
+    P = oracle_lib.prepare_graph(g)
+    ref_f, _ = oracle_lib.estimate_f(P, seed=5, s0=0, count=16, threads=8)
+    with kc.Graph.from_graph(g) as G:
+        G.reserve(16)
+        est, f, _ = G.estimate(5, 0, 16, per_sample=True)
+        assert np.array_equal(f.cpu().numpy(), ref_f)
+        with pytest.raises(kc.KcError):
+            G.reserve(0)
+
+
 def test_step_limit_reports_error(kc, graphs):
     g = graphs["grid32"]
     with kc.Graph.from_graph(g) as G:
