@@ -126,6 +126,17 @@ def main():
     ests = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
+    # progress of the long batch, read from the counters the kernel publishes
+    import threading
+    stop = threading.Event()
+
+    def watch():
+        t_w = time.perf_counter()
+        while not stop.wait(20.0):
+            log("  %.0f s: %d of %d samples of the step finished" % (time.perf_counter() - t_w, G.progress(), B))
+
+    watcher = threading.Thread(target=watch, daemon=True)
+    watcher.start()
     ev0.record(stream)
     for k in range(args.steps):
         est = G.estimate(args.seed, k * B, B)
@@ -136,6 +147,7 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    stop.set()
     gpu_ms = ev0.elapsed_time(ev1)
 
     total = B * args.steps

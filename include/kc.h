@@ -79,9 +79,12 @@ enum {
     KC_OPT_TRAVERSAL = 3,  /* KC_TRAV_* */
     KC_OPT_STEP_LIMIT = 4, /* per-sample cap on sampler rounds (0 = default 1024 n + 2^22) */
     KC_OPT_MEM_BUDGET = 5, /* bytes of device workspace the library may allocate (0 = 60% of free) */
-    KC_OPT_START_ORDER = 6 /* order in which walks are started (results do not depend on it):
+    KC_OPT_START_ORDER = 6, /* order in which walks are started (results do not depend on it):
                               0 = BFS order from the root, 1 = reverse BFS order,
                               2 = a fixed pseudo-random permutation (default) */
+    KC_OPT_CHAINS = 7      /* walks one sample may hold open at once: 1024 (default) or 2048.
+                              More finish one sample in fewer rounds; fewer let more samples
+                              run at once.  Results do not depend on it. */
 };
 
 /*
@@ -182,6 +185,18 @@ kc_status kc_estimate(kc_graph *g, uint64_t seed, int64_t first_sample, int32_t 
  */
 kc_status kc_evaluate_trees(kc_graph *g, const int32_t *parents, int32_t count, int64_t *f_out,
                             void *hip_stream);
+
+/*
+ * Samples finished so far by the sampling call running (or last run) on g:
+ * each workgroup of the persistent kernel publishes its count to pinned host
+ * memory after every sample.  Unlike every other call, this one may be made
+ * from another host thread while kc_sample_trees / kc_estimate /
+ * kc_evaluate_trees is running on the same graph; it reads host memory only
+ * and never blocks on the device.
+ *   samples_done : HOST pointer, receives the count
+ * Errors: KC_ERR_INVALID (NULL argument).
+ */
+kc_status kc_progress(const kc_graph *g, int64_t *samples_done);
 
 /* Static description of a status code. */
 const char *kc_status_string(kc_status s);

@@ -23,9 +23,10 @@ STATUS = {0: "KC_OK", 1: "KC_ERR_INVALID", 2: "KC_ERR_DISCONNECTED", 3: "KC_ERR_
 KC_TRAV_AUTO, KC_TRAV_WALK, KC_TRAV_SWEEP = 0, 1, 2
 KC_OPT_WALKERS, KC_OPT_SLOTS, KC_OPT_TRAVERSAL, KC_OPT_STEP_LIMIT, KC_OPT_MEM_BUDGET = 1, 2, 3, 4, 5
 KC_OPT_START_ORDER = 6
+KC_OPT_CHAINS = 7
 
 # every symbol include/kc.h declares
-EXPORTS = ("kc_graph_create", "kc_graph_destroy", "kc_graph_get_info", "kc_set_option", "kc_reserve",
+EXPORTS = ("kc_graph_create", "kc_graph_destroy", "kc_graph_get_info", "kc_set_option", "kc_reserve", "kc_progress",
            "kc_sample_trees", "kc_estimate", "kc_evaluate_trees", "kc_status_string",
            "kc_last_error")
 
@@ -71,6 +72,8 @@ def library() -> ctypes.CDLL:
     lib.kc_graph_get_info.argtypes = [p, ctypes.POINTER(_Info)]
     lib.kc_set_option.restype = ctypes.c_int
     lib.kc_set_option.argtypes = [p, ctypes.c_int, i64]
+    lib.kc_progress.restype = ctypes.c_int
+    lib.kc_progress.argtypes = [p, ctypes.POINTER(i64)]
     lib.kc_reserve.restype = ctypes.c_int
     lib.kc_reserve.argtypes = [p, i32, p]
     lib.kc_sample_trees.restype = ctypes.c_int
@@ -156,6 +159,13 @@ class Graph:
     def set_option(self, option: int, value: int):
         _check(library().kc_set_option(self._h, option, int(value)))
         self.info = self._info()
+
+    def progress(self) -> int:
+        """Samples finished so far by the running (or last) sampling call; safe to
+        call from another thread while that call runs."""
+        out = ctypes.c_int64(0)
+        _check(library().kc_progress(self._h, ctypes.byref(out)))
+        return out.value
 
     def reserve(self, count: int, stream=None):
         """Allocate the workspace for estimates of up to `count` samples now."""

@@ -154,7 +154,11 @@ constexpr uint32_t TW_NEED = 1u << 29;
 // need bit set; if it is popped later its eraser queues it for a restart.
 // Popped vertices are also offered as optional extra starts (a small LIFO):
 // revealing any free vertex is work the cycle-popping order fixes anyway.
-constexpr int CH = 1024;   // chains per sample
+// Chain-table sizes the kernel is built for (chains per sample).  More chains
+// let more walks proceed at once in one sample (fewer rounds per sample);
+// fewer chains let more samples share a CU (more samples in flight).
+#define KC_CHAIN_VARIANTS(X) X(1024) X(2048)
+constexpr int MAX_CHAINS = 2048;
 constexpr int HINTS = 128; // optional restart hints
 
 enum : int { CS_FREE = 0, CS_ACTIVE = 1, CS_PARKED = 2, CS_QUEUED = 3 };
@@ -174,6 +178,7 @@ enum : int {
     M_RETRACE = 7  // path met the tree: mark from `tgt` until `stopv`
 };
 
+template <int CH>
 struct SamplerShared {
     int32_t block[CH];   // parked: vertex the head's arrow points at
     int16_t up[CH];      // parked: chain owning `block`
@@ -209,7 +214,8 @@ struct SamplerWS {
 // cycle one at a time.
 //
 // Returns the total number of draws, or -1 (error recorded in ctl).
-__device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerShared &sh,
+template <int CH>
+__device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerShared<CH> &sh,
                                uint64_t seed, uint64_t s, int walkers, int64_t iter_cap,
                                int32_t *ctl, int idx, int64_t *iters_used) {
     const int lane = threadIdx.x;
@@ -836,27 +842,30 @@ __device__ int64_t f_sweep(const GraphDev &g, const SlotPtrs &sp, int64_t fen_le
 // ------------------------------------------------------------ the kernels
 
 // The sampler and the sweep run one after the other: one LDS block serves both.
+template <int CH>
 union KernelShared {
-    SamplerShared samp;
+    SamplerShared<CH> samp;
     SweepShared sweep;
 };
 
+template <int CH>
 __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd, RunParams rp) {
-    __shared__ KernelShared lds;
+    __shared__ KernelShared<CH> lds;
     const int lane = threadIdx.x;
     const size_t n = (size_t)g.n;
     SlotPtrs sp;
     sp.ws.tagw = sd.tagw + (size_t)blockIdx.x * n;
     sp.ws.arrow = sd.arrow + (size_t)blockIdx.x * n;
     sp.ws.rq = sd.rq + (size_t)blockIdx.x * n;
-    sp.ws.queue = sd.queue + (size_t)blockIdx.x * CH;
-    sp.ws.start = sd.cstart + (size_t)blockIdx.x * CH;
+    sp.ws.queue = sd.queue + (size_t)blockIdx.x * (size_t)sd.chains;
+    sp.ws.start = sd.cstart + (size_t)blockIdx.x * (size_t)sd.chains;
     sp.word = sd.word ? sd.word + (size_t)blockIdx.x * n : nullptr;
     sp.rec = sd.rec ? reinterpret_cast<uint64_t *>(sd.rec) + 2 * (size_t)blockIdx.x * n : nullptr;
     sp.ordr = sd.ordr ? sd.ordr + (size_t)blockIdx.x * n : nullptr;
     sp.grp = sd.grp ? sd.grp + (size_t)blockIdx.x * (n + 1) : nullptr;
     sp.leaves = sd.leaves ? sd.leaves + (size_t)blockIdx.x * n : nullptr;
     sp.fen = sd.fen ? sd.fen + (size_t)blockIdx.x * (size_t)sd.fen_len : nullptr;
+    int64_t done = 0;
 
     while (true) {
         int idx = 0;
@@ -867,7 +876,7 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
         const uint64_t s = (uint64_t)(rp.first + idx);
         int64_t steps = 0, iters = 0;
         if (rp.mode != RUN_EVALUATE) {
-            steps = sample_tree(g, sp.ws, lds.samp, rp.seed, s, rp.walkers, rp.iter_cap, rp.ctl, idx, &iters);
+            steps = sample_tree<CH>(g, sp.ws, lds.samp, rp.seed, s, rp.walkers, rp.iter_cap, rp.ctl, idx, &iters);
             if (steps < 0) break;
         }
         if (rp.mode == RUN_SAMPLE) {
@@ -903,6 +912,10 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
         }
         if (rp.steps_out && lane == 0) rp.steps_out[idx] = steps;
         if (rp.iters_out && lane == 0) rp.iters_out[idx] = iters;
+        // samples finished by this workgroup, for a host that watches a long batch
+        ++done;
+        if (rp.progress && lane == 0)
+            __hip_atomic_store(&rp.progress[blockIdx.x], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -964,19 +977,39 @@ hipError_t launch_reset_ctl(int32_t *ctl, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_persistent(const GraphDev &g, const SlotDev &s, const RunParams &rp, int slots,
-                             hipStream_t stream) {
-    hipLaunchKernelGGL(persistent_kernel, dim3(slots), dim3(WAVE), 0, stream, g, s, rp);
-    return hipGetLastError();
+bool valid_chains(int chains) {
+#define KC_CASE(C) if (chains == C) return true;
+    KC_CHAIN_VARIANTS(KC_CASE)
+#undef KC_CASE
+    return false;
 }
 
-int sampler_chains() { return CH; }
+hipError_t launch_persistent(const GraphDev &g, const SlotDev &s, const RunParams &rp, int chains,
+                             int slots, hipStream_t stream) {
+#define KC_CASE(C)                                                                              \
+    if (chains == C) {                                                                         \
+        hipLaunchKernelGGL(persistent_kernel<C>, dim3(slots), dim3(WAVE), 0, stream, g, s, rp); \
+        return hipGetLastError();                                                              \
+    }
+    KC_CHAIN_VARIANTS(KC_CASE)
+#undef KC_CASE
+    return hipErrorInvalidValue;
+}
 
-int persistent_blocks_per_cu() {
+int sampler_chains() { return MAX_CHAINS; }
+
+int persistent_blocks_per_cu(int chains) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, persistent_kernel, WAVE, 0) != hipSuccess)
-        return 0;
-    return blocks;
+#define KC_CASE(C)                                                                                   \
+    if (chains == C) {                                                                              \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, persistent_kernel<C>, WAVE, 0) !=   \
+            hipSuccess)                                                                             \
+            return 0;                                                                               \
+        return blocks;                                                                              \
+    }
+    KC_CHAIN_VARIANTS(KC_CASE)
+#undef KC_CASE
+    return 0;
 }
 
 hipError_t launch_reduce(const int64_t *f, const int64_t *steps, const int64_t *iters, int32_t count,

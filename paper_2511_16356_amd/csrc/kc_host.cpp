@@ -56,6 +56,7 @@ struct kc_graph {
     int32_t root = -1, depth0 = 0, max_degree = 0;
     int32_t traversal = KC_TRAV_WALK;
     int32_t walkers = 64;
+    int32_t chains = 1024;
     int32_t slots_opt = 0;
     int32_t trav_opt = KC_TRAV_AUTO;
     int64_t step_limit = 0;
@@ -83,6 +84,9 @@ struct kc_graph {
     int64_t *d_f = nullptr, *d_steps = nullptr, *d_iters = nullptr;  // internal per-sample buffers
     int64_t fbuf_len = 0;
     int32_t *d_ctl = nullptr;
+    int64_t *h_progress = nullptr;  // pinned host array, one counter per slot
+    int64_t *d_progress = nullptr;  // its device view
+    int progress_len = 0;
     kc::ReduceOut *d_red = nullptr;
 };
 
@@ -105,6 +109,10 @@ void free_all(kc_graph *g) {
     dev_free(g->d_off); dev_free(g->d_adj); dev_free(g->d_p0); dev_free(g->d_order);
     dev_free(g->d_pre0); dev_free(g->d_out0); dev_free(g->d_eoff); dev_free(g->d_elist);
     dev_free(g->d_f); dev_free(g->d_steps); dev_free(g->d_iters); dev_free(g->d_ctl); dev_free(g->d_red);
+    if (g->h_progress) (void)hipHostFree(g->h_progress);
+    g->h_progress = nullptr;
+    g->d_progress = nullptr;
+    g->progress_len = 0;
 }
 
 // Walk start orders.  Wilson's algorithm may start its walks in any order
@@ -199,7 +207,7 @@ int default_slots(const kc_graph *g) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1024;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1024;
-    per_cu = kc::persistent_blocks_per_cu();
+    per_cu = kc::persistent_blocks_per_cu(g->chains);
     if (cus <= 0 || per_cu <= 0) return 1024;
     return cus * per_cu;
 }
@@ -232,6 +240,7 @@ kc_status run_persistent(kc_graph *g, kc::RunParams rp, hipStream_t stream) {
     sd.rq = g->d_rq;
     sd.queue = g->d_queue;
     sd.cstart = g->d_cstart;
+    sd.chains = kc::sampler_chains();
     sd.word = g->d_word;
     sd.rec = g->d_rec;
     sd.ordr = g->d_ordr;
@@ -243,8 +252,21 @@ kc_status run_persistent(kc_graph *g, kc::RunParams rp, hipStream_t stream) {
     rp.traversal = g->traversal;
     rp.iter_cap = g->step_limit > 0 ? g->step_limit : 1024 * g->n + (1 << 22);
     rp.ctl = g->d_ctl;
+    if (g->progress_len < slots) {
+        if (g->h_progress) (void)hipHostFree(g->h_progress);
+        g->h_progress = nullptr;
+        g->d_progress = nullptr;
+        g->progress_len = 0;
+        HIP_TRY(hipHostMalloc((void **)&g->h_progress, sizeof(int64_t) * (size_t)slots,
+                              hipHostMallocMapped | hipHostMallocCoherent));
+        HIP_TRY(hipHostGetDevicePointer((void **)&g->d_progress, g->h_progress, 0));
+        g->progress_len = slots;
+    }
+    HIP_TRY(hipStreamSynchronize(stream));  // no earlier launch still writes the counters
+    for (int i = 0; i < g->progress_len; ++i) __atomic_store_n(&g->h_progress[i], (int64_t)0, __ATOMIC_RELAXED);
+    rp.progress = g->d_progress;
     HIP_TRY(kc::launch_reset_ctl(g->d_ctl, stream));
-    HIP_TRY(kc::launch_persistent(gd, sd, rp, slots, stream));
+    HIP_TRY(kc::launch_persistent(gd, sd, rp, g->chains, slots, stream));
     int32_t ctl[4] = {0, 0, 0, 0};
     HIP_TRY(hipMemcpyAsync(ctl, g->d_ctl, sizeof(ctl), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
@@ -489,6 +511,10 @@ kc_status kc_set_option(kc_graph *g, int option, int64_t value) {
             if (value < 1 || value > 64) return fail(KC_ERR_INVALID, "walkers must be 1..64");
             g->walkers = (int32_t)value;
             return KC_OK;
+        case KC_OPT_CHAINS:
+            if (!kc::valid_chains((int)value)) return fail(KC_ERR_INVALID, "chains per sample must be 1024 or 2048");
+            g->chains = (int32_t)value;
+            return KC_OK;
         case KC_OPT_SLOTS:
             if (value < 0 || value > (1 << 20)) return fail(KC_ERR_INVALID, "slots must be 0..2^20");
             g->slots_opt = (int32_t)value;
@@ -516,6 +542,14 @@ kc_status kc_set_option(kc_graph *g, int option, int64_t value) {
         }
     }
     return fail(KC_ERR_INVALID, "unknown option %d", option);
+}
+
+kc_status kc_progress(const kc_graph *g, int64_t *samples_done) {
+    if (!g || !samples_done) return KC_ERR_INVALID;
+    int64_t sum = 0;
+    for (int i = 0; i < g->progress_len; ++i) sum += __atomic_load_n(&g->h_progress[i], __ATOMIC_RELAXED);
+    *samples_done = sum;
+    return KC_OK;
 }
 
 kc_status kc_reserve(kc_graph *g, int32_t count, void *hip_stream) {

@@ -31,6 +31,7 @@ struct SlotDev {
     int32_t *rq;     // [slots*n] sampler: restart queue
     int4 *queue;     // [slots*chains] sampler: ready tasks
     int32_t *cstart; // [slots*chains] sampler: chain start vertices
+    int64_t chains;  // per-slot stride of queue and cstart
     uint64_t *word;  // [slots*n] pending-children | volume accumulator
     int4 *rec;       // [slots*n] {tin_w, vol, parent, unused}
     int32_t *ordr;   // [slots*n] bottom-up completion order
@@ -57,6 +58,7 @@ struct RunParams {
     int64_t *f_out;            // [count] (RUN_ESTIMATE / RUN_EVALUATE)
     int64_t *iters_out;        // [count] sampler rounds per sample (optional)
     int32_t *ctl;              // [4]: work counter, error code, error sample, spare
+    int64_t *progress;         // [slots] samples finished per workgroup (host-mapped), or null
 };
 
 // Device result of the exact reduction.
@@ -75,12 +77,13 @@ enum { DEV_OK = 0, DEV_LIMIT = 6, DEV_PROTOCOL = 8, DEV_BADTREE = 9 };
 
 // Launchers (kc_device.hip).  All are asynchronous on `stream`.
 hipError_t launch_reset_ctl(int32_t *ctl, hipStream_t stream);
-hipError_t launch_persistent(const GraphDev &g, const SlotDev &s, const RunParams &rp, int slots,
-                             hipStream_t stream);
+hipError_t launch_persistent(const GraphDev &g, const SlotDev &s, const RunParams &rp, int chains,
+                             int slots, hipStream_t stream);
 hipError_t launch_reduce(const int64_t *f, const int64_t *steps, const int64_t *iters, int32_t count,
                          ReduceOut *out, hipStream_t stream);
 hipError_t launch_zero_i64(int64_t *p, int64_t len, hipStream_t stream);
-int persistent_blocks_per_cu();  // resident single-wave workgroups per CU
-int sampler_chains();            // chain-table entries per sample
+bool valid_chains(int chains);            // a built chain-table size?
+int persistent_blocks_per_cu(int chains);  // resident workgroups per CU for that size
+int sampler_chains();                      // queue / chain-start entries to allocate per slot
 
 }  // namespace kc

@@ -93,6 +93,26 @@ def test_start_order_invariance(kc, oracle_lib, graphs, order):
             assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ref_cnt)
 
 
+@pytest.mark.parametrize("chains", [2048])
+def test_chain_table_size_invariance(kc, oracle_lib, graphs, chains):
+    """The chain-table size changes nothing: trees, draw counts and f stay exact."""
+    for name in ("K5", "petersen", "grid32", "road3k", "social3k", "torus12"):
+        g = graphs[name]
+        _say("chains", chains, name)
+        P = oracle_lib.prepare_graph(g)
+        ref_par, ref_cnt, ref_steps = oracle_lib.sample(P, seed=31, s0=200, count=20, threads=8)
+        ref_f = np.array([oracle_lib.f_of_tree(P, t, "alg1") for t in ref_par], np.int64)
+        with kc.Graph.from_graph(g) as G:
+            G.set_option(kc.KC_OPT_CHAINS, chains)
+            par, cnt, stp = G.sample_trees(31, 200, 20)
+            assert np.array_equal(par.cpu().numpy(), ref_par)
+            assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ref_cnt)
+            assert np.array_equal(stp.cpu().numpy(), ref_steps)
+            _, f, _ = G.estimate(31, 200, 20, per_sample=True)
+            assert np.array_equal(f.cpu().numpy(), ref_f)
+            assert G.progress() == 20
+
+
 def test_batch_split_invariance(kc, graphs):
     g = graphs["road3k"]
     with kc.Graph.from_graph(g) as G:
