@@ -32,8 +32,17 @@ def kc():
     return kc
 
 
+def double_star(gen, leaves):
+    """Two hubs joined by an edge, each with `leaves` leaves: the non-root hub
+    draws from a row far longer than the inline neighbours."""
+    eu = [0] + [0] * leaves + [1] * leaves
+    ev = [1] + list(range(2, 2 + leaves)) + list(range(2 + leaves, 2 + 2 * leaves))
+    return gen.from_edges("double_star(%d)" % leaves, 2 + 2 * leaves, eu, ev)
+
+
 def small_graphs(gen):
     return {
+        "K2": gen.complete(2), "P300": gen.path(300), "dstar": double_star(gen, 300),
         "K3": gen.complete(3), "K5": gen.complete(5), "C7": gen.cycle(7), "P6": gen.path(6),
         "star9": gen.star(9), "petersen": gen.petersen(), "grid8": gen.grid(8, 8),
         "grid32": gen.grid(32, 32), "ba200": gen.barabasi_albert(200, 3, 1),
@@ -48,8 +57,9 @@ def graphs(gen):
     return small_graphs(gen)
 
 
-@pytest.mark.parametrize("name", ["K3", "K5", "C7", "P6", "star9", "petersen", "grid8", "grid32",
-                                  "ba200", "gnm300", "torus12", "Q7", "road3k", "social3k"])
+@pytest.mark.parametrize("name", ["K2", "K3", "K5", "C7", "P6", "P300", "star9", "dstar", "petersen",
+                                  "grid8", "grid32", "ba200", "gnm300", "torus12", "Q7", "road3k",
+                                  "social3k"])
 def test_sampled_trees_bit_exact(kc, oracle_lib, graphs, name):
     g = graphs[name]
     _say("sample parity", name, g.n)
@@ -144,7 +154,8 @@ def test_tree_values_exact(kc, oracle_lib, graphs, name, trav):
 
 
 @pytest.mark.parametrize("trav", [1, 2])
-@pytest.mark.parametrize("name", ["K5", "grid32", "ba200", "road3k", "social3k", "Q7"])
+@pytest.mark.parametrize("name", ["K2", "K5", "P300", "dstar", "grid32", "ba200", "road3k", "social3k",
+                                  "Q7"])
 def test_estimate_exact(kc, oracle_lib, graphs, name, trav):
     g = graphs[name]
     _say("estimate parity", name, trav)
@@ -190,6 +201,17 @@ def test_reserve_then_estimate(kc, oracle_lib, graphs):
         assert np.array_equal(f.cpu().numpy(), ref_f)
         with pytest.raises(kc.KcError):
             G.reserve(0)
+
+
+def test_empty_batches(kc, graphs):
+    """count 0 samples nothing and succeeds; an estimate needs at least one sample."""
+    g = graphs["grid8"]
+    with kc.Graph.from_graph(g) as G:
+        par, cnt, stp = G.sample_trees(1, 0, 0)
+        assert par.shape == (0, g.n)
+        with pytest.raises(kc.KcError) as ei:
+            G.estimate(1, 0, 0)
+        assert ei.value.status == 1
 
 
 def test_step_limit_reports_error(kc, graphs):
