@@ -29,11 +29,16 @@ HBM_PEAK_GBS = 8000.0
 SECTOR = 64
 KERNEL_SRC = os.path.join(ROOT, "paper_2511_16356_amd", "csrc", "kc_device.hip")
 
-# HBM bytes per tree sample of the persistent kernel on this workload, from
-# rocprofv3 FETCH_SIZE + WRITE_SIZE runs (scaled by a plain copy kernel's
-# reading; see profiles/), keyed by the SHA-256 of the kernel source the
-# counters were taken on.  Any other kernel source reports traffic = null.
-MEASURED_TRAFFIC = {}
+# HBM bytes per launch of the persistent kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs of this script with default arguments, each scaled by what the
+# counter reads for a plain 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0);
+# profiles/hbm_traffic_persistent_kernel_road_like_1M_b4096.md.  Keyed by the
+# SHA-256 of the kernel source the counters were taken on: another kernel
+# source, or another workload, reports traffic = null.
+MEASURED_TRAFFIC = {
+    "b07fcb294c2551384b45c5d0802a357b18f135366d12528dc07e3fcc1248f9b6":
+        {"samples": 4096, "points": 1_000_000, "seed": 0, "bytes": 1.541994e+14},
+}
 
 
 def log(*a):
@@ -161,8 +166,10 @@ def main():
     se = math.sqrt(max(var, 0.0) / total) / g.two_m
     alg = algorithmic_bytes(draws, g.n, info["depth0"], total)
     achieved = alg / (gpu_ms / 1e3) / 1e9  # GB/s: algorithmic bytes over the timed launches
-    per_sample_traffic = MEASURED_TRAFFIC.get(kernel_sha())
-    traffic = per_sample_traffic * B if per_sample_traffic else None  # bytes per launch
+    meas = MEASURED_TRAFFIC.get(kernel_sha())
+    traffic = None  # HBM bytes per launch, when counters exist for this kernel and workload
+    if meas and (meas["samples"], meas["points"], meas["seed"]) == (B, args.points, args.seed):
+        traffic = meas["bytes"]
     out = {
         "metric": METRIC,
         "value": value,
