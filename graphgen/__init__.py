@@ -104,6 +104,38 @@ def from_edges(name: str, n: int, eu, ev, meta=None, keep_lcc: bool = True) -> G
     return largest_component(g) if keep_lcc else g
 
 
+def remove_edges(g: Graph, edges) -> Graph:
+    """The same vertex set with the given undirected edges removed (an update
+    batch's input; no component step, rows stay ascending)."""
+    n = g.n
+    drop = set()
+    for a, b in edges:
+        a, b = int(a), int(b)
+        drop.add((min(a, b), max(a, b)))
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.offsets))
+    keep = np.array([(min(x, y), max(x, y)) not in drop for x, y in zip(src.tolist(), g.indices.tolist())],
+                    dtype=bool)
+    indices = g.indices[keep].astype(np.int32)
+    counts = np.bincount(src[keep], minlength=n)
+    offsets = np.zeros(n + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(counts)
+    return Graph(g.name + "-del%d" % len(drop), offsets, indices, dict(g.meta))
+
+
+def is_connected(g: Graph) -> bool:
+    """Whether every vertex is reachable from vertex 0."""
+    seen = np.zeros(g.n, dtype=bool)
+    seen[0] = True
+    stack = [0]
+    while stack:
+        x = stack.pop()
+        for y in g.indices[g.offsets[x]:g.offsets[x + 1]]:
+            if not seen[y]:
+                seen[y] = True
+                stack.append(int(y))
+    return bool(seen.all())
+
+
 def largest_component(g: Graph) -> Graph:
     """Keep the largest connected component, relabelled in original order."""
     from scipy.sparse import csr_matrix

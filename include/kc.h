@@ -198,6 +198,46 @@ kc_status kc_evaluate_trees(kc_graph *g, const int32_t *parents, int32_t count, 
  */
 kc_status kc_progress(const kc_graph *g, int64_t *samples_done);
 
+/*
+ * Resident sample set (section 4: the sample set S kept between updates).
+ *
+ * kc_samples_init draws the trees of samples 0 .. count-1 (as
+ * kc_sample_trees, with `seed`) and keeps their parent arrays and f values
+ * on the device with the graph.  Replaces any earlier set.
+ * Errors: as kc_sample_trees; KC_ERR_INVALID for count < 1.
+ */
+kc_status kc_samples_init(kc_graph *g, uint64_t seed, int32_t count, void *hip_stream);
+
+/* kc_estimate's result over the resident trees on the current graph
+ * (Theorem 3.3 with omega = the set's size).  result: HOST pointer.
+ * Errors: KC_ERR_INVALID if no set was initialised. */
+kc_status kc_samples_query(kc_graph *g, kc_result *result, void *hip_stream);
+
+/* Copy the resident set out: parents_out DEVICE [count*n] int32, f_out
+ * DEVICE [count] int64, ids_out HOST [count] int64 (the sample index each
+ * tree was drawn with); any may be NULL.  count is the set's size. */
+kc_status kc_samples_get(const kc_graph *g, int32_t *parents_out, int64_t *f_out, int64_t *ids_out,
+                         void *hip_stream);
+
+/*
+ * Apply a batch of edge updates (section 4.1, Algorithm 2: basic sample
+ * maintenance).  This version supports deletions: each (u[k], v[k]) must be
+ * an edge of the graph, all distinct; is_insert may be NULL or all zero.
+ * The graph becomes G' = G minus the batch, which must stay connected.
+ * tau0 and every per-graph array are rebuilt on G' with the same root.
+ * Resident trees that contain a deleted edge are replaced by fresh uniform
+ * spanning trees of G' (the set's seed, the next unused sample indices, in
+ * slot order); the others are uniform on G' already (Theorem 4.2).  f is
+ * recomputed for every resident tree on G', since degrees, 2m and tau0 change.
+ *   u, v, is_insert : HOST pointers, count entries
+ *   resampled       : HOST pointer or NULL, receives how many trees were replaced
+ * Errors: KC_ERR_INVALID (not an edge, duplicate, bad vertex),
+ * KC_ERR_UNSUPPORTED (an insertion), KC_ERR_DISCONNECTED (G' not connected;
+ * the graph and the set are left unchanged), and those of kc_sample_trees.
+ */
+kc_status kc_apply_updates(kc_graph *g, const int32_t *u, const int32_t *v, const uint8_t *is_insert,
+                           int32_t count, int32_t *resampled, void *hip_stream);
+
 /* Static description of a status code. */
 const char *kc_status_string(kc_status s);
 

@@ -212,3 +212,58 @@ def reduce_estimate(f, two_m: int):
     else:
         se = float("nan")
     return K, se, s1, s2
+
+
+# ------------------------------------------------------ basic sample maintenance
+
+@dataclass
+class SampleSet:
+    """The sample set S of section 4: trees kept between updates, with the
+    sample index each was drawn with and its f on the current graph."""
+    offsets: np.ndarray
+    indices: np.ndarray
+    root: int
+    seed: int
+    parents: np.ndarray  # [count, n] int32
+    ids: np.ndarray      # [count] int64
+    next_id: int
+    f: np.ndarray        # [count] int64
+
+    @property
+    def two_m(self) -> int:
+        return int(self.offsets[-1])
+
+
+def samples_init(offsets, indices, seed: int, count: int, root: int = -1, threads: int = 8) -> SampleSet:
+    """Samples 0..count-1 of the graph, kept as a set."""
+    P = prepare(offsets, indices, root)
+    parents, _, _ = sample(P, seed, 0, count, threads=threads)
+    f = np.array([f_of_tree(P, t) for t in parents], np.int64)
+    return SampleSet(P.offsets, P.indices, P.root, seed, parents, np.arange(count, dtype=np.int64), count, f)
+
+
+def bsm_delete(S: SampleSet, offsets_new, indices_new, edges, threads: int = 8):
+    """Algorithm 2 (basic sample maintenance), deletion case, for a batch of
+    edges removed at once: the trees that contain a deleted edge are replaced
+    by fresh uniform spanning trees of G' (the set's seed, the next unused
+    sample indices in slot order); the others are uniform spanning trees of
+    G' already (Theorem 4.2).  f is evaluated on G' for every tree, since the
+    degrees, 2m and tau0 (rebuilt on G' from the same root) change.
+    Returns (new set, number of replaced trees)."""
+    P = prepare(offsets_new, indices_new, S.root)
+    par = S.parents.copy()
+    ids = S.ids.copy()
+    redo = []
+    for t in range(par.shape[0]):
+        row = par[t]
+        for a, b in edges:
+            if row[a] == b or row[b] == a:
+                redo.append(t)
+                break
+    if redo:
+        fresh, _, _ = sample(P, S.seed, S.next_id, len(redo), threads=threads)
+        for k, t in enumerate(redo):
+            par[t] = fresh[k]
+            ids[t] = S.next_id + k
+    f = np.array([f_of_tree(P, t) for t in par], np.int64)
+    return SampleSet(P.offsets, P.indices, P.root, S.seed, par, ids, S.next_id + len(redo), f), len(redo)

@@ -27,6 +27,7 @@ KC_OPT_CHAINS = 7
 
 # every symbol include/kc.h declares
 EXPORTS = ("kc_graph_create", "kc_graph_destroy", "kc_graph_get_info", "kc_set_option", "kc_reserve", "kc_progress",
+           "kc_samples_init", "kc_samples_query", "kc_samples_get", "kc_apply_updates",
            "kc_sample_trees", "kc_estimate", "kc_evaluate_trees", "kc_status_string",
            "kc_last_error")
 
@@ -72,6 +73,14 @@ def library() -> ctypes.CDLL:
     lib.kc_graph_get_info.argtypes = [p, ctypes.POINTER(_Info)]
     lib.kc_set_option.restype = ctypes.c_int
     lib.kc_set_option.argtypes = [p, ctypes.c_int, i64]
+    lib.kc_samples_init.restype = ctypes.c_int
+    lib.kc_samples_init.argtypes = [p, u64, i32, p]
+    lib.kc_samples_query.restype = ctypes.c_int
+    lib.kc_samples_query.argtypes = [p, ctypes.POINTER(_Result), p]
+    lib.kc_samples_get.restype = ctypes.c_int
+    lib.kc_samples_get.argtypes = [p, p, p, p, p]
+    lib.kc_apply_updates.restype = ctypes.c_int
+    lib.kc_apply_updates.argtypes = [p, p, p, p, i32, ctypes.POINTER(i32), p]
     lib.kc_progress.restype = ctypes.c_int
     lib.kc_progress.argtypes = [p, ctypes.POINTER(i64)]
     lib.kc_reserve.restype = ctypes.c_int
@@ -117,6 +126,12 @@ class Estimate:
     count: int
     total_steps: int
     sampler_iterations: int
+
+
+def _estimate_of(res: "_Result") -> Estimate:
+    s1 = (res.sum_f_hi << 64) | res.sum_f_lo
+    s2 = (res.sum_f2_hi << 64) | res.sum_f2_lo
+    return Estimate(res.kappa, res.std_error, s1, s2, res.count, res.total_steps, res.sampler_iterations)
 
 
 class Graph:
@@ -167,6 +182,41 @@ class Graph:
         _check(library().kc_progress(self._h, ctypes.byref(out)))
         return out.value
 
+    # ---- resident sample set and updates
+    def samples_init(self, seed: int, count: int, stream=None):
+        """Draw samples 0..count-1 and keep them (parents and f) on the device."""
+        _check(library().kc_samples_init(self._h, seed, count, _stream(stream)))
+        self.res_count = count
+
+    def samples_query(self, stream=None) -> "Estimate":
+        res = _Result()
+        _check(library().kc_samples_query(self._h, ctypes.byref(res), _stream(stream)))
+        return _estimate_of(res)
+
+    def samples_get(self, stream=None):
+        """(parents [count, n] int32 CUDA, f [count] int64 CUDA, ids [count] numpy int64)."""
+        import torch
+        c = self.res_count
+        par = torch.empty((c, self.n), dtype=torch.int32, device="cuda")
+        f = torch.empty((c,), dtype=torch.int64, device="cuda")
+        ids = np.zeros(c, dtype=np.int64)
+        _check(library().kc_samples_get(self._h, _dptr(par), _dptr(f), ids.ctypes.data_as(ctypes.c_void_p),
+                                        _stream(stream)))
+        return par, f, ids
+
+    def apply_updates(self, u, v, is_insert=None, stream=None) -> int:
+        """Apply a batch of edge updates; returns how many resident trees were replaced."""
+        u = np.ascontiguousarray(u, dtype=np.int32)
+        v = np.ascontiguousarray(v, dtype=np.int32)
+        ins = None if is_insert is None else np.ascontiguousarray(is_insert, dtype=np.uint8)
+        out = ctypes.c_int32(0)
+        _check(library().kc_apply_updates(self._h, u.ctypes.data_as(ctypes.c_void_p),
+                                          v.ctypes.data_as(ctypes.c_void_p),
+                                          None if ins is None else ins.ctypes.data_as(ctypes.c_void_p),
+                                          int(u.shape[0]), ctypes.byref(out), _stream(stream)))
+        self.info = self._info()
+        return out.value
+
     def reserve(self, count: int, stream=None):
         """Allocate the workspace for estimates of up to `count` samples now."""
         _check(library().kc_reserve(self._h, count, _stream(stream)))
@@ -194,10 +244,7 @@ class Graph:
         res = _Result()
         _check(library().kc_estimate(self._h, seed, first, count, ctypes.byref(res), _dptr(f),
                                      _dptr(stp), _stream(stream)))
-        s1 = (res.sum_f_hi << 64) | res.sum_f_lo
-        s2 = (res.sum_f2_hi << 64) | res.sum_f2_lo
-        est = Estimate(res.kappa, res.std_error, s1, s2, res.count, res.total_steps,
-                       res.sampler_iterations)
+        est = _estimate_of(res)
         return (est, f, stp) if per_sample else est
 
     def evaluate_trees(self, parents, stream=None):

@@ -919,6 +919,21 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
     }
 }
 
+// Resident trees that contain one of the deleted edges {u, v} (as u -> v or
+// v -> u in the parent array): flags[t] = 1.  One thread per (tree, edge).
+__global__ void flag_trees_kernel(const int32_t *par, int32_t count, int64_t n, const int32_t *eu,
+                                  const int32_t *ev, int32_t ne, uint8_t *flags) {
+    const int64_t total = (int64_t)count * ne;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = i / ne;
+        const int k = (int)(i - t * ne);
+        const int32_t u = eu[k], v = ev[k];
+        const int32_t *row = par + t * n;
+        if (row[u] == v || row[v] == u) flags[t] = 1;
+    }
+}
+
 __global__ void reset_ctl_kernel(int32_t *ctl) {
     if (threadIdx.x < 4) ctl[threadIdx.x] = 0;
 }
@@ -1015,6 +1030,17 @@ int persistent_blocks_per_cu(int chains) {
 hipError_t launch_reduce(const int64_t *f, const int64_t *steps, const int64_t *iters, int32_t count,
                          ReduceOut *out, hipStream_t stream) {
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, stream, f, steps, iters, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_flag_trees(const int32_t *par, int32_t count, int64_t n, const int32_t *eu,
+                             const int32_t *ev, int32_t ne, uint8_t *flags, hipStream_t stream) {
+    const int64_t total = (int64_t)count * ne;
+    if (total <= 0) return hipSuccess;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(flag_trees_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, par, count, n, eu, ev,
+                       ne, flags);
     return hipGetLastError();
 }
 

@@ -51,6 +51,11 @@ hipError_t dev_alloc(T **p, size_t count) {
 
 }  // namespace
 
+struct PreparedGraph {
+    int32_t root = -1, depth0 = 0, nblk = 0;
+    std::vector<int32_t> order, p0, pre0, out0, eoff, elist, vrec;
+};
+
 struct kc_graph {
     int64_t n = 0, two_m = 0;
     int32_t root = -1, depth0 = 0, max_degree = 0;
@@ -65,6 +70,15 @@ struct kc_graph {
     int32_t nblk = 0;
     int32_t start_order = 2;
     std::vector<int32_t> bfs_order;  // host copy of the BFS order from the root
+    std::vector<int64_t> h_off;      // host copy of the current CSR
+    std::vector<int32_t> h_adj;
+    // resident sample set (kc_samples_init / kc_apply_updates)
+    int32_t res_count = 0;
+    uint64_t res_seed = 0;
+    int64_t res_next = 0;             // next unused sample index
+    std::vector<int64_t> res_ids;     // sample index of each resident tree
+    int32_t *d_res_par = nullptr;     // [res_count * n] parents
+    int64_t *d_res_f = nullptr;       // [res_count] f of each tree on the current graph
     // graph arrays on the device
     int64_t *d_off = nullptr;
     int32_t *d_adj = nullptr, *d_p0 = nullptr, *d_order = nullptr, *d_pre0 = nullptr;
@@ -103,11 +117,13 @@ void free_workspace(kc_graph *g) {
     g->ws_slots = 0; g->ws_trav = g->ws_fen = false;
 }
 
+void free_graph_arrays(kc_graph *g);
+
 void free_all(kc_graph *g) {
     free_workspace(g);
-    dev_free(g->d_vrec);
-    dev_free(g->d_off); dev_free(g->d_adj); dev_free(g->d_p0); dev_free(g->d_order);
-    dev_free(g->d_pre0); dev_free(g->d_out0); dev_free(g->d_eoff); dev_free(g->d_elist);
+    free_graph_arrays(g);
+    dev_free(g->d_res_par); dev_free(g->d_res_f);
+    g->d_res_par = nullptr; g->d_res_f = nullptr; g->res_count = 0;
     dev_free(g->d_f); dev_free(g->d_steps); dev_free(g->d_iters); dev_free(g->d_ctl); dev_free(g->d_red);
     if (g->h_progress) (void)hipHostFree(g->h_progress);
     g->h_progress = nullptr;
@@ -283,6 +299,179 @@ kc_status run_persistent(kc_graph *g, kc::RunParams rp, hipStream_t stream) {
     return KC_OK;
 }
 
+// (Re)build every per-graph array from the host CSR in g->h_off / g->h_adj:
+// root (highest degree, smallest index, unless given), tau0 (BFS, parent =
+// smallest-index neighbour one level up), tau0 preorder and subtree ends, the
+// per-block open-subtree lists, the walk start order and the per-vertex graph
+// records; then replace the device copies.  On failure the graph is unchanged
+// only if nothing was uploaded yet (callers validate first).
+kc_status prepare_graph(const std::vector<int64_t> &off, const std::vector<int32_t> &adj, int32_t root,
+                        PreparedGraph *pg) {
+    const int64_t n = (int64_t)off.size() - 1;
+    const int64_t nnz = off[(size_t)n];
+    const int32_t *indices = adj.data();
+    if (root < 0) {
+        int64_t best = -1;
+        for (int64_t v = 0; v < n; ++v) {
+            const int64_t d = off[(size_t)v + 1] - off[(size_t)v];
+            if (d > best) { best = d; root = (int32_t)v; }
+        }
+    }
+    if (root < 0 || root >= n) return fail(KC_ERR_INVALID, "root %d out of range", root);
+    pg->root = root;
+    // BFS from the root; the queue order is the walk start order
+    std::vector<int32_t> dist((size_t)n, -1);
+    std::vector<int32_t> &order = pg->order;
+    order.clear();
+    order.reserve((size_t)n);
+    dist[(size_t)root] = 0;
+    order.push_back(root);
+    for (size_t h = 0; h < order.size(); ++h) {
+        const int32_t x = order[h];
+        for (int64_t e = off[(size_t)x]; e < off[(size_t)x + 1]; ++e) {
+            const int32_t y = indices[e];
+            if (dist[(size_t)y] < 0) {
+                dist[(size_t)y] = dist[(size_t)x] + 1;
+                order.push_back(y);
+            }
+        }
+    }
+    if ((int64_t)order.size() != n)
+        return fail(KC_ERR_DISCONNECTED, "only %zu of %lld vertices reachable from the root", order.size(), (long long)n);
+    // tau0: parent = smallest-index neighbour one level up
+    std::vector<int32_t> &p0 = pg->p0;
+    p0.assign((size_t)n, -1);
+    int32_t depth0 = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        depth0 = std::max(depth0, dist[(size_t)v]);
+        if (v == root) continue;
+        for (int64_t e = off[(size_t)v]; e < off[(size_t)v + 1]; ++e) {
+            const int32_t u = indices[e];
+            if (dist[(size_t)u] == dist[(size_t)v] - 1) { p0[(size_t)v] = u; break; }  // rows ascending
+        }
+    }
+    pg->depth0 = depth0;
+    const unsigned __int128 bound = (unsigned __int128)nnz * (unsigned __int128)nnz * (unsigned __int128)depth0;
+    if (bound >= ((unsigned __int128)1 << 63))
+        return fail(KC_ERR_OVERFLOW, "4 m^2 depth0 = (2m)^2 * %d exceeds 2^63", depth0);
+    // tau0 preorder, children in ascending order
+    std::vector<int64_t> cst((size_t)n + 1, 0);
+    for (int64_t v = 0; v < n; ++v) if (v != root) cst[(size_t)p0[(size_t)v] + 1]++;
+    for (int64_t v = 0; v < n; ++v) cst[(size_t)v + 1] += cst[(size_t)v];
+    std::vector<int32_t> clist((size_t)n);
+    {
+        std::vector<int64_t> fill(cst.begin(), cst.end() - 1);
+        for (int64_t v = 0; v < n; ++v) if (v != root) clist[(size_t)fill[(size_t)p0[(size_t)v]]++] = (int32_t)v;
+    }
+    std::vector<int32_t> in0((size_t)n);
+    std::vector<int32_t> &pre0 = pg->pre0, &out0 = pg->out0;
+    pre0.assign((size_t)n, 0);
+    out0.assign((size_t)n, 0);
+    {
+        std::vector<int32_t> stack;
+        std::vector<int64_t> next((size_t)n);
+        int32_t t = 0;
+        stack.push_back(root);
+        next[(size_t)root] = cst[(size_t)root];
+        pre0[(size_t)t] = root;
+        in0[(size_t)root] = t++;
+        while (!stack.empty()) {
+            const int32_t x = stack.back();
+            if (next[(size_t)x] < cst[(size_t)x + 1]) {
+                const int32_t c = clist[(size_t)next[(size_t)x]++];
+                next[(size_t)c] = cst[(size_t)c];
+                pre0[(size_t)t] = c;
+                in0[(size_t)c] = t++;
+                stack.push_back(c);
+            } else {
+                out0[(size_t)x] = t - 1;
+                stack.pop_back();
+            }
+        }
+    }
+    // per 64-position block: tau0 vertices whose subtree opened before the block and closes in it
+    const int32_t nblk = (int32_t)((n + 63) / 64);
+    pg->nblk = nblk;
+    std::vector<int32_t> &eoff = pg->eoff, &elist = pg->elist;
+    eoff.assign((size_t)nblk + 1, 0);
+    for (int64_t x = 0; x < n; ++x) {
+        const int32_t be = out0[(size_t)x] / 64;
+        if (in0[(size_t)x] < be * 64) eoff[(size_t)be + 1]++;
+    }
+    for (int32_t b = 0; b < nblk; ++b) eoff[(size_t)b + 1] += eoff[(size_t)b];
+    elist.assign((size_t)eoff[(size_t)nblk], 0);
+    {
+        std::vector<int32_t> fill(eoff.begin(), eoff.end() - 1);
+        for (int64_t x = 0; x < n; ++x) {
+            const int32_t be = out0[(size_t)x] / 64;
+            if (in0[(size_t)x] < be * 64) elist[(size_t)fill[(size_t)be]++] = (int32_t)x;
+        }
+    }
+    // per-vertex graph record for the sampler: offset, degree, first six neighbours
+    std::vector<int32_t> &vrec = pg->vrec;
+    vrec.assign((size_t)n * 8, -1);
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t a = off[(size_t)v], b = off[(size_t)v + 1];
+        int32_t *r = &vrec[(size_t)v * 8];
+        r[0] = (int32_t)a;
+        r[1] = (int32_t)(b - a);
+        for (int64_t k = 0; k < 6 && a + k < b; ++k) r[2 + k] = indices[a + k];
+    }
+    return KC_OK;
+}
+
+void free_graph_arrays(kc_graph *g) {
+    dev_free(g->d_vrec);
+    dev_free(g->d_off); dev_free(g->d_adj); dev_free(g->d_p0); dev_free(g->d_order);
+    dev_free(g->d_pre0); dev_free(g->d_out0); dev_free(g->d_eoff); dev_free(g->d_elist);
+    g->d_vrec = nullptr;
+    g->d_off = nullptr; g->d_adj = g->d_p0 = g->d_order = g->d_pre0 = g->d_out0 = nullptr;
+    g->d_eoff = g->d_elist = nullptr;
+    g->graph_bytes = 0;
+}
+
+kc_status rebuild_graph(kc_graph *g, int32_t root, hipStream_t stream) {
+    PreparedGraph pg;
+    const kc_status st = prepare_graph(g->h_off, g->h_adj, root, &pg);
+    if (st != KC_OK) return st;
+    HIP_TRY(hipStreamSynchronize(stream));  // no running launch reads the old arrays
+    free_graph_arrays(g);
+    const int64_t n = (int64_t)g->h_off.size() - 1;
+    g->n = n;
+    g->two_m = g->h_off[(size_t)n];
+    g->root = pg.root;
+    g->depth0 = pg.depth0;
+    g->nblk = pg.nblk;
+    g->max_degree = 0;
+    for (int64_t v = 0; v < n; ++v)
+        g->max_degree = (int32_t)std::max<int64_t>(g->max_degree, g->h_off[(size_t)v + 1] - g->h_off[(size_t)v]);
+    if (g->trav_opt == KC_TRAV_AUTO) g->traversal = pg.depth0 <= 12 ? KC_TRAV_WALK : KC_TRAV_SWEEP;
+    g->bfs_order = pg.order;
+    auto up = [&](auto **dst, const auto *src, size_t cnt) -> hipError_t {
+        hipError_t e = dev_alloc(dst, cnt);
+        if (e != hipSuccess) return e;
+        g->graph_bytes += (int64_t)(cnt * sizeof(**dst));
+        if (cnt == 0) return hipSuccess;
+        return hipMemcpyAsync(*dst, src, cnt * sizeof(**dst), hipMemcpyHostToDevice, stream);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up(&g->d_off, g->h_off.data(), g->h_off.size());
+    if (e == hipSuccess) e = up(&g->d_adj, g->h_adj.data(), g->h_adj.size());
+    if (e == hipSuccess) e = up(&g->d_p0, pg.p0.data(), pg.p0.size());
+    const std::vector<int32_t> start_ord = start_order_of(pg.order, g->start_order);
+    if (e == hipSuccess) e = up(&g->d_order, start_ord.data(), start_ord.size());
+    if (e == hipSuccess) e = up(&g->d_pre0, pg.pre0.data(), pg.pre0.size());
+    if (e == hipSuccess) e = up(&g->d_out0, pg.out0.data(), pg.out0.size());
+    if (e == hipSuccess) e = up(&g->d_eoff, pg.eoff.data(), pg.eoff.size());
+    if (e == hipSuccess) e = up(&g->d_elist, pg.elist.data(), pg.elist.size());
+    if (e == hipSuccess) e = up(&g->d_vrec, reinterpret_cast<const int4 *>(pg.vrec.data()), (size_t)n * 2);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? KC_ERR_NOMEM : KC_ERR_DEVICE, "upload failed: %s",
+                    hipGetErrorString(e));
+    return KC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -344,142 +533,23 @@ kc_status kc_graph_create(int64_t n, const void *offsets, int offsets_are_i64, c
                 return fail(KC_ERR_INVALID, "edge (%lld,%d) has no reverse entry", (long long)v, u);
         }
     }
-    // root: highest degree, smallest index on ties
-    if (root < 0) {
-        int64_t best = -1;
-        for (int64_t v = 0; v < n; ++v) {
-            const int64_t d = off[(size_t)v + 1] - off[(size_t)v];
-            if (d > best) { best = d; root = (int32_t)v; }
-        }
-    }
-    if (root < 0 || root >= n) return fail(KC_ERR_INVALID, "root %d out of range", root);
-    // BFS from the root; the queue order is the walk start order
-    std::vector<int32_t> dist((size_t)n, -1), order;
-    order.reserve((size_t)n);
-    dist[(size_t)root] = 0;
-    order.push_back(root);
-    for (size_t h = 0; h < order.size(); ++h) {
-        const int32_t x = order[h];
-        for (int64_t e = off[(size_t)x]; e < off[(size_t)x + 1]; ++e) {
-            const int32_t y = indices[e];
-            if (dist[(size_t)y] < 0) {
-                dist[(size_t)y] = dist[(size_t)x] + 1;
-                order.push_back(y);
-            }
-        }
-    }
-    if ((int64_t)order.size() != n)
-        return fail(KC_ERR_DISCONNECTED, "only %zu of %lld vertices reachable from the root", order.size(), (long long)n);
-    // tau0: parent = smallest-index neighbour one level up
-    std::vector<int32_t> p0((size_t)n, -1);
-    int32_t depth0 = 0;
-    for (int64_t v = 0; v < n; ++v) {
-        depth0 = std::max(depth0, dist[(size_t)v]);
-        if (v == root) continue;
-        for (int64_t e = off[(size_t)v]; e < off[(size_t)v + 1]; ++e) {
-            const int32_t u = indices[e];
-            if (dist[(size_t)u] == dist[(size_t)v] - 1) { p0[(size_t)v] = u; break; }  // rows ascending
-        }
-    }
-    const unsigned __int128 bound = (unsigned __int128)nnz * (unsigned __int128)nnz * (unsigned __int128)depth0;
-    if (bound >= ((unsigned __int128)1 << 63))
-        return fail(KC_ERR_OVERFLOW, "4 m^2 depth0 = (2m)^2 * %d exceeds 2^63", depth0);
-    // tau0 preorder, children in ascending order
-    std::vector<int64_t> cst((size_t)n + 1, 0);
-    for (int64_t v = 0; v < n; ++v) if (v != root) cst[(size_t)p0[(size_t)v] + 1]++;
-    for (int64_t v = 0; v < n; ++v) cst[(size_t)v + 1] += cst[(size_t)v];
-    std::vector<int32_t> clist((size_t)n);
-    {
-        std::vector<int64_t> fill(cst.begin(), cst.end() - 1);
-        for (int64_t v = 0; v < n; ++v) if (v != root) clist[(size_t)fill[(size_t)p0[(size_t)v]]++] = (int32_t)v;
-    }
-    std::vector<int32_t> pre0((size_t)n), in0((size_t)n), out0((size_t)n);
-    {
-        std::vector<int32_t> stack;
-        std::vector<int64_t> next((size_t)n);
-        int32_t t = 0;
-        stack.push_back(root);
-        next[(size_t)root] = cst[(size_t)root];
-        pre0[(size_t)t] = root;
-        in0[(size_t)root] = t++;
-        while (!stack.empty()) {
-            const int32_t x = stack.back();
-            if (next[(size_t)x] < cst[(size_t)x + 1]) {
-                const int32_t c = clist[(size_t)next[(size_t)x]++];
-                next[(size_t)c] = cst[(size_t)c];
-                pre0[(size_t)t] = c;
-                in0[(size_t)c] = t++;
-                stack.push_back(c);
-            } else {
-                out0[(size_t)x] = t - 1;
-                stack.pop_back();
-            }
-        }
-    }
-    // per 64-position block: tau0 vertices whose subtree opened before the block and closes in it
-    const int32_t nblk = (int32_t)((n + 63) / 64);
-    std::vector<int32_t> eoff((size_t)nblk + 1, 0), elist;
-    for (int64_t x = 0; x < n; ++x) {
-        const int32_t be = out0[(size_t)x] / 64;
-        if (in0[(size_t)x] < be * 64) eoff[(size_t)be + 1]++;
-    }
-    for (int32_t b = 0; b < nblk; ++b) eoff[(size_t)b + 1] += eoff[(size_t)b];
-    elist.resize((size_t)eoff[(size_t)nblk]);
-    {
-        std::vector<int32_t> fill(eoff.begin(), eoff.end() - 1);
-        for (int64_t x = 0; x < n; ++x) {
-            const int32_t be = out0[(size_t)x] / 64;
-            if (in0[(size_t)x] < be * 64) elist[(size_t)fill[(size_t)be]++] = (int32_t)x;
-        }
-    }
-
-    // per-vertex graph record for the sampler: offset, degree, first six neighbours
-    std::vector<int32_t> vrec((size_t)n * 8, -1);
-    for (int64_t v = 0; v < n; ++v) {
-        const int64_t a = off[(size_t)v], b = off[(size_t)v + 1];
-        int32_t *r = &vrec[(size_t)v * 8];
-        r[0] = (int32_t)a;
-        r[1] = (int32_t)(b - a);
-        for (int64_t k = 0; k < 6 && a + k < b; ++k) r[2 + k] = indices[a + k];
-    }
-
     kc_graph *g = new (std::nothrow) kc_graph();
     if (!g) return fail(KC_ERR_NOMEM, "host allocation failed");
-    g->n = n;
-    g->two_m = nnz;
-    g->root = root;
-    g->depth0 = depth0;
+    g->h_off = std::move(off);
+    g->h_adj.assign(indices, indices + nnz);
     g->max_degree = maxdeg;
-    g->nblk = nblk;
-    g->traversal = depth0 <= 12 ? KC_TRAV_WALK : KC_TRAV_SWEEP;
-    g->bfs_order = order;
-    auto up = [&](auto **dst, const auto *src, size_t cnt) -> hipError_t {
-        hipError_t e = dev_alloc(dst, cnt);
-        if (e != hipSuccess) return e;
-        g->graph_bytes += (int64_t)(cnt * sizeof(**dst));
-        if (cnt == 0) return hipSuccess;
-        return hipMemcpyAsync(*dst, src, cnt * sizeof(**dst), hipMemcpyHostToDevice, stream);
-    };
-    hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = up(&g->d_off, off.data(), off.size());
-    if (e == hipSuccess) e = up(&g->d_adj, indices, (size_t)nnz);
-    if (e == hipSuccess) e = up(&g->d_p0, p0.data(), p0.size());
-    const std::vector<int32_t> start_ord = start_order_of(order, 2);
-    g->start_order = 2;
-    if (e == hipSuccess) e = up(&g->d_order, start_ord.data(), start_ord.size());
-    if (e == hipSuccess) e = up(&g->d_pre0, pre0.data(), pre0.size());
-    if (e == hipSuccess) e = up(&g->d_out0, out0.data(), out0.size());
-    if (e == hipSuccess) e = up(&g->d_eoff, eoff.data(), eoff.size());
-    if (e == hipSuccess) e = up(&g->d_elist, elist.data(), elist.size());
-    if (e == hipSuccess) e = up(&g->d_vrec, reinterpret_cast<const int4 *>(vrec.data()), (size_t)n * 2);
-    if (e == hipSuccess) e = dev_alloc(&g->d_ctl, 4);
+    const kc_status st = rebuild_graph(g, root, stream);
+    if (st != KC_OK) {
+        free_all(g);
+        delete g;
+        return st;
+    }
+    hipError_t e = dev_alloc(&g->d_ctl, 4);
     if (e == hipSuccess) e = dev_alloc(&g->d_red, 1);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         free_all(g);
         delete g;
-        return fail(e == hipErrorOutOfMemory ? KC_ERR_NOMEM : KC_ERR_DEVICE, "upload failed: %s",
-                    hipGetErrorString(e));
+        return fail(KC_ERR_NOMEM, "allocation failed: %s", hipGetErrorString(e));
     }
     *out = g;
     return KC_OK;
@@ -650,6 +720,153 @@ kc_status kc_evaluate_trees(kc_graph *g, const int32_t *parents, int32_t count, 
     rp.parents_in = parents;
     rp.f_out = f_out;
     return run_persistent(g, rp, (hipStream_t)hip_stream);
+}
+
+
+kc_status kc_samples_init(kc_graph *g, uint64_t seed, int32_t count, void *hip_stream) {
+    g_last_error.clear();
+    if (!g) return fail(KC_ERR_INVALID, "NULL graph");
+    if (count < 1) return fail(KC_ERR_INVALID, "count must be >= 1");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    dev_free(g->d_res_par);
+    dev_free(g->d_res_f);
+    g->d_res_par = nullptr;
+    g->d_res_f = nullptr;
+    g->res_count = 0;
+    g->res_ids.clear();
+    HIP_TRY(dev_alloc(&g->d_res_par, (size_t)count * (size_t)g->n));
+    HIP_TRY(dev_alloc(&g->d_res_f, (size_t)count));
+    kc_status st = kc_sample_trees(g, seed, 0, count, g->d_res_par, nullptr, nullptr, hip_stream);
+    if (st != KC_OK) return st;
+    st = kc_evaluate_trees(g, g->d_res_par, count, g->d_res_f, hip_stream);
+    if (st != KC_OK) return st;
+    HIP_TRY(hipStreamSynchronize(stream));
+    g->res_count = count;
+    g->res_seed = seed;
+    g->res_next = count;
+    g->res_ids.resize((size_t)count);
+    for (int32_t i = 0; i < count; ++i) g->res_ids[(size_t)i] = i;
+    return KC_OK;
+}
+
+kc_status kc_samples_query(kc_graph *g, kc_result *result, void *hip_stream) {
+    g_last_error.clear();
+    if (!g || !result) return fail(KC_ERR_INVALID, "NULL graph or result");
+    if (g->res_count < 1) return fail(KC_ERR_INVALID, "no resident samples (call kc_samples_init)");
+    return finish_reduce(g, g->res_count, g->d_res_f, nullptr, nullptr, result, (hipStream_t)hip_stream);
+}
+
+kc_status kc_samples_get(const kc_graph *g, int32_t *parents_out, int64_t *f_out, int64_t *ids_out,
+                         void *hip_stream) {
+    g_last_error.clear();
+    if (!g) return fail(KC_ERR_INVALID, "NULL graph");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    const size_t c = (size_t)g->res_count;
+    if (parents_out && c)
+        HIP_TRY(hipMemcpyAsync(parents_out, g->d_res_par, c * (size_t)g->n * sizeof(int32_t),
+                               hipMemcpyDeviceToDevice, stream));
+    if (f_out && c) HIP_TRY(hipMemcpyAsync(f_out, g->d_res_f, c * sizeof(int64_t), hipMemcpyDeviceToDevice, stream));
+    if (ids_out && c) std::memcpy(ids_out, g->res_ids.data(), c * sizeof(int64_t));
+    HIP_TRY(hipStreamSynchronize(stream));
+    return KC_OK;
+}
+
+kc_status kc_apply_updates(kc_graph *g, const int32_t *u, const int32_t *v, const uint8_t *is_insert,
+                           int32_t count, int32_t *resampled, void *hip_stream) {
+    g_last_error.clear();
+    if (!g) return fail(KC_ERR_INVALID, "NULL graph");
+    if (count < 0 || (count > 0 && (!u || !v))) return fail(KC_ERR_INVALID, "bad update arrays");
+    if (resampled) *resampled = 0;
+    if (count == 0) return KC_OK;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    const int64_t n = g->n;
+    // validate: deletions of distinct existing edges
+    std::vector<std::pair<int32_t, int32_t>> del;
+    del.reserve((size_t)count);
+    for (int32_t k = 0; k < count; ++k) {
+        if (is_insert && is_insert[k]) return fail(KC_ERR_UNSUPPORTED, "edge insertion is not supported");
+        int32_t a = u[k], b = v[k];
+        if (a < 0 || a >= n || b < 0 || b >= n || a == b) return fail(KC_ERR_INVALID, "bad edge (%d,%d)", a, b);
+        if (a > b) std::swap(a, b);
+        if (!std::binary_search(g->h_adj.begin() + g->h_off[(size_t)a], g->h_adj.begin() + g->h_off[(size_t)a + 1], b))
+            return fail(KC_ERR_INVALID, "edge (%d,%d) is not in the graph", a, b);
+        del.emplace_back(a, b);
+    }
+    std::sort(del.begin(), del.end());
+    if (std::adjacent_find(del.begin(), del.end()) != del.end()) return fail(KC_ERR_INVALID, "duplicate edge in batch");
+    auto deleted = [&](int32_t a, int32_t b) {
+        if (a > b) std::swap(a, b);
+        return std::binary_search(del.begin(), del.end(), std::make_pair(a, b));
+    };
+    // the graph after the batch (G')
+    std::vector<int64_t> noff((size_t)n + 1, 0);
+    std::vector<int32_t> nadj;
+    nadj.reserve(g->h_adj.size() - 2 * del.size());
+    for (int64_t x = 0; x < n; ++x) {
+        for (int64_t e = g->h_off[(size_t)x]; e < g->h_off[(size_t)x + 1]; ++e) {
+            const int32_t y = g->h_adj[(size_t)e];
+            if (!deleted((int32_t)x, y)) nadj.push_back(y);
+        }
+        noff[(size_t)x + 1] = (int64_t)nadj.size();
+    }
+    {
+        PreparedGraph probe;  // G' must stay connected (section 2.1); nothing changes if not
+        const kc_status st = prepare_graph(noff, nadj, g->root, &probe);
+        if (st != KC_OK) return st;
+    }
+    // resident trees that use a deleted edge (Algorithm 2, deletion: they are
+    // replaced; the others are uniform spanning trees of G' already, Theorem 4.2)
+    std::vector<int32_t> redo;
+    if (g->res_count > 0) {
+        std::vector<int32_t> eu(del.size()), ev(del.size());
+        for (size_t k = 0; k < del.size(); ++k) { eu[k] = del[k].first; ev[k] = del[k].second; }
+        int32_t *d_eu = nullptr, *d_ev = nullptr;
+        uint8_t *d_flags = nullptr;
+        HIP_TRY(dev_alloc(&d_eu, del.size()));
+        HIP_TRY(dev_alloc(&d_ev, del.size()));
+        HIP_TRY(dev_alloc(&d_flags, (size_t)g->res_count));
+        HIP_TRY(hipMemcpyAsync(d_eu, eu.data(), eu.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(d_ev, ev.data(), ev.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemsetAsync(d_flags, 0, (size_t)g->res_count, stream));
+        HIP_TRY(kc::launch_flag_trees(g->d_res_par, g->res_count, n, d_eu, d_ev, (int32_t)del.size(), d_flags, stream));
+        std::vector<uint8_t> flags((size_t)g->res_count);
+        HIP_TRY(hipMemcpyAsync(flags.data(), d_flags, flags.size(), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        dev_free(d_eu);
+        dev_free(d_ev);
+        dev_free(d_flags);
+        for (int32_t t = 0; t < g->res_count; ++t)
+            if (flags[(size_t)t]) redo.push_back(t);
+    }
+    // switch to G'
+    g->h_off.swap(noff);
+    g->h_adj.swap(nadj);
+    kc_status st = rebuild_graph(g, g->root, stream);
+    if (st != KC_OK) return st;
+    if (g->res_count > 0) {
+        // fresh trees of G' for the replaced ones: the next unused sample indices, in slot order
+        const int32_t k = (int32_t)redo.size();
+        if (k > 0) {
+            int32_t *d_tmp = nullptr;
+            HIP_TRY(dev_alloc(&d_tmp, (size_t)k * (size_t)n));
+            st = kc_sample_trees(g, g->res_seed, g->res_next, k, d_tmp, nullptr, nullptr, hip_stream);
+            if (st != KC_OK) { dev_free(d_tmp); return st; }
+            for (int32_t i = 0; i < k; ++i) {
+                HIP_TRY(hipMemcpyAsync(g->d_res_par + (size_t)redo[(size_t)i] * (size_t)n, d_tmp + (size_t)i * (size_t)n,
+                                       (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
+                g->res_ids[(size_t)redo[(size_t)i]] = g->res_next + i;
+            }
+            HIP_TRY(hipStreamSynchronize(stream));
+            dev_free(d_tmp);
+            g->res_next += k;
+        }
+        // every tree's f on G' (degrees, 2m and tau0 changed)
+        st = kc_evaluate_trees(g, g->d_res_par, g->res_count, g->d_res_f, hip_stream);
+        if (st != KC_OK) return st;
+        HIP_TRY(hipStreamSynchronize(stream));
+        if (resampled) *resampled = k;
+    }
+    return KC_OK;
 }
 
 }  // extern "C"

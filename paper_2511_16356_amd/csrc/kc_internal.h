@@ -82,6 +82,8 @@ hipError_t launch_persistent(const GraphDev &g, const SlotDev &s, const RunParam
 hipError_t launch_reduce(const int64_t *f, const int64_t *steps, const int64_t *iters, int32_t count,
                          ReduceOut *out, hipStream_t stream);
 hipError_t launch_zero_i64(int64_t *p, int64_t len, hipStream_t stream);
+hipError_t launch_flag_trees(const int32_t *par, int32_t count, int64_t n, const int32_t *eu,
+                             const int32_t *ev, int32_t ne, uint8_t *flags, hipStream_t stream);
 bool valid_chains(int chains);            // a built chain-table size?
 int persistent_blocks_per_cu(int chains);  // resident workgroups per CU for that size
 int sampler_chains();                      // queue / chain-start entries to allocate per slot

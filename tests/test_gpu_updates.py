@@ -1,0 +1,105 @@
+"""GPU parity of basic sample maintenance (section 4.1, Algorithm 2, deletion
+case) against the oracle: after every batch of edge deletions the resident
+trees, their sample indices, their f on the new graph and the estimate are
+identical to the oracle's."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_16356_amd as kc
+    kc.library()
+    return kc
+
+
+def deletion_batches(gen, g, sizes, seed):
+    """Seeded batches of distinct edges whose removal keeps the graph connected:
+    candidates in a seeded random order, each kept if the graph stays connected."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    rng = np.random.default_rng(seed)
+    out = []
+    for size in sizes:
+        src = np.repeat(np.arange(g.n), np.diff(g.offsets))
+        mask = src < g.indices
+        eu, ev = src[mask], g.indices[mask]
+        batch = []
+        for i in rng.permutation(eu.shape[0]):
+            trial = batch + [(int(eu[i]), int(ev[i]))]
+            g2 = gen.remove_edges(g, trial)
+            a = csr_matrix((np.ones(g2.indices.shape[0]), g2.indices, g2.offsets), shape=(g2.n, g2.n))
+            if connected_components(a, directed=False)[0] == 1:
+                batch = trial
+                if len(batch) == size:
+                    break
+        assert len(batch) == size
+        out.append(batch)
+        g = gen.remove_edges(g, batch)
+    return out
+
+
+def _compare(G, S, two_m):
+    par, f, ids = G.samples_get()
+    assert np.array_equal(ids, S.ids)
+    assert np.array_equal(par.cpu().numpy(), S.parents)
+    assert np.array_equal(f.cpu().numpy(), S.f)
+    assert G.two_m == two_m
+
+
+@pytest.mark.parametrize("name", ["grid32", "road3k", "social3k"])
+def test_bsm_deletions_match_oracle(kc, oracle_lib, gen, name):
+    from test_gpu_parity import small_graphs
+    g = small_graphs(gen)[name]
+    count = 64
+    S = oracle_lib.samples_init(g.offsets, g.indices, seed=11, count=count)
+    with kc.Graph.from_graph(g) as G:
+        G.samples_init(11, count)
+        _compare(G, S, g.two_m)
+        for batch in deletion_batches(gen, g, [1, 5, 40], seed=3):
+            _say(name, "delete", len(batch))
+            g = gen.remove_edges(g, batch)
+            S, ref_k = oracle_lib.bsm_delete(S, g.offsets, g.indices, batch)
+            k = G.apply_updates([a for a, _ in batch], [b for _, b in batch])
+            assert k == ref_k
+            _compare(G, S, g.two_m)
+            est = G.samples_query()
+            K, se, s1, s2 = oracle_lib.reduce_estimate(S.f, g.two_m)
+            assert est.sum_f == s1 and est.sum_f2 == s2
+            assert est.kappa == K and est.std_error == se
+
+
+def test_rejected_updates_change_nothing(kc, gen):
+    from test_gpu_parity import small_graphs
+    g = small_graphs(gen)["road3k"]
+    deg = np.diff(g.offsets)
+    leaf = int(np.nonzero(deg == 1)[0][0])
+    nb = int(g.indices[g.offsets[leaf]])
+    with kc.Graph.from_graph(g) as G:
+        G.samples_init(2, 16)
+        par0, f0, ids0 = G.samples_get()
+        with pytest.raises(kc.KcError) as ei:   # a bridge: G' would be disconnected
+            G.apply_updates([leaf], [nb])
+        assert ei.value.status == 2
+        with pytest.raises(kc.KcError) as ei:   # not an edge
+            G.apply_updates([0], [g.n - 1] if g.n - 1 not in g.indices[g.offsets[0]:g.offsets[1]] else [0])
+        assert ei.value.status == 1
+        with pytest.raises(kc.KcError) as ei:   # insertions are the next step of this build
+            G.apply_updates([leaf], [nb], is_insert=[1])
+        assert ei.value.status == 7
+        par1, f1, ids1 = G.samples_get()
+        assert np.array_equal(par0.cpu().numpy(), par1.cpu().numpy())
+        assert np.array_equal(f0.cpu().numpy(), f1.cpu().numpy())
+        assert np.array_equal(ids0, ids1) and G.two_m == g.two_m

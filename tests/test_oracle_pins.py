@@ -7,6 +7,7 @@ worked triangle example, the cycle-popping order-independence theorem, and
 chi-square uniformity of the sampled trees.
 """
 import json
+import math
 import os
 import shutil
 import subprocess
@@ -267,3 +268,58 @@ def test_reduce_estimate_exact_sums(oracle_lib):
     assert s1 == 3 * 2 ** 62 + 5
     assert s2 == 3 * 2 ** 124 + 25
     assert K == float(3 * 2 ** 62 + 5) / 40.0
+
+
+# ---------------------------------------------------------------- section 4
+
+def _k4_tree_id(row):
+    return tuple(int(x) for x in row)
+
+
+def test_bsm_deletion_keeps_the_set_uniform(gen, oracle_lib):
+    """Theorem 4.2 (deletion): after replacing the trees that contain the
+    deleted edge, the set is uniform over the spanning trees of G' = K4 - e
+    (8 trees), the replaced fraction is P(e in a UST of K4) = R_eff(e) = 1/2,
+    untouched trees keep their sample index, and the estimate is unbiased on G'."""
+    from oracle import exact as E
+    g = gen.complete(4)
+    S = oracle_lib.samples_init(g.offsets, g.indices, seed=5, count=4000)
+    assert S.root == 0
+    e = (1, 2)
+    g2 = gen.remove_edges(g, [e])
+    S2, replaced = oracle_lib.bsm_delete(S, g2.offsets, g2.indices, [e])
+    # replaced fraction ~ 1/2 (4.5 sigma)
+    assert abs(replaced / 4000 - 0.5) < 4.5 * math.sqrt(0.25 / 4000)
+    kept = S2.ids < 4000
+    assert np.array_equal(S2.parents[kept], S.parents[kept])
+    assert sorted(S2.ids[~kept].tolist()) == list(range(4000, 4000 + replaced))
+    # no tree uses the deleted edge; uniform over the 8 trees of K4 - e
+    for row in S2.parents:
+        assert row[1] != 2 and row[2] != 1
+    trees = E.spanning_trees(g2.offsets, g2.indices, 0)
+    assert len(trees) == 8
+    counts = {}
+    for row in S2.parents:
+        counts[_k4_tree_id(row)] = counts.get(_k4_tree_id(row), 0) + 1
+    assert len(counts) == 8
+    expect = 4000 / 8
+    chi2 = sum((c - expect) ** 2 / expect for c in counts.values())
+    assert chi2 < 24.32  # 7 degrees of freedom, p = 0.001
+    K, se, _, _ = oracle_lib.reduce_estimate(S2.f, g2.two_m)
+    assert abs(K - E.kemeny_exact(g2.offsets, g2.indices)) < 4.5 * se
+
+
+def test_bsm_deletion_estimate_unbiased_on_grid(gen, oracle_lib):
+    """Three deletion batches on a 6x6 grid; after each the estimate over the
+    maintained set matches the exact Kemeny constant of the current graph."""
+    from oracle import exact as E
+    g = gen.grid(6, 6)
+    S = oracle_lib.samples_init(g.offsets, g.indices, seed=9, count=3000)
+    batches = [[(7, 8)], [(14, 20), (21, 22)], [(1, 7), (28, 29)]]
+    for batch in batches:
+        g = gen.remove_edges(g, batch)
+        assert gen.is_connected(g)
+        S, replaced = oracle_lib.bsm_delete(S, g.offsets, g.indices, batch)
+        assert replaced > 0
+        K, se, _, _ = oracle_lib.reduce_estimate(S.f, g.two_m)
+        assert abs(K - E.kemeny_exact(g.offsets, g.indices)) < 4.5 * se
