@@ -65,6 +65,68 @@ def cpu_baseline(g, seed: int, first: int, threads: int, per_thread: int):
                       (first, first + count - 1, per_thread, dt)}
 
 
+def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: float, duration: float):
+    """Served query and update latency on resident graphs (continuous batching,
+    paper_2511_16356_amd.serve): Poisson arrivals, 80% Kemeny queries and 20%
+    edge-deletion batches (sizes log-uniform in [1, 1000], edges drawn with
+    probability proportional to d(u) d(v), batches that keep the graph connected)."""
+    import numpy as np
+    import torch
+    import graphgen
+    from paper_2511_16356_amd.serve import Server, Request, latency_stats
+    t_gen = time.perf_counter()
+    gs = graphgen.serving_graphs(graphs, lo, hi, seed)
+    rng = np.random.default_rng(seed + 1)
+    n_req = int(rate * duration)
+    times = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    upd = rng.random(n_req) < 0.2
+    gids = rng.integers(0, graphs, size=n_req)
+    cur = list(gs)
+    plan = []
+    for t, is_upd, gid in zip(times, upd, gids):
+        gid = int(gid)
+        if is_upd:
+            size = int(round(math.exp(rng.uniform(0.0, math.log(1000.0)))))
+            batch = graphgen.deletion_batch(cur[gid], size, rng)
+            cur[gid] = graphgen.remove_edges(cur[gid], batch)
+            plan.append((float(t), gid, "update", batch))
+        else:
+            plan.append((float(t), gid, "query", []))
+    log("serving: %d graphs, %d requests planned (%.1f s)" % (graphs, n_req, time.perf_counter() - t_gen))
+    srv = Server(budget_bytes=32 << 30, update_share=4 << 30)
+    try:
+        t_init = time.perf_counter()
+        for gid, g in enumerate(gs):
+            srv.add_graph(gid, g, seed=seed + gid, samples=samples)
+        torch.cuda.synchronize()
+        log("serving: %d x %d resident trees drawn (%.1f s)" % (graphs, samples, time.perf_counter() - t_init))
+        reqs = []
+        t0 = time.perf_counter()
+        for t, gid, kind, batch in plan:
+            now = time.perf_counter() - t0
+            if t > now:
+                time.sleep(t - now)
+            r = Request(gid, kind, batch)
+            reqs.append(r)
+            srv.submit(r)
+        while srv.drain(timeout=20.0) < len(reqs):
+            log("serving: %d of %d requests served" % (len(srv.done), len(reqs)))
+        makespan = time.perf_counter() - t0
+        errors = sum(1 for r in reqs if r.error)
+        return {
+            "workload": "%d resident graphs (cycle of grid, road-like, Chung-Lu types), %d-%d vertices "
+                        "log-uniform, %d trees each; Poisson arrivals at %.0f requests/s for %.0f s, "
+                        "80%% queries / 20%% deletion batches (1-1000 edges, prob. ~ d(u)d(v))"
+                        % (graphs, lo, hi, samples, rate, duration),
+            "requests": len(reqs), "errors": errors, "makespan_s": makespan,
+            "throughput_req_per_s": len(reqs) / makespan,
+            "query": latency_stats(reqs, "query"), "update": latency_stats(reqs, "update"),
+            "trees_replaced": int(sum(r.result for r in reqs if r.kind == "update" and not r.error)),
+        }
+    finally:
+        srv.close()
+
+
 def kernel_sha() -> str:
     import hashlib
     with open(KERNEL_SRC, "rb") as fh:
@@ -93,6 +155,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-per-thread", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-latency leg")
+    ap.add_argument("--serve-graphs", type=int, default=8)
+    ap.add_argument("--serve-rate", type=float, default=5.0, help="requests per second")
+    ap.add_argument("--serve-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -207,6 +273,9 @@ def main():
             "algorithmic_bytes_per_launch": alg / args.steps,
         },
     }
+    if not args.no_serve:
+        out["served"] = serving_leg(args.seed + 7, args.serve_graphs, 10_000, 30_000, 1024,
+                                    args.serve_rate, args.serve_seconds)
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         try:

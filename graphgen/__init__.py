@@ -16,6 +16,8 @@ import os
 import subprocess
 from dataclasses import dataclass, field
 
+import math
+
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -108,18 +110,15 @@ def remove_edges(g: Graph, edges) -> Graph:
     """The same vertex set with the given undirected edges removed (an update
     batch's input; no component step, rows stay ascending)."""
     n = g.n
-    drop = set()
-    for a, b in edges:
-        a, b = int(a), int(b)
-        drop.add((min(a, b), max(a, b)))
+    e = np.asarray(list(edges), dtype=np.int64).reshape(-1, 2)
+    drop = np.concatenate([e[:, 0] * n + e[:, 1], e[:, 1] * n + e[:, 0]])
     src = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.offsets))
-    keep = np.array([(min(x, y), max(x, y)) not in drop for x, y in zip(src.tolist(), g.indices.tolist())],
-                    dtype=bool)
+    keep = ~np.isin(src * n + g.indices.astype(np.int64), drop)
     indices = g.indices[keep].astype(np.int32)
     counts = np.bincount(src[keep], minlength=n)
     offsets = np.zeros(n + 1, dtype=np.int64)
     offsets[1:] = np.cumsum(counts)
-    return Graph(g.name + "-del%d" % len(drop), offsets, indices, dict(g.meta))
+    return Graph(g.name + "-del%d" % e.shape[0], offsets, indices, dict(g.meta))
 
 
 def is_connected(g: Graph) -> bool:
@@ -348,3 +347,49 @@ def workload(name: str, scale: float = 1.0) -> Graph:
     if name == "dense":
         return chung_lu(max(1000, int(3_000_000 * scale)), 2.0, 76.0, 30000.0, seed=0)
     raise KeyError(name)
+
+
+# ---------------------------------------------------------------- serving mix
+
+def serving_graphs(count: int, lo: int, hi: int, seed: int):
+    """`count` resident graphs for the serving mix: types cycle grid, road-like,
+    Chung-Lu; vertex counts log-uniform in [lo, hi] (seeded)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        size = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        kind = i % 3
+        if kind == 0:
+            side = max(4, int(round(math.sqrt(size))))
+            g = grid(side, side)
+        elif kind == 1:
+            g = road_like(max(1000, int(size / 0.8)), seed=int(rng.integers(1 << 30)))
+        else:
+            g = chung_lu(size, 2.2, 10.0, max(50.0, size ** 0.5 * 5), seed=int(rng.integers(1 << 30)))
+        out.append(g)
+    return out
+
+
+def deletion_batch(g: Graph, size: int, rng) -> list:
+    """Up to `size` distinct edges drawn with probability proportional to
+    d(u) d(v) (the power-law update model), whose removal keeps the graph
+    connected: a batch that would disconnect it is halved until it does not."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    deg = np.diff(g.offsets).astype(np.float64)
+    src = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    mask = src < g.indices
+    eu, ev = src[mask], g.indices[mask]
+    w = deg[eu] * deg[ev]
+    size = min(size, eu.shape[0] - g.n + 1)
+    if size <= 0:
+        return []
+    pick = rng.choice(eu.shape[0], size=size, replace=False, p=w / w.sum())
+    batch = [(int(eu[i]), int(ev[i])) for i in pick]
+    while batch:
+        g2 = remove_edges(g, batch)
+        a = csr_matrix((np.ones(g2.indices.shape[0]), g2.indices, g2.offsets), shape=(g2.n, g2.n))
+        if connected_components(a, directed=False)[0] == 1:
+            return batch
+        batch = batch[: len(batch) // 2]
+    return batch
