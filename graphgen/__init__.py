@@ -121,6 +121,22 @@ def remove_edges(g: Graph, edges) -> Graph:
     return Graph(g.name + "-del%d" % e.shape[0], offsets, indices, dict(g.meta))
 
 
+def add_edges(g: Graph, edges) -> Graph:
+    """The same vertex set with the given undirected edges added (an update
+    batch's input; rows stay ascending)."""
+    n = g.n
+    e = np.asarray(list(edges), dtype=np.int64).reshape(-1, 2)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.offsets))
+    src = np.concatenate([src, e[:, 0], e[:, 1]])
+    dst = np.concatenate([g.indices.astype(np.int64), e[:, 1], e[:, 0]])
+    order = np.lexsort((dst, src))
+    src, dst = src[order], dst[order]
+    counts = np.bincount(src, minlength=n)
+    offsets = np.zeros(n + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(counts)
+    return Graph(g.name + "-add%d" % e.shape[0], offsets, dst.astype(np.int32), dict(g.meta))
+
+
 def is_connected(g: Graph) -> bool:
     """Whether every vertex is reachable from vertex 0."""
     seen = np.zeros(g.n, dtype=bool)
@@ -393,3 +409,20 @@ def deletion_batch(g: Graph, size: int, rng) -> list:
             return batch
         batch = batch[: len(batch) // 2]
     return batch
+
+
+def insertion_batch(g: Graph, size: int, rng) -> list:
+    """`size` distinct new edges {u, v} (not in the graph, u != v), endpoints
+    drawn with probability proportional to their degrees (the power-law update
+    model: an edge's probability is proportional to d(u) d(v))."""
+    deg = np.diff(g.offsets).astype(np.float64)
+    p = deg / deg.sum()
+    out, seen = [], set()
+    while len(out) < size:
+        a, b = (int(x) for x in rng.choice(g.n, size=2, p=p))
+        key = (min(a, b), max(a, b))
+        if a == b or key in seen or b in g.indices[g.offsets[a]:g.offsets[a + 1]]:
+            continue
+        seen.add(key)
+        out.append(key)
+    return out

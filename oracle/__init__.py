@@ -54,6 +54,8 @@ def _load():
         lib.orc_arrow.argtypes = [u64, u64, u32, u32, u32]
         lib.orc_prepare.restype = ctypes.c_int
         lib.orc_prepare.argtypes = [i64, p, p, i32, p, p, p, p, p, p]
+        lib.orc_wilson_two_roots.restype = ctypes.c_int
+        lib.orc_wilson_two_roots.argtypes = [i64, p, p, i32, i32, u64, u64, p, p, p]
         lib.orc_wilson_order.restype = ctypes.c_int
         lib.orc_wilson_order.argtypes = [i64, p, p, i32, u64, u64, p, p, p, p]
         lib.orc_f.restype = ctypes.c_int
@@ -150,6 +152,32 @@ def with_tau0(P: Prepared, p0) -> Prepared:
         else:
             out0[x] = t - 1
     return Prepared(n, P.offsets, P.indices, P.root, p0, P.dist, in0, out0, P.depth0)
+
+
+def dfs_tree(offsets, indices, root: int) -> np.ndarray:
+    """Depth-first spanning tree from `root` (one of the reference-tree choices
+    compared in section 5, Exp-II): the search scans each row in ascending
+    order and a vertex's parent is the vertex it was first reached from.
+    Returns the parent array (root -> -1)."""
+    off = np.asarray(offsets, dtype=np.int64)
+    adj = np.asarray(indices, dtype=np.int32)
+    n = len(off) - 1
+    parent = np.full(n, -1, np.int32)
+    seen = np.zeros(n, bool)
+    seen[root] = True
+    stack = [(root, int(off[root]))]   # (vertex, next row position to scan)
+    while stack:
+        x, e = stack[-1]
+        if e == off[x + 1]:
+            stack.pop()
+            continue
+        stack[-1] = (x, e + 1)
+        y = int(adj[e])
+        if not seen[y]:
+            seen[y] = True
+            parent[y] = x
+            stack.append((y, int(off[y])))
+    return parent
 
 
 def wilson(P: Prepared, seed: int, s: int, order=None):
@@ -267,3 +295,105 @@ def bsm_delete(S: SampleSet, offsets_new, indices_new, edges, threads: int = 8):
             ids[t] = S.next_id + k
     f = np.array([f_of_tree(P, t) for t in par], np.int64)
     return SampleSet(P.offsets, P.indices, P.root, S.seed, par, ids, S.next_id + len(redo), f), len(redo)
+
+
+# ------------------------------------------- basic sample maintenance: inserts
+
+def update_uniform(seed: int, slot: int, serial: int) -> float:
+    """The replacement draw of resident tree `slot` at insertion number
+    `serial`: Philox4x32-10 with key (seed_lo, seed_hi) and counter
+    (slot, serial, 2^32-1, 2^32-1) (a counter no tree sample uses), x = o0 |
+    o1 << 32, uniform = (x >> 11) * 2^-53 in [0, 1)."""
+    o = philox4x32_10([slot, serial, 0xFFFFFFFF, 0xFFFFFFFF], [seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF])
+    x = int(o[0]) | (int(o[1]) << 32)
+    return (x >> 11) * 2.0 ** -53
+
+
+def reference_path(offsets, indices, u: int, v: int) -> list:
+    """A fixed u -> v path: breadth-first search from u (rows ascending), each
+    vertex reached from the first vertex that reaches it."""
+    n = len(offsets) - 1
+    pred = np.full(n, -1, np.int64)
+    pred[u] = u
+    q = [u]
+    h = 0
+    while h < len(q) and pred[v] < 0:
+        x = q[h]
+        h += 1
+        for y in indices[offsets[x]:offsets[x + 1]]:
+            if pred[y] < 0:
+                pred[y] = x
+                q.append(int(y))
+    path = [v]
+    while path[-1] != u:
+        path.append(int(pred[path[-1]]))
+    return path[::-1]
+
+
+def path_current(parent, path) -> int:
+    """Signed number of edges of `path` that the tree's own u -> v path uses,
+    +1 in the path's direction and -1 against it.  Its mean over uniform
+    spanning trees is the effective resistance R(u, v): the tree path's
+    direction on an edge has mean equal to the unit u -> v current there
+    (Kirchhoff), and the currents summed along any u -> v path give the
+    potential difference."""
+    u, v = path[0], path[-1]
+
+    def ancestors(x):
+        out = set()
+        while x != -1:
+            out.add(int(x))
+            x = int(parent[x])
+        return out
+
+    au, av = ancestors(u), ancestors(v)
+    up, dn = au - av, av - au  # tree path: up from u to the meeting point, then down to v
+    c = 0
+    for a, b in zip(path[:-1], path[1:]):
+        if (a in up and parent[a] == b) or (b in dn and parent[b] == a):
+            c += 1
+        elif (b in up and parent[b] == a) or (a in dn and parent[a] == b):
+            c -= 1
+    return c
+
+
+def wilson_two_roots(P: Prepared, u: int, v: int, seed: int, s: int):
+    n = P.n
+    parent = np.zeros(n, np.int32); cnt = np.zeros(n, np.uint32)
+    steps = ctypes.c_int64()
+    _check(_load().orc_wilson_two_roots(n, _ptr(P.offsets), _ptr(P.indices), u, v, seed, s,
+                                        _ptr(parent), _ptr(cnt), ctypes.byref(steps)))
+    return parent
+
+
+def bsm_insert(S: SampleSet, offsets_new, indices_new, u: int, v: int, serial: int):
+    """Algorithm 2 (basic sample maintenance), insertion of edge (u, v):
+    R(u, v) on the old graph is estimated from the set's own trees
+    (path_current), each tree is replaced independently with probability
+    R_G'(e) = R / (1 + R) (Theorem 4.1; a binomial number of replacements,
+    each tree drawn by update_uniform), and every replacement is a uniform
+    spanning tree of G' through e: Wilson's algorithm with u and v both in the
+    tree, then the edge (v -> u) and the path from r re-oriented toward r.
+    f is evaluated on G' for every tree.  Returns (new set, replaced, R-hat)."""
+    path = reference_path(S.offsets, S.indices, u, v)
+    csum = sum(path_current(t, path) for t in S.parents)
+    count = S.parents.shape[0]
+    rhat = csum / count
+    p = rhat / (1.0 + rhat)
+    redo = [t for t in range(count) if update_uniform(S.seed, t, serial) < p]
+    P = prepare(offsets_new, indices_new, S.root)
+    par = S.parents.copy()
+    ids = S.ids.copy()
+    for k, t in enumerate(redo):
+        tree = wilson_two_roots(P, u, v, S.seed, S.next_id + k)
+        tree[v] = u
+        prev, x = -1, P.root
+        while x != -1:
+            nx = int(tree[x])
+            tree[x] = prev
+            prev, x = x, nx
+        par[t] = tree
+        ids[t] = S.next_id + k
+    f = np.array([f_of_tree(P, t) for t in par], np.int64)
+    return (SampleSet(P.offsets, P.indices, P.root, S.seed, par, ids, S.next_id + len(redo), f),
+            len(redo), rhat)

@@ -548,6 +548,41 @@ int orc_estimate(int64_t n, const int64_t *off, const int32_t *adj, int32_t root
 }
 
 /* Wilson with an explicit start order (for the order-independence pin). */
+/*
+ * Wilson's algorithm with the two vertices u and v both in the tree from the
+ * start (section 4.1: a uniform spanning tree that contains the new edge
+ * (u, v) is the edge plus a uniform spanning forest of two trees rooted at
+ * u and v).  Same arrows as orc_wilson; walks start in ascending order.
+ * parent[u] = parent[v] = -1 on return.  Returns total draws.
+ */
+int orc_wilson_two_roots(int64_t n, const int64_t *off, const int32_t *adj, int32_t u, int32_t v,
+                         uint64_t seed, uint64_t s, int32_t *parent, uint32_t *cnt, int64_t *steps_out) {
+    uint8_t *intree = (uint8_t *)malloc((size_t)n);
+    if (!intree) return ORC_NOMEM;
+    for (int64_t x = 0; x < n; ++x) { cnt[x] = 0; intree[x] = 0; parent[x] = -1; }
+    intree[u] = 1;
+    intree[v] = 1;
+    int64_t steps = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t x = (int32_t)i;
+        while (!intree[x]) {
+            uint32_t deg = (uint32_t)(off[x + 1] - off[x]);
+            uint32_t j = orc_arrow(seed, s, (uint32_t)x, cnt[x], deg);
+            cnt[x]++;
+            parent[x] = adj[off[x] + j];
+            x = parent[x];
+            ++steps;
+        }
+        x = (int32_t)i;
+        while (!intree[x]) { intree[x] = 1; x = parent[x]; }
+    }
+    parent[u] = -1;
+    parent[v] = -1;
+    free(intree);
+    *steps_out = steps;
+    return ORC_OK;
+}
+
 int orc_wilson_order(int64_t n, const int64_t *off, const int32_t *adj, int32_t root,
                      uint64_t seed, uint64_t s, const int32_t *order,
                      int32_t *parent, uint32_t *cnt, int64_t *steps_out) {

@@ -23,7 +23,7 @@ def kc():
 def declared_functions():
     text = open(os.path.join(ROOT, "include", "kc.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return set(re.findall(r"\b(kc_[a-z_]+)\s*\(", text))
+    return set(re.findall(r"\b(kc_[a-z0-9_]+)\s*\(", text))
 
 
 def test_exports_every_declared_symbol(kc):

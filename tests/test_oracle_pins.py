@@ -131,7 +131,8 @@ def test_enumeration_with_non_bfs_tau0(gen, oracle_lib):
         P = oracle_lib.prepare_graph(g)
         trees = E.spanning_trees(g.offsets, g.indices, P.root)
         K = E.kemeny_exact(g.offsets, g.indices)
-        for t0 in (trees[0], trees[len(trees) // 2], trees[-1]):
+        dfs = oracle_lib.dfs_tree(g.offsets, g.indices, P.root)
+        for t0 in (trees[0], trees[len(trees) // 2], trees[-1], dfs):
             Q = oracle_lib.with_tau0(P, t0)
             for form in ("naive", "alg1", "peredge", "walk"):
                 fs = [oracle_lib.f_of_tree(Q, t, form) for t in trees]
@@ -207,6 +208,50 @@ def test_root_and_bfs_rules(gen, oracle_lib):
         if v != P.root:
             u = P.p0[v]
             assert P.in0[u] < P.in0[v] <= P.out0[v] <= P.out0[u]
+
+
+def test_dfs_tau0_rule(gen, oracle_lib):
+    """The depth-first reference tree of section 5 (Exp-II)."""
+    # hand-traced: 3x3 grid (id 3i+j) from 0, rows ascending:
+    # 0 -> 1 -> 2 -> 5 -> 4 -> 3 -> 6 -> 7 -> 8, a Hamiltonian path
+    g = gen.grid(3, 3)
+    assert list(oracle_lib.dfs_tree(g.offsets, g.indices, 0)) == [-1, 0, 1, 4, 5, 2, 3, 6, 7]
+    # K4 from 0: the chain 0-1-2-3; from 2: 2-0-1-3
+    g = gen.complete(4)
+    assert list(oracle_lib.dfs_tree(g.offsets, g.indices, 0)) == [-1, 0, 1, 2]
+    assert list(oracle_lib.dfs_tree(g.offsets, g.indices, 2)) == [2, 0, -1, 1]
+    # star from a leaf: the leaf's only neighbour, the centre, then every other leaf
+    g = gen.star(6)
+    assert list(oracle_lib.dfs_tree(g.offsets, g.indices, 3)) == [3, 0, 0, -1, 0, 0]
+    # the defining property of a depth-first tree of an undirected graph: it
+    # spans, and every graph edge joins a vertex to one of its tree ancestors
+    for g in (gen.grid(8, 8), gen.largest_component(gen.gnm(60, 150, 3)), gen.barabasi_albert(80, 2, 1),
+              gen.road_like(800, seed=2)):
+        r = int(np.argmax(np.diff(g.offsets)))
+        par = oracle_lib.dfs_tree(g.offsets, g.indices, r)
+        depth = np.full(g.n, -1)
+        depth[r] = 0
+        for v in range(g.n):
+            chain = []
+            x = v
+            while depth[x] < 0:
+                chain.append(x)
+                x = par[x]
+                assert len(chain) <= g.n
+            for i, y in enumerate(reversed(chain)):
+                depth[y] = depth[x] + 1 + i
+        assert par[r] == -1
+
+        def is_anc(a, b):
+            while depth[b] > depth[a]:
+                b = par[b]
+            return a == b
+        for v in range(g.n):
+            nb = g.indices[g.offsets[v]:g.offsets[v + 1]]
+            if v != r:
+                assert par[v] in nb
+            for u in nb:
+                assert is_anc(u, v) or is_anc(v, u)
 
 
 def test_wilson_order_independent(gen, oracle_lib):
@@ -321,5 +366,79 @@ def test_bsm_deletion_estimate_unbiased_on_grid(gen, oracle_lib):
         assert gen.is_connected(g)
         S, replaced = oracle_lib.bsm_delete(S, g.offsets, g.indices, batch)
         assert replaced > 0
+        K, se, _, _ = oracle_lib.reduce_estimate(S.f, g.two_m)
+        assert abs(K - E.kemeny_exact(g.offsets, g.indices)) < 4.5 * se
+
+
+def _resistance(offsets, indices, u, v):
+    n = len(offsets) - 1
+    L = np.zeros((n, n))
+    for x in range(n):
+        for y in indices[offsets[x]:offsets[x + 1]]:
+            L[x, y] -= 1.0
+            L[x, x] += 1.0
+    Lp = np.linalg.pinv(L)
+    return Lp[u, u] + Lp[v, v] - 2 * Lp[u, v]
+
+
+@pytest.mark.parametrize("name,pairs", [("K4", [(1, 2), (0, 3)]), ("grid3", [(0, 8), (1, 4), (2, 6)]),
+                                        ("petersen", [(0, 5), (2, 8)]), ("C6", [(0, 3), (1, 2)])])
+def test_path_current_mean_is_effective_resistance(gen, oracle_lib, name, pairs):
+    """Over all spanning trees, the signed path count has mean R(u, v) exactly
+    (Kirchhoff's current flow), for adjacent and non-adjacent pairs."""
+    g = {"K4": gen.complete(4), "grid3": gen.grid(3, 3), "petersen": gen.petersen(), "C6": gen.cycle(6)}[name]
+    from oracle import exact as E
+    P = oracle_lib.prepare_graph(g)
+    trees = E.spanning_trees(g.offsets, g.indices, P.root)
+    for u, v in pairs:
+        path = oracle_lib.reference_path(g.offsets, g.indices, u, v)
+        assert path[0] == u and path[-1] == v
+        mean = sum(oracle_lib.path_current(t, path) for t in trees) / len(trees)
+        assert abs(mean - _resistance(g.offsets, g.indices, u, v)) < 1e-12
+
+
+def test_bsm_insertion_keeps_the_set_uniform(gen, oracle_lib):
+    """Theorem 4.1 (insertion): from a uniform set on K4 - e, inserting e
+    replaces a binomial share R_G'(e) = 1/2 of the trees by uniform trees through
+    e; the set is then uniform over the 16 spanning trees of K4, untouched trees
+    keep their index, and the estimate is unbiased on K4."""
+    from oracle import exact as E
+    g0 = gen.remove_edges(gen.complete(4), [(1, 2)])
+    S = oracle_lib.samples_init(g0.offsets, g0.indices, seed=21, count=4000, root=0)
+    g1 = gen.add_edges(g0, [(1, 2)])
+    S2, replaced, rhat = oracle_lib.bsm_insert(S, g1.offsets, g1.indices, 1, 2, serial=0)
+    assert abs(rhat - _resistance(g0.offsets, g0.indices, 1, 2)) < 0.05
+    assert abs(replaced / 4000 - 0.5) < 4.5 * math.sqrt(0.25 / 4000) + 0.02
+    kept = S2.ids < 4000
+    assert np.array_equal(S2.parents[kept], S.parents[kept])
+    for t in S2.parents[~kept]:
+        assert t[1] == 2 or t[2] == 1  # replacements go through the new edge
+        assert t[0] == -1
+    counts = {}
+    for row in S2.parents:
+        counts[tuple(int(x) for x in row)] = counts.get(tuple(int(x) for x in row), 0) + 1
+    assert len(counts) == 16
+    expect = 4000 / 16
+    chi2 = sum((c - expect) ** 2 / expect for c in counts.values())
+    assert chi2 < 37.70  # 15 degrees of freedom, p = 0.001
+    K, se, _, _ = oracle_lib.reduce_estimate(S2.f, g1.two_m)
+    assert abs(K - E.kemeny_exact(g1.offsets, g1.indices)) < 4.5 * se
+
+
+def test_bsm_mixed_updates_unbiased_on_grid(gen, oracle_lib):
+    """Insertions and deletions on a 6x6 grid; the maintained estimate stays
+    within the CLT interval of the exact Kemeny constant of the current graph."""
+    from oracle import exact as E
+    g = gen.grid(6, 6)
+    S = oracle_lib.samples_init(g.offsets, g.indices, seed=13, count=3000)
+    serial = 0
+    for kind, e in [("add", (0, 35)), ("del", (7, 8)), ("add", (3, 20)), ("add", (10, 25)), ("del", (14, 20))]:
+        if kind == "add":
+            g = gen.add_edges(g, [e])
+            S, _, _ = oracle_lib.bsm_insert(S, g.offsets, g.indices, e[0], e[1], serial)
+            serial += 1
+        else:
+            g = gen.remove_edges(g, [e])
+            S, _ = oracle_lib.bsm_delete(S, g.offsets, g.indices, [e])
         K, se, _, _ = oracle_lib.reduce_estimate(S.f, g.two_m)
         assert abs(K - E.kemeny_exact(g.offsets, g.indices)) < 4.5 * se
