@@ -68,8 +68,9 @@ def cpu_baseline(g, seed: int, first: int, threads: int, per_thread: int):
 def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: float, duration: float):
     """Served query and update latency on resident graphs (continuous batching,
     paper_2511_16356_amd.serve): Poisson arrivals, 80% Kemeny queries and 20%
-    edge-deletion batches (sizes log-uniform in [1, 1000], edges drawn with
-    probability proportional to d(u) d(v), batches that keep the graph connected)."""
+    update batches, half deletions (sizes log-uniform in [1, 1000], batches
+    that keep the graph connected) and half insertions (sizes log-uniform in
+    [1, 10]); edges drawn with probability proportional to d(u) d(v)."""
     import numpy as np
     import torch
     import graphgen
@@ -85,13 +86,18 @@ def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: fl
     plan = []
     for t, is_upd, gid in zip(times, upd, gids):
         gid = int(gid)
-        if is_upd:
+        if is_upd and rng.random() < 0.5:
             size = int(round(math.exp(rng.uniform(0.0, math.log(1000.0)))))
             batch = graphgen.deletion_batch(cur[gid], size, rng)
             cur[gid] = graphgen.remove_edges(cur[gid], batch)
-            plan.append((float(t), gid, "update", batch))
+            plan.append((float(t), gid, "update", batch, False))
+        elif is_upd:
+            size = int(round(math.exp(rng.uniform(0.0, math.log(10.0)))))
+            batch = graphgen.insertion_batch(cur[gid], size, rng)
+            cur[gid] = graphgen.add_edges(cur[gid], batch)
+            plan.append((float(t), gid, "update", batch, True))
         else:
-            plan.append((float(t), gid, "query", []))
+            plan.append((float(t), gid, "query", [], False))
     log("serving: %d graphs, %d requests planned (%.1f s)" % (graphs, n_req, time.perf_counter() - t_gen))
     srv = Server(budget_bytes=32 << 30, update_share=4 << 30)
     try:
@@ -102,11 +108,11 @@ def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: fl
         log("serving: %d x %d resident trees drawn (%.1f s)" % (graphs, samples, time.perf_counter() - t_init))
         reqs = []
         t0 = time.perf_counter()
-        for t, gid, kind, batch in plan:
+        for t, gid, kind, batch, ins in plan:
             now = time.perf_counter() - t0
             if t > now:
                 time.sleep(t - now)
-            r = Request(gid, kind, batch)
+            r = Request(gid, kind, batch, insert=ins)
             reqs.append(r)
             srv.submit(r)
         while srv.drain(timeout=20.0) < len(reqs):
@@ -116,7 +122,8 @@ def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: fl
         return {
             "workload": "%d resident graphs (cycle of grid, road-like, Chung-Lu types), %d-%d vertices "
                         "log-uniform, %d trees each; Poisson arrivals at %.0f requests/s for %.0f s, "
-                        "80%% queries / 20%% deletion batches (1-1000 edges, prob. ~ d(u)d(v))"
+                        "80%% queries / 20%% update batches: half deletions (1-1000 edges), half "
+                        "insertions (1-10 edges), edges with prob. ~ d(u)d(v)"
                         % (graphs, lo, hi, samples, rate, duration),
             "requests": len(reqs), "errors": errors, "makespan_s": makespan,
             "throughput_req_per_s": len(reqs) / makespan,
@@ -125,6 +132,80 @@ def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: fl
         }
     finally:
         srv.close()
+
+
+def study_graphs(points: int):
+    """The three synthetic shapes at a reduced size: the 32x32 grid (exact
+    kappa known), road-like and social-like graphs of about `points` vertices."""
+    import graphgen
+    return [("grid 32x32", graphgen.grid(32, 32), 3400.358743308690),
+            ("road-like %d points" % points, graphgen.road_like(points, seed=0), None),
+            ("social-like %d vertices" % points, graphgen.chung_lu(points, 2.2, 10.0, 5000.0, seed=0), None)]
+
+
+def study_paths(points: int, samples: int, seed: int):
+    """Section 5, Exp-II: the reference tree tau0 (breadth-first, depth-first,
+    a uniform random spanning tree) against the spread of f/2m.  The same
+    resident trees are evaluated under each tau0, so the comparison is paired;
+    the traversal time is that of re-evaluating all of them."""
+    import torch
+    import paper_2511_16356_amd as kc
+    rows = []
+    for name, g, exact in study_graphs(points):
+        with kc.Graph.from_graph(g) as G:
+            t0 = time.perf_counter()
+            G.samples_init(seed, samples)
+            torch.cuda.synchronize()
+            t_sample = time.perf_counter() - t0
+            rand_tau0 = G.sample_trees(seed + 1, 0, 1, popcounts=False, steps=False)[0][0].cpu().numpy()
+            for label, kind, par in (("bfs", kc.KC_TAU0_BFS, None), ("dfs", kc.KC_TAU0_DFS, None),
+                                     ("wilson", kc.KC_TAU0_GIVEN, rand_tau0)):
+                t0 = time.perf_counter()
+                G.set_tau0(kind, par)
+                torch.cuda.synchronize()
+                t_eval = time.perf_counter() - t0
+                est = G.samples_query()
+                rel_sd = est.std_error * math.sqrt(samples) / est.kappa
+                row = {"graph": name, "n": g.n, "m": g.two_m // 2, "tau0": label, "depth0": G.info["depth0"],
+                       "samples": samples, "kappa": est.kappa, "rel_sd_per_tree": rel_sd,
+                       "rel_ci95": 1.959963984540054 * est.std_error / est.kappa,
+                       "sampling_s": t_sample, "reevaluate_s": t_eval}
+                if exact:
+                    row["rel_error_vs_exact"] = est.kappa / exact - 1.0
+                rows.append(row)
+                log("%s tau0=%s depth0=%d kappa=%.2f rel_sd=%.4f eval %.2f s" %
+                    (name, label, row["depth0"], est.kappa, rel_sd, t_eval))
+    return {"study": "reference tree tau0 (section 5, Exp-II)", "seed": seed, "rows": rows}
+
+
+def study_roots(points: int, samples: int, seed: int):
+    """Section 5, Exp-III: the root's degree against the sampling time.  Roots
+    of degree closest to d_max/5, 2 d_max/5, ..., d_max (the smallest such
+    index), each timed over the same sample ids."""
+    import numpy as np
+    import torch
+    import paper_2511_16356_amd as kc
+    rows = []
+    for name, g, _ in study_graphs(points)[1:]:
+        deg = np.diff(g.offsets)
+        dmax = int(deg.max())
+        for k in range(1, 6):
+            target = k * dmax / 5.0
+            root = int(np.argmin(np.abs(deg - target)))
+            with kc.Graph.from_graph(g, root=root) as G:
+                G.reserve(samples)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                est = G.estimate(seed, 0, samples)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                rows.append({"graph": name, "n": g.n, "root": root, "root_degree": int(deg[root]),
+                             "target_degree": target, "samples": samples, "seconds": dt,
+                             "samples_per_s": samples / dt, "draws_per_sample": est.total_steps / samples,
+                             "kappa": est.kappa, "rel_ci95": 1.959963984540054 * est.std_error / est.kappa})
+                log("%s root %d (deg %d) %.2f s draws/sample %.0f kappa %.1f" %
+                    (name, root, deg[root], dt, est.total_steps / samples, est.kappa))
+    return {"study": "root degree (section 5, Exp-III)", "seed": seed, "rows": rows}
 
 
 def kernel_sha() -> str:
@@ -159,6 +240,11 @@ def main():
     ap.add_argument("--serve-graphs", type=int, default=8)
     ap.add_argument("--serve-rate", type=float, default=5.0, help="requests per second")
     ap.add_argument("--serve-seconds", type=float, default=12.0)
+    ap.add_argument("--study", choices=["tau0", "root"], default=None,
+                    help="instead of the benchmark, run the reference-tree (Exp-II) or root-degree "
+                         "(Exp-III) study on reduced graphs and print its JSON line")
+    ap.add_argument("--study-points", type=int, default=100_000)
+    ap.add_argument("--study-samples", type=int, default=512)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -169,6 +255,12 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(samples shard trivially by index; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.study:
+        import torch
+        torch.cuda.set_device(0)
+        fn = study_paths if args.study == "tau0" else study_roots
+        print(json.dumps(fn(args.study_points, args.study_samples, args.seed)), flush=True)
+        return
 
     import torch
     import graphgen

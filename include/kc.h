@@ -58,11 +58,23 @@ typedef struct {
     int64_t n;          /* vertices */
     int64_t two_m;      /* sum of degrees = 2 |E| */
     int32_t root;       /* r: highest degree, smallest index on ties, unless given */
-    int32_t depth0;     /* depth of the BFS tree tau0 = eccentricity of r */
+    int32_t depth0;     /* depth of tau0 (for the BFS rule: the eccentricity of r) */
     int32_t max_degree;
     int32_t traversal;  /* KC_TRAV_WALK or KC_TRAV_SWEEP, as chosen for this graph */
     int64_t device_bytes; /* graph arrays resident on the device */
+    int32_t tau0;       /* KC_TAU0_* rule tau0 is built with */
 } kc_graph_info;
+
+/* How tau0, the fixed spanning tree whose root paths define the path mapping,
+ * is chosen (Theorem 3.4 holds for any spanning tree; section 5, Exp-II
+ * compares breadth-first, depth-first and random trees). */
+enum {
+    KC_TAU0_BFS = 0,   /* breadth-first from r, parent = smallest-index neighbour one level up
+                          (Algorithm 1; the default) */
+    KC_TAU0_DFS = 1,   /* depth-first from r, rows scanned in ascending order, parent = the
+                          vertex a vertex is discovered from */
+    KC_TAU0_GIVEN = 2  /* a spanning tree the caller supplies (kc_set_tau0) */
+};
 
 /* Traversal variants for f(tau) (Theorem 3.4); results are identical. */
 enum {
@@ -113,6 +125,24 @@ kc_status kc_graph_get_info(const kc_graph *g, kc_graph_info *info);
 
 /* Set a KC_OPT_* option.  KC_ERR_INVALID for an unknown option or value. */
 kc_status kc_set_option(kc_graph *g, int option, int64_t value);
+
+/*
+ * Choose tau0 (KC_TAU0_*).  f(tau) changes with tau0 tree by tree, its mean
+ * over uniform trees does not (Theorem 3.4); a tau0 with shorter root paths
+ * gives a smaller variance (section 5, Exp-II).  Trees already drawn keep
+ * their parent arrays; the resident set's f values are recomputed on the new
+ * tau0.  Updates (kc_apply_updates) rebuild tau0 with the same rule on the new
+ * graph; a given tree is kept while all its edges remain and gives way to
+ * KC_TAU0_BFS when one of them is deleted.
+ *   kind   : KC_TAU0_BFS, KC_TAU0_DFS or KC_TAU0_GIVEN
+ *   parent : HOST pointer, n int32, read for KC_TAU0_GIVEN only (copied):
+ *            parent[r] = -1 and, for every other v, (v, parent[v]) an edge of
+ *            the graph, with every vertex reaching r
+ * Errors: KC_ERR_INVALID (unknown kind; a given array that is not a spanning
+ * tree of the graph rooted at r), KC_ERR_OVERFLOW (4 m^2 depth(tau0) >= 2^63),
+ * KC_ERR_NOMEM, KC_ERR_DEVICE.  On an error nothing changes.
+ */
+kc_status kc_set_tau0(kc_graph *g, int kind, const int32_t *parent, void *hip_stream);
 
 /*
  * Allocate, ahead of time, the device workspace that kc_estimate needs for
@@ -220,20 +250,35 @@ kc_status kc_samples_get(const kc_graph *g, int32_t *parents_out, int64_t *f_out
                          void *hip_stream);
 
 /*
- * Apply a batch of edge updates (section 4.1, Algorithm 2: basic sample
- * maintenance).  This version supports deletions: each (u[k], v[k]) must be
- * an edge of the graph, all distinct; is_insert may be NULL or all zero.
- * The graph becomes G' = G minus the batch, which must stay connected.
- * tau0 and every per-graph array are rebuilt on G' with the same root.
- * Resident trees that contain a deleted edge are replaced by fresh uniform
- * spanning trees of G' (the set's seed, the next unused sample indices, in
- * slot order); the others are uniform on G' already (Theorem 4.2).  f is
- * recomputed for every resident tree on G', since degrees, 2m and tau0 change.
- *   u, v, is_insert : HOST pointers, count entries
+ * Apply a list of edge updates (section 4.1, Algorithm 2: basic sample
+ * maintenance), in order.  A run of consecutive deletions is applied at
+ * once; each insertion is applied on its own.  tau0 and every per-graph array
+ * are rebuilt on the new graph with the same root, and f is recomputed for
+ * every resident tree, since degrees, 2m and tau0 change.
+ *   Deletion of (u, v), an edge of the graph (distinct within a run): the
+ *     graph after the run must stay connected.  Resident trees that contain
+ *     a deleted edge are replaced by fresh uniform spanning trees of the new
+ *     graph (the set's seed, the next unused sample indices, in slot order);
+ *     the others are uniform on it already (Theorem 4.2).
+ *   Insertion of (u, v), not an edge of the graph: R(u, v) on the graph
+ *     before it is estimated from the resident trees (the signed count of
+ *     the edges of a fixed breadth-first u -> v path that each tree's own
+ *     u -> v path uses; its mean is R(u, v)).  Each resident tree is then
+ *     replaced independently with probability R / (1 + R), the probability
+ *     that a uniform spanning tree of the new graph uses the new edge
+ *     (Theorem 4.1), by the draw (x >> 11) * 2^-53 with x the first two words
+ *     of Philox4x32-10, key (seed_lo, seed_hi), counter (slot, number of
+ *     insertions applied to the set so far, 2^32-1, 2^32-1).  A replacement
+ *     is a uniform spanning tree through the new edge: Wilson's algorithm with
+ *     u and v in the tree from the start (next unused sample index), the edge
+ *     v -> u added, and the path from the root re-oriented toward it.
+ *   u, v, is_insert : HOST pointers, count entries (is_insert NULL: all deletions)
  *   resampled       : HOST pointer or NULL, receives how many trees were replaced
- * Errors: KC_ERR_INVALID (not an edge, duplicate, bad vertex),
- * KC_ERR_UNSUPPORTED (an insertion), KC_ERR_DISCONNECTED (G' not connected;
- * the graph and the set are left unchanged), and those of kc_sample_trees.
+ * Errors: KC_ERR_INVALID (a deletion that is not an edge, a duplicate within a
+ * run, an insertion of an existing edge, a bad vertex), KC_ERR_DISCONNECTED
+ * (a deletion run would disconnect the graph), KC_ERR_OVERFLOW (2m would
+ * reach 2^31), and those of kc_sample_trees.  Updates before the failing one
+ * stay applied; the failing one changes nothing.
  */
 kc_status kc_apply_updates(kc_graph *g, const int32_t *u, const int32_t *v, const uint8_t *is_insert,
                            int32_t count, int32_t *resampled, void *hip_stream);

@@ -24,9 +24,11 @@ KC_TRAV_AUTO, KC_TRAV_WALK, KC_TRAV_SWEEP = 0, 1, 2
 KC_OPT_WALKERS, KC_OPT_SLOTS, KC_OPT_TRAVERSAL, KC_OPT_STEP_LIMIT, KC_OPT_MEM_BUDGET = 1, 2, 3, 4, 5
 KC_OPT_START_ORDER = 6
 KC_OPT_CHAINS = 7
+KC_TAU0_BFS, KC_TAU0_DFS, KC_TAU0_GIVEN = 0, 1, 2
 
 # every symbol include/kc.h declares
-EXPORTS = ("kc_graph_create", "kc_graph_destroy", "kc_graph_get_info", "kc_set_option", "kc_reserve", "kc_progress",
+EXPORTS = ("kc_graph_create", "kc_graph_destroy", "kc_graph_get_info", "kc_set_option", "kc_set_tau0",
+           "kc_reserve", "kc_progress",
            "kc_samples_init", "kc_samples_query", "kc_samples_get", "kc_apply_updates",
            "kc_sample_trees", "kc_estimate", "kc_evaluate_trees", "kc_status_string",
            "kc_last_error")
@@ -42,7 +44,7 @@ class KcError(RuntimeError):
 class _Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("two_m", ctypes.c_int64), ("root", ctypes.c_int32),
                 ("depth0", ctypes.c_int32), ("max_degree", ctypes.c_int32),
-                ("traversal", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+                ("traversal", ctypes.c_int32), ("device_bytes", ctypes.c_int64), ("tau0", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -73,6 +75,8 @@ def library() -> ctypes.CDLL:
     lib.kc_graph_get_info.argtypes = [p, ctypes.POINTER(_Info)]
     lib.kc_set_option.restype = ctypes.c_int
     lib.kc_set_option.argtypes = [p, ctypes.c_int, i64]
+    lib.kc_set_tau0.restype = ctypes.c_int
+    lib.kc_set_tau0.argtypes = [p, ctypes.c_int, p, p]
     lib.kc_samples_init.restype = ctypes.c_int
     lib.kc_samples_init.argtypes = [p, u64, i32, p]
     lib.kc_samples_query.restype = ctypes.c_int
@@ -173,6 +177,18 @@ class Graph:
 
     def set_option(self, option: int, value: int):
         _check(library().kc_set_option(self._h, option, int(value)))
+        self.info = self._info()
+
+    def set_tau0(self, kind: int, parent=None, stream=None):
+        """Rebuild tau0 by rule `kind` (KC_TAU0_BFS / KC_TAU0_DFS), or adopt the
+        spanning tree `parent` (host int array, parent[root] = -1) for KC_TAU0_GIVEN."""
+        arr = None
+        if parent is not None:
+            arr = np.ascontiguousarray(parent, dtype=np.int32)
+            if arr.shape != (self.n,):
+                raise ValueError("tau0 parent array must have n entries")
+        _check(library().kc_set_tau0(self._h, int(kind), None if arr is None else arr.ctypes.data_as(ctypes.c_void_p),
+                                     _stream(stream)))
         self.info = self._info()
 
     def progress(self) -> int:

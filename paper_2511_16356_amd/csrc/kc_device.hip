@@ -175,7 +175,8 @@ enum : int {
     M_ADJ = 4,     // the drawn neighbour lies beyond the inline ones: fetch it
     M_ERASE0 = 5,  // popping: load the kept vertex `tgt` (the new head)
     M_ERASE = 6,   // popping: free `tgt`, follow next until `stopv`
-    M_RETRACE = 7  // path met the tree: mark from `tgt` until `stopv`
+    M_RETRACE = 7, // path met the tree: mark from `tgt` until `stopv`
+    M_RETRACE0 = 8 // path met the tree: read the chain's start vertex first
 };
 
 template <int CH>
@@ -217,13 +218,16 @@ struct SamplerWS {
 template <int CH>
 __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerShared<CH> &sh,
                                uint64_t seed, uint64_t s, int walkers, int64_t iter_cap,
-                               int32_t *ctl, int idx, int64_t *iters_used) {
+                               int32_t *ctl, int idx, int64_t *iters_used, int32_t root_u,
+                               int32_t root_v) {
     const int lane = threadIdx.x;
     const int n = g.n, root = g.root;
+    const bool two_roots = root_u >= 0;  // start from {u, v} instead of {root}
     uint64_t *__restrict__ tagw = ws.tagw;
     uint64_t *__restrict__ arw = ws.arrow;
     for (int v = lane; v < n; v += WAVE) {
-        astore(&tagw[v], (uint64_t)(v == root ? T_TREE : T_FREE));
+        const bool in_tree = two_roots ? (v == root_u || v == root_v) : v == root;
+        astore(&tagw[v], (uint64_t)(in_tree ? T_TREE : T_FREE));
         astore(&arw[v], arrow_of(-1, 0));
     }
     for (int c = lane; c < CH; c += WAVE) {
@@ -288,9 +292,15 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             const int take_h = min(min(left, room), hint_top);
             if (worker && mode == M_IDLE) {
                 const int r = rank_in(idle);
+                const int k = r - take_q;
                 pend = false;
+                // each lane reads all four sources at clamped, always valid indices and
+                // keeps the one it needs: no load waits on another lane's
+                const int4 t = ws.queue[(q_head + max(0, min(r, take_q - 1))) & (CH - 1)];
+                const int32_t t_rq = aload(&ws.rq[(rq_head + max(0, min(k, take_r - 1))) % n]);
+                const int32_t t_ord = aload(&g.order[max(0, min(next_start + k - take_r, n - 1))]);
+                const int32_t t_hint = sh.hint[max(0, min(hint_top - 1 - (k - take_r - take_s), HINTS - 1))];
                 if (r < take_q) {
-                    const int4 t = ws.queue[(q_head + r) & (CH - 1)];
                     chain = t.x;
                     ctag = T_CHAIN0 + (uint32_t)chain;
                     if (t.y == T_RESUME) {
@@ -298,21 +308,17 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
                         haspath = true;
                         mode = M_LOOK;
                     } else if (t.y == T_RETRACE) {
-                        tgt = aload(&ws.start[chain]);
                         stopv = t.z;
-                        mode = M_RETRACE;
+                        mode = M_RETRACE0;
                     } else {
                         tgt = t.z;
                         stopv = t.w;
                         mode = M_ERASE0;
                     }
-                } else if (r < take_q + take_r + take_s + take_h) {
-                    const int k = r - take_q;
+                } else if (k < take_r + take_s + take_h) {
                     chain = sh.freestk[free_top - 1 - k];
                     ctag = T_CHAIN0 + (uint32_t)chain;
-                    if (k < take_r) tgt = aload(&ws.rq[(rq_head + k) % n]);
-                    else if (k < take_r + take_s) tgt = g.order[next_start + (k - take_r)];
-                    else tgt = sh.hint[hint_top - 1 - (k - take_r - take_s)];
+                    tgt = k < take_r ? t_rq : (k < take_r + take_s ? t_ord : t_hint);
                     astore(&ws.start[chain], tgt);
                     haspath = false;
                     mode = M_LOOK;
@@ -331,7 +337,8 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             break;
         }
         if (++iters > iter_cap) err = DEV_LIMIT;
-        if (err == 0 && mode != M_IDLE && mode != M_ADJ && (unsigned)tgt >= (unsigned)n) err = DEV_PROTOCOL;
+        if (err == 0 && mode != M_IDLE && mode != M_ADJ && mode != M_RETRACE0 && (unsigned)tgt >= (unsigned)n)
+            err = DEV_PROTOCOL;
         if (err == 0 && mode == M_ADJ && (unsigned)adjpos >= (unsigned)g.two_m) err = DEV_PROTOCOL;
         const int m0 = err == 0 ? mode : M_IDLE;
 
@@ -341,18 +348,20 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
         const bool do_arrow = m0 == M_LOOK || m0 == M_ERASE0 || do_xchg;
         const bool do_rec = m0 == M_LOOK || m0 == M_ERASE0;
         if (m0 == M_LOOK && pend) astore(&arw[cur], arrow_of(tgt, dcur));
-        uint64_t o64 = 0;
+        // (each operation returns into a register of its own: a shared one would make
+        // every later issue wait for the earlier operations' results)
+        uint64_t o_cas = 0, o_xchg = 0, o_tag = 0;
         if (do_cas) {
             const uint64_t expect = m0 == M_LOOK ? (uint64_t)T_FREE : seen;
             const uint64_t want = m0 == M_LOOK ? (uint64_t)ctag
                                 : m0 == M_PARK ? ((seen & 0xffffffffull) | ((uint64_t)(chain + 1) << 32))
                                                : (seen | TW_NEED);
-            o64 = acas(&tagw[tgt], expect, want);
+            o_cas = acas(&tagw[tgt], expect, want);
         }
         if (do_xchg)
-            o64 = __hip_atomic_exchange(&tagw[tgt], (uint64_t)(m0 == M_ERASE ? T_FREE : T_TREE),
-                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (m0 == M_ERASE0) o64 = aload(&tagw[tgt]);
+            o_xchg = __hip_atomic_exchange(&tagw[tgt], (uint64_t)(m0 == M_ERASE ? T_FREE : T_TREE),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (m0 == M_ERASE0) o_tag = aload(&tagw[tgt]);
         uint64_t ar = 0;
         if (do_arrow) ar = aload(&arw[tgt]);
         int4 r0 = make_int4(0, 0, 0, 0), r1 = make_int4(0, 0, 0, 0);
@@ -366,6 +375,9 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
         };
         int32_t y = -1;
         if (m0 == M_ADJ) y = g.adj[adjpos];
+        int32_t st0 = -1;
+        if (m0 == M_RETRACE0) st0 = aload(&ws.start[chain]);
+        const uint64_t o64 = do_cas ? o_cas : (do_xchg ? o_xchg : o_tag);
 
         // ---- apply the results
         bool retire = false, park = false, drawing = false;
@@ -387,8 +399,7 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             } else if (tg == T_TREE) {
                 if (haspath) {
                     stopv = tgt;
-                    tgt = aload(&ws.start[chain]);
-                    mode = M_RETRACE;
+                    mode = M_RETRACE0;
                 } else {
                     retire = true;  // a fresh chain whose start is already in the tree
                 }
@@ -420,8 +431,7 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             } else if (tg == T_TREE) {
                 if (m0 == M_PARK) {
                     stopv = tgt;
-                    tgt = aload(&ws.start[chain]);
-                    mode = M_RETRACE;
+                    mode = M_RETRACE0;
                 } else {
                     retire = true;
                 }
@@ -434,6 +444,9 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             tgt = y;
             pend = true;
             mode = M_LOOK;
+        } else if (m0 == M_RETRACE0) {
+            tgt = st0;
+            mode = M_RETRACE;
         } else if (m0 == M_ERASE) {
             if (tg != ctag) err = DEV_PROTOCOL;
             wake_head = (int)(o64 >> 32) - 1;
@@ -839,6 +852,42 @@ __device__ int64_t f_sweep(const GraphDev &g, const SlotPtrs &sp, int64_t fen_le
     return wave_sum(acc);
 }
 
+// Signed count of the edges of a fixed u -> v path that the tree's own u -> v
+// path uses (+1 along the path's direction, -1 against it); its mean over
+// uniform spanning trees is the effective resistance R(u, v) (Kirchhoff: the
+// tree path's direction on an edge has mean equal to the unit current there,
+// and currents summed along any u -> v path give the potential difference).
+// Ancestry from the tree numbering: x is an ancestor of y (or y itself) iff
+// tin(x) <= tin(y) < tin(x) + vol(x).
+__device__ int64_t path_current(const SlotPtrs &sp, const int32_t *path, int len) {
+    const int lane = threadIdx.x;
+    const int u = path[0], v = path[len - 1];
+    auto tinv = [&](int x, uint32_t &t, uint32_t &vol) {
+        const uint64_t r = aload(&sp.rec[2 * (size_t)x]);
+        t = (uint32_t)r;
+        vol = (uint32_t)(r >> 32);
+    };
+    uint32_t tu, vu, tv, vv;
+    tinv(u, tu, vu);
+    tinv(v, tv, vv);
+    auto anc_u = [&](uint32_t t, uint32_t vol) { return t <= tu && tu < t + vol; };
+    auto anc_v = [&](uint32_t t, uint32_t vol) { return t <= tv && tv < t + vol; };
+    int64_t c = 0;
+    for (int i = lane; i + 1 < len; i += WAVE) {
+        const int a = path[i], b = path[i + 1];
+        uint32_t ta, va, tb, vb;
+        tinv(a, ta, va);
+        tinv(b, tb, vb);
+        const int32_t pa = (int32_t)aload(&sp.rec[2 * (size_t)a + 1]);
+        const int32_t pb = (int32_t)aload(&sp.rec[2 * (size_t)b + 1]);
+        const bool up_a = anc_u(ta, va) && !anc_v(ta, va), up_b = anc_u(tb, vb) && !anc_v(tb, vb);
+        const bool dn_a = anc_v(ta, va) && !anc_u(ta, va), dn_b = anc_v(tb, vb) && !anc_u(tb, vb);
+        if ((up_a && pa == b) || (dn_b && pb == a)) c += 1;
+        else if ((up_b && pb == a) || (dn_a && pa == b)) c -= 1;
+    }
+    return wave_sum(c);
+}
+
 // ------------------------------------------------------------ the kernels
 
 // The sampler and the sweep run one after the other: one LDS block serves both.
@@ -875,8 +924,9 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
         if (__hip_atomic_load(&rp.ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
         const uint64_t s = (uint64_t)(rp.first + idx);
         int64_t steps = 0, iters = 0;
-        if (rp.mode != RUN_EVALUATE) {
-            steps = sample_tree<CH>(g, sp.ws, lds.samp, rp.seed, s, rp.walkers, rp.iter_cap, rp.ctl, idx, &iters);
+        if (rp.mode == RUN_SAMPLE || rp.mode == RUN_ESTIMATE) {
+            steps = sample_tree<CH>(g, sp.ws, lds.samp, rp.seed, s, rp.walkers, rp.iter_cap, rp.ctl, idx, &iters,
+                                    rp.root_u, rp.root_v);
             if (steps < 0) break;
         }
         if (rp.mode == RUN_SAMPLE) {
@@ -884,7 +934,7 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
             uint32_t *co = rp.cnt_out ? rp.cnt_out + (size_t)idx * n : nullptr;
             for (int v = lane; v < g.n; v += WAVE) {
                 const uint64_t ar = aload(&sp.ws.arrow[v]);
-                po[v] = (v == g.root) ? -1 : (int32_t)(uint32_t)ar;
+                po[v] = (int32_t)(uint32_t)ar;  // -1 at vertices that started in the tree
                 if (co) co[v] = (uint32_t)(ar >> 32);
             }
         } else {
@@ -895,7 +945,7 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
                 if (v == g.root) {
                     p = -1;
                 } else {
-                    p = (rp.mode == RUN_EVALUATE) ? rp.parents_in[(size_t)idx * n + v]
+                    p = (rp.mode != RUN_ESTIMATE) ? rp.parents_in[(size_t)idx * n + v]
                                                   : (int32_t)(uint32_t)aload(&sp.ws.arrow[v]);
                     if (p < 0 || p >= g.n || p == v) { bad = true; p = g.root; }
                 }
@@ -905,7 +955,8 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
             bool ok = tree_numbering(g, sp);
             if (__ballot(bad) != 0ull) ok = false;
             int64_t f = 0;
-            if (rp.traversal == 2) f = f_sweep(g, sp, sd.fen_len, lds.sweep);
+            if (rp.mode == RUN_CURRENT) f = path_current(sp, rp.path, rp.path_len);
+            else if (rp.traversal == 2) f = f_sweep(g, sp, sd.fen_len, lds.sweep);
             else f = f_walk(g, sp);
             if (!ok) report_error(rp.ctl, DEV_BADTREE, idx);
             if (lane == 0) rp.f_out[idx] = f;
@@ -931,6 +982,23 @@ __global__ void flag_trees_kernel(const int32_t *par, int32_t count, int64_t n, 
         const int32_t u = eu[k], v = ev[k];
         const int32_t *row = par + t * n;
         if (row[u] == v || row[v] == u) flags[t] = 1;
+    }
+}
+
+// Trees drawn with u and v in the tree from the start (a two-tree forest
+// rooted at u and v): add the edge v -> u, then re-orient the path from r so
+// that every vertex points toward r.  One thread per tree.
+__global__ void reroot_kernel(int32_t *par, int32_t count, int64_t n, int32_t u, int32_t v, int32_t r) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    int32_t *row = par + (int64_t)t * n;
+    row[v] = u;
+    int32_t prev = -1, x = r;
+    for (int64_t guard = 0; x != -1 && guard <= n; ++guard) {
+        const int32_t nx = row[x];
+        row[x] = prev;
+        prev = x;
+        x = nx;
     }
 }
 
@@ -1030,6 +1098,14 @@ int persistent_blocks_per_cu(int chains) {
 hipError_t launch_reduce(const int64_t *f, const int64_t *steps, const int64_t *iters, int32_t count,
                          ReduceOut *out, hipStream_t stream) {
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, stream, f, steps, iters, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reroot(int32_t *par, int32_t count, int64_t n, int32_t u, int32_t v, int32_t r,
+                         hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reroot_kernel, dim3((unsigned)((count + 63) / 64)), dim3(64), 0, stream, par, count, n,
+                       u, v, r);
     return hipGetLastError();
 }
 

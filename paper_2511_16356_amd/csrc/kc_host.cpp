@@ -69,6 +69,8 @@ struct kc_graph {
     int64_t graph_bytes = 0;
     int32_t nblk = 0;
     int32_t start_order = 2;
+    int32_t tau0_kind = KC_TAU0_BFS;  // rule that builds tau0 on every (re)build
+    std::vector<int32_t> h_tau0;     // the caller's tau0 when tau0_kind == KC_TAU0_GIVEN
     std::vector<int32_t> bfs_order;  // host copy of the BFS order from the root
     std::vector<int64_t> h_off;      // host copy of the current CSR
     std::vector<int32_t> h_adj;
@@ -76,6 +78,7 @@ struct kc_graph {
     int32_t res_count = 0;
     uint64_t res_seed = 0;
     int64_t res_next = 0;             // next unused sample index
+    int64_t res_serial = 0;           // insertions applied so far (counter of their draws)
     std::vector<int64_t> res_ids;     // sample index of each resident tree
     int32_t *d_res_par = nullptr;     // [res_count * n] parents
     int64_t *d_res_f = nullptr;       // [res_count] f of each tree on the current graph
@@ -87,6 +90,7 @@ struct kc_graph {
     // workspace
     int ws_slots = 0;
     bool ws_trav = false, ws_fen = false;
+    int64_t ws_fen_len = 0;  // per-slot Fenwick length the buffer was sized for (2m + 2)
     uint64_t *d_tagw = nullptr, *d_arrow = nullptr;
     int32_t *d_rq = nullptr;
     int4 *d_queue = nullptr;
@@ -162,7 +166,9 @@ int64_t slot_bytes(const kc_graph *g, bool trav, bool fen) {
 // Make sure at least `want` slots of workspace exist; returns the usable count.
 kc_status ensure_workspace(kc_graph *g, int want, bool trav, bool fen, hipStream_t stream, int *got) {
     if (want < 1) want = 1;
-    if (g->ws_slots >= want && (!trav || g->ws_trav) && (!fen || g->ws_fen)) {
+    // the sweep's per-slot stride is 2m + 2: a graph that gained edges needs a new buffer
+    const bool fen_small = fen && g->ws_fen && g->ws_fen_len < g->two_m + 2;
+    if (g->ws_slots >= want && (!trav || g->ws_trav) && (!fen || g->ws_fen) && !fen_small) {
         *got = want;
         return KC_OK;
     }
@@ -199,6 +205,7 @@ kc_status ensure_workspace(kc_graph *g, int want, bool trav, bool fen, hipStream
     g->ws_slots = slots;
     g->ws_trav = trav;
     g->ws_fen = fen;
+    g->ws_fen_len = fen ? g->two_m + 2 : 0;
     *got = slots;
     return KC_OK;
 }
@@ -299,14 +306,69 @@ kc_status run_persistent(kc_graph *g, kc::RunParams rp, hipStream_t stream) {
     return KC_OK;
 }
 
+// Philox4x32-10 (Salmon et al., SC'11) on the host: ten rounds of two 32x32
+// products with the Weyl key increments.
+void philox_host(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3], k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = (uint64_t)0xD2511F53u * x0;
+        const uint64_t b = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t y0 = (uint32_t)(b >> 32) ^ x1 ^ k0;
+        const uint32_t y2 = (uint32_t)(a >> 32) ^ x3 ^ k1;
+        x0 = y0; x1 = (uint32_t)b; x2 = y2; x3 = (uint32_t)a;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+// The replacement draw of resident tree `slot` at insertion number `serial`:
+// counter (slot, serial, 2^32-1, 2^32-1), which no tree sample uses; the first
+// two output words as a 64-bit x, uniform = (x >> 11) * 2^-53 in [0, 1).
+double update_uniform(uint64_t seed, uint32_t slot, uint32_t serial) {
+    const uint32_t ctr[4] = {slot, serial, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t o[4];
+    philox_host(ctr, key, o);
+    const uint64_t x = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
+    return (double)(x >> 11) * 0x1.0p-53;
+}
+
+// A fixed u -> v path: breadth-first search from u (rows ascending), each
+// vertex reached from the first vertex that reaches it.
+std::vector<int32_t> reference_path(const std::vector<int64_t> &off, const std::vector<int32_t> &adj,
+                                    int32_t u, int32_t v) {
+    const int64_t n = (int64_t)off.size() - 1;
+    std::vector<int32_t> pred((size_t)n, -1), q;
+    pred[(size_t)u] = u;
+    q.push_back(u);
+    for (size_t h = 0; h < q.size() && pred[(size_t)v] < 0; ++h) {
+        const int32_t x = q[h];
+        for (int64_t e = off[(size_t)x]; e < off[(size_t)x + 1]; ++e) {
+            const int32_t y = adj[(size_t)e];
+            if (pred[(size_t)y] < 0) { pred[(size_t)y] = x; q.push_back(y); }
+        }
+    }
+    std::vector<int32_t> path;
+    if (pred[(size_t)v] < 0) return path;
+    for (int32_t x = v;; x = pred[(size_t)x]) {
+        path.push_back(x);
+        if (x == u) break;
+    }
+    std::reverse(path.begin(), path.end());
+    return path;
+}
+
 // (Re)build every per-graph array from the host CSR in g->h_off / g->h_adj:
-// root (highest degree, smallest index, unless given), tau0 (BFS, parent =
-// smallest-index neighbour one level up), tau0 preorder and subtree ends, the
-// per-block open-subtree lists, the walk start order and the per-vertex graph
-// records; then replace the device copies.  On failure the graph is unchanged
-// only if nothing was uploaded yet (callers validate first).
+// root (highest degree, smallest index, unless given), tau0 (by `tau0_kind`:
+// BFS with parent = smallest-index neighbour one level up, depth-first from the
+// root with rows in ascending order, or the caller's tree in `given`), tau0
+// preorder and subtree ends, the per-block open-subtree lists, the walk start
+// order and the per-vertex graph records; then replace the device copies.  On
+// failure the graph is unchanged only if nothing was uploaded yet (callers
+// validate first).
 kc_status prepare_graph(const std::vector<int64_t> &off, const std::vector<int32_t> &adj, int32_t root,
-                        PreparedGraph *pg) {
+                        int tau0_kind, const std::vector<int32_t> *given, PreparedGraph *pg) {
     const int64_t n = (int64_t)off.size() - 1;
     const int64_t nnz = off[(size_t)n];
     const int32_t *indices = adj.data();
@@ -338,17 +400,66 @@ kc_status prepare_graph(const std::vector<int64_t> &off, const std::vector<int32
     }
     if ((int64_t)order.size() != n)
         return fail(KC_ERR_DISCONNECTED, "only %zu of %lld vertices reachable from the root", order.size(), (long long)n);
-    // tau0: parent = smallest-index neighbour one level up
     std::vector<int32_t> &p0 = pg->p0;
     p0.assign((size_t)n, -1);
     int32_t depth0 = 0;
-    for (int64_t v = 0; v < n; ++v) {
-        depth0 = std::max(depth0, dist[(size_t)v]);
-        if (v == root) continue;
-        for (int64_t e = off[(size_t)v]; e < off[(size_t)v + 1]; ++e) {
-            const int32_t u = indices[e];
-            if (dist[(size_t)u] == dist[(size_t)v] - 1) { p0[(size_t)v] = u; break; }  // rows ascending
+    if (tau0_kind == KC_TAU0_BFS) {
+        // parent = smallest-index neighbour one level up
+        for (int64_t v = 0; v < n; ++v) {
+            depth0 = std::max(depth0, dist[(size_t)v]);
+            if (v == root) continue;
+            for (int64_t e = off[(size_t)v]; e < off[(size_t)v + 1]; ++e) {
+                const int32_t u = indices[e];
+                if (dist[(size_t)u] == dist[(size_t)v] - 1) { p0[(size_t)v] = u; break; }  // rows ascending
+            }
         }
+    } else if (tau0_kind == KC_TAU0_DFS) {
+        // depth-first search from the root, each row scanned in ascending order;
+        // a vertex's parent is the vertex it was discovered from
+        std::vector<int64_t> pos((size_t)n);
+        std::vector<int32_t> depth((size_t)n, -1), stack;
+        stack.push_back(root);
+        depth[(size_t)root] = 0;
+        pos[(size_t)root] = off[(size_t)root];
+        while (!stack.empty()) {
+            const int32_t x = stack.back();
+            if (pos[(size_t)x] == off[(size_t)x + 1]) { stack.pop_back(); continue; }
+            const int32_t y = indices[pos[(size_t)x]++];
+            if (depth[(size_t)y] >= 0) continue;
+            depth[(size_t)y] = depth[(size_t)x] + 1;
+            depth0 = std::max(depth0, depth[(size_t)y]);
+            p0[(size_t)y] = x;
+            pos[(size_t)y] = off[(size_t)y];
+            stack.push_back(y);
+        }
+    } else if (tau0_kind == KC_TAU0_GIVEN && given && (int64_t)given->size() == n) {
+        // the caller's tree: parent[root] = -1, every (v, parent[v]) an edge, no cycle
+        const std::vector<int32_t> &t = *given;
+        if (t[(size_t)root] != -1) return fail(KC_ERR_INVALID, "tau0: parent of the root %d must be -1", root);
+        for (int64_t v = 0; v < n; ++v) {
+            if (v == root) continue;
+            const int32_t u = t[(size_t)v];
+            if (u < 0 || u >= n) return fail(KC_ERR_INVALID, "tau0: parent %d of %lld out of range", u, (long long)v);
+            if (!std::binary_search(indices + off[(size_t)v], indices + off[(size_t)v + 1], u))
+                return fail(KC_ERR_INVALID, "tau0: (%lld,%d) is not an edge of the graph", (long long)v, u);
+        }
+        std::vector<int32_t> depth((size_t)n, -1), chain;
+        depth[(size_t)root] = 0;
+        for (int64_t v = 0; v < n; ++v) {
+            int32_t x = (int32_t)v;
+            chain.clear();
+            while (depth[(size_t)x] < 0) {  // at most n steps: a longer chain repeats a vertex
+                if ((int64_t)chain.size() >= n)
+                    return fail(KC_ERR_INVALID, "tau0: the parent array has a cycle through %lld", (long long)v);
+                chain.push_back(x);
+                x = t[(size_t)x];
+            }
+            for (size_t i = chain.size(); i-- > 0;) depth[(size_t)chain[i]] = depth[(size_t)x] + (int32_t)(chain.size() - i);
+        }
+        p0 = t;
+        for (int64_t v = 0; v < n; ++v) depth0 = std::max(depth0, depth[(size_t)v]);
+    } else {
+        return fail(KC_ERR_INVALID, "unknown tau0 rule %d (or a given tree of the wrong size)", tau0_kind);
     }
     pg->depth0 = depth0;
     const unsigned __int128 bound = (unsigned __int128)nnz * (unsigned __int128)nnz * (unsigned __int128)depth0;
@@ -432,7 +543,7 @@ void free_graph_arrays(kc_graph *g) {
 
 kc_status rebuild_graph(kc_graph *g, int32_t root, hipStream_t stream) {
     PreparedGraph pg;
-    const kc_status st = prepare_graph(g->h_off, g->h_adj, root, &pg);
+    const kc_status st = prepare_graph(g->h_off, g->h_adj, root, g->tau0_kind, &g->h_tau0, &pg);
     if (st != KC_OK) return st;
     HIP_TRY(hipStreamSynchronize(stream));  // no running launch reads the old arrays
     free_graph_arrays(g);
@@ -571,6 +682,34 @@ kc_status kc_graph_get_info(const kc_graph *g, kc_graph_info *info) {
     info->max_degree = g->max_degree;
     info->traversal = g->traversal;
     info->device_bytes = g->graph_bytes;
+    info->tau0 = g->tau0_kind;
+    return KC_OK;
+}
+
+kc_status kc_set_tau0(kc_graph *g, int kind, const int32_t *parent, void *hip_stream) {
+    g_last_error.clear();
+    if (!g) return fail(KC_ERR_INVALID, "NULL graph");
+    if (kind != KC_TAU0_BFS && kind != KC_TAU0_DFS && kind != KC_TAU0_GIVEN)
+        return fail(KC_ERR_INVALID, "unknown tau0 rule %d", kind);
+    if (kind == KC_TAU0_GIVEN && !parent) return fail(KC_ERR_INVALID, "tau0 parent array is NULL");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    std::vector<int32_t> given;
+    if (kind == KC_TAU0_GIVEN) given.assign(parent, parent + g->n);
+    {
+        PreparedGraph probe;  // validate before anything changes
+        const kc_status st = prepare_graph(g->h_off, g->h_adj, g->root, kind, &given, &probe);
+        if (st != KC_OK) return st;
+    }
+    g->tau0_kind = kind;
+    g->h_tau0.swap(given);
+    kc_status st = rebuild_graph(g, g->root, stream);
+    if (st != KC_OK) return st;
+    if (g->res_count > 0) {
+        // resident trees are unchanged; their f is taken over the new tau0 (Theorem 3.4)
+        st = kc_evaluate_trees(g, g->d_res_par, g->res_count, g->d_res_f, hip_stream);
+        if (st != KC_OK) return st;
+        HIP_TRY(hipStreamSynchronize(stream));
+    }
     return KC_OK;
 }
 
@@ -771,20 +910,14 @@ kc_status kc_samples_get(const kc_graph *g, int32_t *parents_out, int64_t *f_out
     return KC_OK;
 }
 
-kc_status kc_apply_updates(kc_graph *g, const int32_t *u, const int32_t *v, const uint8_t *is_insert,
-                           int32_t count, int32_t *resampled, void *hip_stream) {
-    g_last_error.clear();
-    if (!g) return fail(KC_ERR_INVALID, "NULL graph");
-    if (count < 0 || (count > 0 && (!u || !v))) return fail(KC_ERR_INVALID, "bad update arrays");
-    if (resampled) *resampled = 0;
-    if (count == 0) return KC_OK;
-    hipStream_t stream = (hipStream_t)hip_stream;
+// A run of deletions, applied at once (Algorithm 2, deletion case).
+static kc_status apply_deletions(kc_graph *g, const int32_t *u, const int32_t *v, int32_t count,
+                                 int32_t *resampled, hipStream_t stream) {
     const int64_t n = g->n;
     // validate: deletions of distinct existing edges
     std::vector<std::pair<int32_t, int32_t>> del;
     del.reserve((size_t)count);
     for (int32_t k = 0; k < count; ++k) {
-        if (is_insert && is_insert[k]) return fail(KC_ERR_UNSUPPORTED, "edge insertion is not supported");
         int32_t a = u[k], b = v[k];
         if (a < 0 || a >= n || b < 0 || b >= n || a == b) return fail(KC_ERR_INVALID, "bad edge (%d,%d)", a, b);
         if (a > b) std::swap(a, b);
@@ -809,9 +942,14 @@ kc_status kc_apply_updates(kc_graph *g, const int32_t *u, const int32_t *v, cons
         }
         noff[(size_t)x + 1] = (int64_t)nadj.size();
     }
+    // a caller's tau0 that loses an edge gives way to the BFS rule
+    int kind = g->tau0_kind;
+    if (kind == KC_TAU0_GIVEN)
+        for (const auto &e : del)
+            if (g->h_tau0[(size_t)e.first] == e.second || g->h_tau0[(size_t)e.second] == e.first) kind = KC_TAU0_BFS;
     {
         PreparedGraph probe;  // G' must stay connected (section 2.1); nothing changes if not
-        const kc_status st = prepare_graph(noff, nadj, g->root, &probe);
+        const kc_status st = prepare_graph(noff, nadj, g->root, kind, &g->h_tau0, &probe);
         if (st != KC_OK) return st;
     }
     // resident trees that use a deleted edge (Algorithm 2, deletion: they are
@@ -841,6 +979,10 @@ kc_status kc_apply_updates(kc_graph *g, const int32_t *u, const int32_t *v, cons
     // switch to G'
     g->h_off.swap(noff);
     g->h_adj.swap(nadj);
+    if (kind != g->tau0_kind) {
+        g->tau0_kind = kind;
+        g->h_tau0.clear();
+    }
     kc_status st = rebuild_graph(g, g->root, stream);
     if (st != KC_OK) return st;
     if (g->res_count > 0) {
@@ -849,7 +991,7 @@ kc_status kc_apply_updates(kc_graph *g, const int32_t *u, const int32_t *v, cons
         if (k > 0) {
             int32_t *d_tmp = nullptr;
             HIP_TRY(dev_alloc(&d_tmp, (size_t)k * (size_t)n));
-            st = kc_sample_trees(g, g->res_seed, g->res_next, k, d_tmp, nullptr, nullptr, hip_stream);
+            st = kc_sample_trees(g, g->res_seed, g->res_next, k, d_tmp, nullptr, nullptr, (void *)stream);
             if (st != KC_OK) { dev_free(d_tmp); return st; }
             for (int32_t i = 0; i < k; ++i) {
                 HIP_TRY(hipMemcpyAsync(g->d_res_par + (size_t)redo[(size_t)i] * (size_t)n, d_tmp + (size_t)i * (size_t)n,
@@ -861,10 +1003,136 @@ kc_status kc_apply_updates(kc_graph *g, const int32_t *u, const int32_t *v, cons
             g->res_next += k;
         }
         // every tree's f on G' (degrees, 2m and tau0 changed)
-        st = kc_evaluate_trees(g, g->d_res_par, g->res_count, g->d_res_f, hip_stream);
+        st = kc_evaluate_trees(g, g->d_res_par, g->res_count, g->d_res_f, (void *)stream);
         if (st != KC_OK) return st;
         HIP_TRY(hipStreamSynchronize(stream));
-        if (resampled) *resampled = k;
+        if (resampled) *resampled += k;
+    }
+    return KC_OK;
+}
+
+// One insertion (Algorithm 2, insertion case; Theorem 4.1).
+static kc_status apply_insertion(kc_graph *g, int32_t a, int32_t b, int32_t *resampled, hipStream_t stream) {
+    const int64_t n = g->n;
+    if (a < 0 || a >= n || b < 0 || b >= n || a == b) return fail(KC_ERR_INVALID, "bad edge (%d,%d)", a, b);
+    if (std::binary_search(g->h_adj.begin() + g->h_off[(size_t)a], g->h_adj.begin() + g->h_off[(size_t)a + 1], b))
+        return fail(KC_ERR_INVALID, "edge (%d,%d) is already in the graph", a, b);
+    if (g->two_m + 2 >= (1ll << 31)) return fail(KC_ERR_OVERFLOW, "2m would reach 2^31");
+    // G' = G + (a, b)
+    std::vector<int64_t> noff((size_t)n + 1, 0);
+    std::vector<int32_t> nadj;
+    nadj.reserve(g->h_adj.size() + 2);
+    for (int64_t x = 0; x < n; ++x) {
+        const int32_t add = x == a ? b : x == b ? a : -1;
+        bool done = add < 0;
+        for (int64_t e = g->h_off[(size_t)x]; e < g->h_off[(size_t)x + 1]; ++e) {
+            const int32_t y = g->h_adj[(size_t)e];
+            if (!done && add < y) { nadj.push_back(add); done = true; }
+            nadj.push_back(y);
+        }
+        if (!done) nadj.push_back(add);
+        noff[(size_t)x + 1] = (int64_t)nadj.size();
+    }
+    {
+        PreparedGraph probe;  // tau0 of G' must pass the overflow bound; nothing changes if not
+        const kc_status st = prepare_graph(noff, nadj, g->root, g->tau0_kind, &g->h_tau0, &probe);
+        if (st != KC_OK) return st;
+    }
+    std::vector<int32_t> redo;
+    if (g->res_count > 0) {
+        // R(a, b) on the current graph from the set's own trees
+        const std::vector<int32_t> path = reference_path(g->h_off, g->h_adj, a, b);
+        if (path.size() < 2) return fail(KC_ERR_DEVICE, "no path between %d and %d", a, b);
+        int32_t *d_path = nullptr;
+        int64_t *d_c = nullptr;
+        HIP_TRY(dev_alloc(&d_path, path.size()));
+        HIP_TRY(dev_alloc(&d_c, (size_t)g->res_count));
+        HIP_TRY(hipMemcpyAsync(d_path, path.data(), path.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+        kc::RunParams rp{};
+        rp.count = g->res_count;
+        rp.mode = kc::RUN_CURRENT;
+        rp.parents_in = g->d_res_par;
+        rp.f_out = d_c;
+        rp.path = d_path;
+        rp.path_len = (int32_t)path.size();
+        kc_status st = run_persistent(g, rp, stream);
+        std::vector<int64_t> c((size_t)g->res_count);
+        if (st == KC_OK) {
+            const hipError_t e = hipMemcpy(c.data(), d_c, c.size() * sizeof(int64_t), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) st = fail(KC_ERR_DEVICE, "copy failed: %s", hipGetErrorString(e));
+        }
+        dev_free(d_path);
+        dev_free(d_c);
+        if (st != KC_OK) return st;
+        int64_t csum = 0;
+        for (int64_t x : c) csum += x;
+        const double rhat = (double)csum / (double)g->res_count;
+        const double p = rhat / (1.0 + rhat);  // R_G'(e), Theorem 4.1
+        for (int32_t t = 0; t < g->res_count; ++t)
+            if (update_uniform(g->res_seed, (uint32_t)t, (uint32_t)g->res_serial) < p) redo.push_back(t);
+    }
+    g->h_off.swap(noff);
+    g->h_adj.swap(nadj);
+    kc_status st = rebuild_graph(g, g->root, stream);
+    if (st != KC_OK) return st;
+    if (g->res_count > 0) {
+        const int32_t k = (int32_t)redo.size();
+        if (k > 0) {
+            // uniform spanning trees of G' through (a, b): a and b start in the tree
+            int32_t *d_tmp = nullptr;
+            HIP_TRY(dev_alloc(&d_tmp, (size_t)k * (size_t)n));
+            kc::RunParams rp{};
+            rp.seed = g->res_seed;
+            rp.first = g->res_next;
+            rp.count = k;
+            rp.mode = kc::RUN_SAMPLE;
+            rp.parents_out = d_tmp;
+            rp.root_u = a;
+            rp.root_v = b;
+            st = run_persistent(g, rp, stream);
+            if (st == KC_OK) {
+                const hipError_t e = kc::launch_reroot(d_tmp, k, n, a, b, g->root, stream);
+                if (e != hipSuccess) st = fail(KC_ERR_DEVICE, "reroot failed: %s", hipGetErrorString(e));
+            }
+            if (st != KC_OK) { dev_free(d_tmp); return st; }
+            for (int32_t i = 0; i < k; ++i) {
+                HIP_TRY(hipMemcpyAsync(g->d_res_par + (size_t)redo[(size_t)i] * (size_t)n, d_tmp + (size_t)i * (size_t)n,
+                                       (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
+                g->res_ids[(size_t)redo[(size_t)i]] = g->res_next + i;
+            }
+            HIP_TRY(hipStreamSynchronize(stream));
+            dev_free(d_tmp);
+            g->res_next += k;
+        }
+        st = kc_evaluate_trees(g, g->d_res_par, g->res_count, g->d_res_f, (void *)stream);
+        if (st != KC_OK) return st;
+        HIP_TRY(hipStreamSynchronize(stream));
+        g->res_serial += 1;
+        if (resampled) *resampled += k;
+    }
+    return KC_OK;
+}
+
+kc_status kc_apply_updates(kc_graph *g, const int32_t *u, const int32_t *v, const uint8_t *is_insert,
+                           int32_t count, int32_t *resampled, void *hip_stream) {
+    g_last_error.clear();
+    if (!g) return fail(KC_ERR_INVALID, "NULL graph");
+    if (count < 0 || (count > 0 && (!u || !v))) return fail(KC_ERR_INVALID, "bad update arrays");
+    if (resampled) *resampled = 0;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    int32_t k = 0;
+    while (k < count) {
+        if (is_insert && is_insert[k]) {
+            const kc_status st = apply_insertion(g, u[k], v[k], resampled, stream);
+            if (st != KC_OK) return st;
+            ++k;
+        } else {
+            int32_t e = k;
+            while (e < count && !(is_insert && is_insert[e])) ++e;
+            const kc_status st = apply_deletions(g, u + k, v + k, e - k, resampled, stream);
+            if (st != KC_OK) return st;
+            k = e;
+        }
     }
     return KC_OK;
 }

@@ -41,7 +41,7 @@ struct SlotDev {
     int64_t fen_len; // 2m + 2 (0 if not allocated)
 };
 
-enum RunMode { RUN_SAMPLE = 0, RUN_ESTIMATE = 1, RUN_EVALUATE = 2 };
+enum RunMode { RUN_SAMPLE = 0, RUN_ESTIMATE = 1, RUN_EVALUATE = 2, RUN_CURRENT = 3 };
 
 struct RunParams {
     uint64_t seed;
@@ -59,6 +59,10 @@ struct RunParams {
     int64_t *iters_out;        // [count] sampler rounds per sample (optional)
     int32_t *ctl;              // [4]: work counter, error code, error sample, spare
     int64_t *progress;         // [slots] samples finished per workgroup (host-mapped), or null
+    int32_t root_u = -1;       // RUN_SAMPLE: if root_u >= 0, u and v start in the tree instead of
+    int32_t root_v = -1;       // the graph's root (a forest of two trees rooted at u and v)
+    const int32_t *path = nullptr;  // RUN_CURRENT: vertices of a u -> v path in the graph
+    int32_t path_len = 0;           //              number of vertices (>= 2)
 };
 
 // Device result of the exact reduction.
@@ -82,6 +86,8 @@ hipError_t launch_persistent(const GraphDev &g, const SlotDev &s, const RunParam
 hipError_t launch_reduce(const int64_t *f, const int64_t *steps, const int64_t *iters, int32_t count,
                          ReduceOut *out, hipStream_t stream);
 hipError_t launch_zero_i64(int64_t *p, int64_t len, hipStream_t stream);
+hipError_t launch_reroot(int32_t *par, int32_t count, int64_t n, int32_t u, int32_t v, int32_t r,
+                         hipStream_t stream);
 hipError_t launch_flag_trees(const int32_t *par, int32_t count, int64_t n, const int32_t *eu,
                              const int32_t *ev, int32_t ne, uint8_t *flags, hipStream_t stream);
 bool valid_chains(int chains);            // a built chain-table size?

@@ -33,7 +33,8 @@ from . import Graph, KC_OPT_MEM_BUDGET, KcError
 class Request:
     gid: int
     kind: str                      # "query" or "update"
-    edges: list = field(default_factory=list)  # update: [(u, v), ...] to delete
+    edges: list = field(default_factory=list)  # update: [(u, v), ...]
+    insert: bool = False           # update: insert the edges (else delete them)
     t_arrive: float = 0.0
     t_start: float = 0.0
     t_done: float = 0.0
@@ -114,7 +115,7 @@ class Server:
                     req.result = G.samples_query(stream=stream)
                 else:
                     req.result = G.apply_updates([a for a, _ in req.edges], [b for _, b in req.edges],
-                                                 stream=stream)
+                                                 [1 if req.insert else 0] * len(req.edges), stream=stream)
             except KcError as exc:
                 req.error = str(exc)
             finally:

@@ -25,13 +25,19 @@ def kc():
 
 
 def _ops(gen, g, seed, rounds):
-    """A fixed request sequence for one graph: query, delete a batch, query, ..."""
+    """A fixed request sequence for one graph: query, update (a deletion batch
+    or an insertion batch), query, ..."""
     rng = np.random.default_rng(seed)
-    ops = [("query", None)]
+    ops = [("query", None, False)]
     for k in range(rounds):
-        batch = gen.deletion_batch(g, [1, 7, 60][k % 3], rng)
-        g = gen.remove_edges(g, batch)
-        ops += [("update", batch), ("query", None)]
+        if k % 2 == 0:
+            batch = gen.deletion_batch(g, [1, 7, 60][k % 3], rng)
+            g = gen.remove_edges(g, batch)
+            ops += [("update", batch, False), ("query", None, False)]
+        else:
+            batch = gen.insertion_batch(g, 2, rng)
+            g = gen.add_edges(g, batch)
+            ops += [("update", batch, True), ("query", None, False)]
     return ops
 
 
@@ -43,8 +49,8 @@ def _serve(kc, graphs, ops, order):
             srv.add_graph(gid, graphs[gid], seed=100 + gid, samples=128)
         reqs = []
         for gid, k in order:
-            kind, batch = ops[gid][k]
-            r = Request(gid, kind, batch or [])
+            kind, batch, ins = ops[gid][k]
+            r = Request(gid, kind, batch or [], insert=ins)
             reqs.append(r)
             srv.submit(r)
         srv.drain()

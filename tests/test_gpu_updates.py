@@ -96,10 +96,79 @@ def test_rejected_updates_change_nothing(kc, gen):
         with pytest.raises(kc.KcError) as ei:   # not an edge
             G.apply_updates([0], [g.n - 1] if g.n - 1 not in g.indices[g.offsets[0]:g.offsets[1]] else [0])
         assert ei.value.status == 1
-        with pytest.raises(kc.KcError) as ei:   # insertions are the next step of this build
+        with pytest.raises(kc.KcError) as ei:   # inserting an existing edge
             G.apply_updates([leaf], [nb], is_insert=[1])
-        assert ei.value.status == 7
+        assert ei.value.status == 1
         par1, f1, ids1 = G.samples_get()
         assert np.array_equal(par0.cpu().numpy(), par1.cpu().numpy())
         assert np.array_equal(f0.cpu().numpy(), f1.cpu().numpy())
         assert np.array_equal(ids0, ids1) and G.two_m == g.two_m
+
+
+def _mixed_plan(gen, g, seed, steps):
+    """A seeded list of updates: runs of deletions (that keep the graph connected)
+    and single insertions of new edges."""
+    rng = np.random.default_rng(seed)
+    plan = []
+    for k in range(steps):
+        if k % 2 == 0:
+            while True:
+                a, b = (int(x) for x in rng.integers(0, g.n, size=2))
+                if a != b and b not in g.indices[g.offsets[a]:g.offsets[a + 1]]:
+                    break
+            plan.append(("add", [(a, b)]))
+            g = gen.add_edges(g, [(a, b)])
+        else:
+            batch = gen.deletion_batch(g, [3, 20][(k // 2) % 2], rng)
+            plan.append(("del", batch))
+            g = gen.remove_edges(g, batch)
+    return plan
+
+
+@pytest.mark.parametrize("name", ["grid32", "road3k", "social3k"])
+def test_bsm_insertions_and_deletions_match_oracle(kc, oracle_lib, gen, name):
+    from test_gpu_parity import small_graphs
+    g = small_graphs(gen)[name]
+    count = 64
+    S = oracle_lib.samples_init(g.offsets, g.indices, seed=17, count=count)
+    serial = 0
+    with kc.Graph.from_graph(g) as G:
+        G.samples_init(17, count)
+        for kind, edges in _mixed_plan(gen, g, 5, 8):
+            _say(name, kind, len(edges))
+            if kind == "add":
+                (a, b), = edges
+                g = gen.add_edges(g, edges)
+                S, ref_k, _ = oracle_lib.bsm_insert(S, g.offsets, g.indices, a, b, serial)
+                serial += 1
+                k = G.apply_updates([a], [b], is_insert=[1])
+            else:
+                g = gen.remove_edges(g, edges)
+                S, ref_k = oracle_lib.bsm_delete(S, g.offsets, g.indices, edges)
+                k = G.apply_updates([a for a, _ in edges], [b for _, b in edges])
+            assert k == ref_k
+            _compare(G, S, g.two_m)
+        est = G.samples_query()
+        K, se, s1, s2 = oracle_lib.reduce_estimate(S.f, g.two_m)
+        assert est.sum_f == s1 and est.kappa == K and est.std_error == se
+
+
+def test_one_call_runs_in_order(kc, oracle_lib, gen):
+    """A single call with insertions and deletions equals applying, in order,
+    each insertion alone and each run of consecutive deletions at once."""
+    from test_gpu_parity import small_graphs
+    g = small_graphs(gen)["grid32"]
+    ups = [(5, 900, 1), (0, 1, 0), (1, 2, 0), (40, 75, 1), (2, 34, 0)]
+    groups = [[ups[0]], [ups[1], ups[2]], [ups[3]], [ups[4]]]
+    with kc.Graph.from_graph(g) as G1, kc.Graph.from_graph(g) as G2:
+        G1.samples_init(3, 32)
+        G2.samples_init(3, 32)
+        k1 = G1.apply_updates([a for a, _, _ in ups], [b for _, b, _ in ups], [i for _, _, i in ups])
+        k2 = 0
+        for grp in groups:
+            k2 += G2.apply_updates([a for a, _, _ in grp], [b for _, b, _ in grp], [i for _, _, i in grp])
+        p1, f1, i1 = G1.samples_get()
+        p2, f2, i2 = G2.samples_get()
+        assert k1 == k2
+        assert np.array_equal(f1.cpu().numpy(), f2.cpu().numpy())
+        assert np.array_equal(p1.cpu().numpy(), p2.cpu().numpy()) and np.array_equal(i1, i2)
