@@ -94,9 +94,17 @@ enum {
     KC_OPT_START_ORDER = 6, /* order in which walks are started (results do not depend on it):
                               0 = BFS order from the root, 1 = reverse BFS order,
                               2 = a fixed pseudo-random permutation (default) */
-    KC_OPT_CHAINS = 7      /* walks one sample may hold open at once: 1024 (default) or 2048.
+    KC_OPT_CHAINS = 7,     /* walks one sample may hold open at once: 1024 (default) or 2048.
                               More finish one sample in fewer rounds; fewer let more samples
                               run at once.  Results do not depend on it. */
+    KC_OPT_MAINTENANCE = 8 /* KC_MAINT_*: how kc_apply_updates maintains the resident set;
+                              set while no resident set exists (before kc_samples_init) */
+};
+
+/* Sample maintenance of a resident set (section 4). */
+enum {
+    KC_MAINT_BASIC = 0,    /* Algorithm 2: replace trees by fresh uniform samples (default) */
+    KC_MAINT_IMPROVED = 1  /* Algorithm 3: link-cut / cut-link the affected trees and weight them */
 };
 
 /*
@@ -240,8 +248,16 @@ kc_status kc_samples_init(kc_graph *g, uint64_t seed, int32_t count, void *hip_s
 
 /* kc_estimate's result over the resident trees on the current graph
  * (Theorem 3.3 with omega = the set's size).  result: HOST pointer.
+ * Under KC_MAINT_IMPROVED, kappa is the weighted estimate sum_t w_t f_t / 2m
+ * (Algorithm 3, weights summing to one, added in slot order) and std_error
+ * is sqrt(sum_t w_t^2 (f_t / 2m - kappa)^2); the exact sums stay unweighted.
  * Errors: KC_ERR_INVALID if no set was initialised. */
 kc_status kc_samples_query(kc_graph *g, kc_result *result, void *hip_stream);
+
+/* The resident trees' weights (HOST pointer, the set's size in doubles):
+ * 1/count after kc_samples_init, changed only by improved maintenance.
+ * Errors: KC_ERR_INVALID (NULL argument, no set). */
+kc_status kc_samples_weights(const kc_graph *g, double *w_out);
 
 /* Copy the resident set out: parents_out DEVICE [count*n] int32, f_out
  * DEVICE [count] int64, ids_out HOST [count] int64 (the sample index each
@@ -274,6 +290,28 @@ kc_status kc_samples_get(const kc_graph *g, int32_t *parents_out, int64_t *f_out
  *     v -> u added, and the path from the root re-oriented toward it.
  *   u, v, is_insert : HOST pointers, count entries (is_insert NULL: all deletions)
  *   resampled       : HOST pointer or NULL, receives how many trees were replaced
+ *
+ * Under KC_MAINT_IMPROVED (section 4.2, Algorithm 3) every edge is applied on
+ * its own, in order, and trees are transformed instead of redrawn; Philox
+ * with key (seed_lo, seed_hi) and counter (slot, j, 2^32-2, 2^32-1) picks an
+ * edge among d candidates as floor(x d / 2^64), j counting the edges applied
+ * to the set so far:
+ *   Insertion of e = (u, v): R on the graph before it is estimated from the
+ *     weighted trees (sum_t w_t times the signed path count above); ceil(R' n_S)
+ *     trees (R' = R / (1 + R), n_S the set's size) are chosen, those with the
+ *     smallest replacement draws of the basic case.  Each goes through
+ *     link-cut: e is added and one of the d edges of the tree path between u
+ *     and v removed (counted from u upward, then from v upward).  Its weight is
+ *     multiplied by d / d', d' being the number of edges of the old graph that
+ *     join the two parts of the new tree minus e (Theorem 4.4).  The chosen
+ *     trees' weights are then scaled to sum to R', the others' to 1 - R'.
+ *   Deletion of e: each tree through e goes through cut-link: e is removed and
+ *     one of the d edges of the new graph that join the two parts added (edges
+ *     {x, y}, x < y, by x, then in row order).  Its weight is multiplied by
+ *     d / d', d' being the length of the new tree's path between u and v
+ *     (Theorem 4.5), and these trees' weights are scaled back to their total
+ *     before the update.
+ *   Sample indices do not change; resampled receives the trees transformed.
  * Errors: KC_ERR_INVALID (a deletion that is not an edge, a duplicate within a
  * run, an insertion of an existing edge, a bad vertex), KC_ERR_DISCONNECTED
  * (a deletion run would disconnect the graph), KC_ERR_OVERFLOW (2m would

@@ -397,3 +397,219 @@ def bsm_insert(S: SampleSet, offsets_new, indices_new, u: int, v: int, serial: i
     f = np.array([f_of_tree(P, t) for t in par], np.int64)
     return (SampleSet(P.offsets, P.indices, P.root, S.seed, par, ids, S.next_id + len(redo), f),
             len(redo), rhat)
+
+
+# ---------------------------------------- improved sample maintenance (ISM)
+
+def ism_draw(seed: int, slot: int, serial: int, count: int) -> int:
+    """The link-cut or cut-link choice for resident tree `slot` at update
+    number `serial`: Philox4x32-10, key (seed_lo, seed_hi), counter
+    (slot, serial, 2^32-2, 2^32-1) (a counter no tree sample uses), x = o0 |
+    o1 << 32, choice floor(x * count / 2^64) in [0, count)."""
+    o = philox4x32_10([slot, serial, 0xFFFFFFFE, 0xFFFFFFFF], [seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF])
+    x = int(o[0]) | (int(o[1]) << 32)
+    return (x * count) >> 64
+
+
+def tree_path(parent, u: int, v: int):
+    """The tree path between u and v: (vertices from u up to, not including,
+    the lowest common ancestor; the same from v)."""
+    av = set()
+    y = v
+    while y != -1:
+        av.add(int(y))
+        y = int(parent[y])
+    up = []
+    x = u
+    while x not in av:
+        up.append(int(x))
+        x = int(parent[x])
+    dn = []
+    y = v
+    while y != x:
+        dn.append(int(y))
+        y = int(parent[y])
+    return up, dn
+
+
+def link_cut(parent, u: int, v: int, j: int):
+    """link-cut(tau, e) of section 4.2: add e = {u, v} to the tree, which closes
+    a cycle with the tree path between u and v, and remove the j-th edge of that
+    path (edges {x, p(x)} for x on u's side from u upward, then on v's side from
+    v upward).  The cut-off part is re-hung through e, so the result is rooted
+    at r again.  Returns (new parent array, d(tau) = length of the path)."""
+    up, dn = tree_path(parent, u, v)
+    d = len(up) + len(dn)
+    new = np.array(parent, dtype=np.int32, copy=True)
+    side, other = (up[: j + 1], v) if j < len(up) else (dn[: j - len(up) + 1], u)
+    prev = other
+    for x in side:
+        new[x] = prev
+        prev = x
+    return new, d
+
+
+def in_subtree(parent, c: int) -> np.ndarray:
+    """inside[x] = c is x or one of x's tree ancestors."""
+    n = len(parent)
+    inside = np.zeros(n, bool)
+    known = np.zeros(n, bool)
+    inside[c] = True
+    known[c] = True
+    for x in range(n):
+        chain = []
+        y = x
+        while y != -1 and not known[y]:
+            chain.append(y)
+            y = int(parent[y])
+        val = bool(inside[y]) if y != -1 else False
+        for z in chain:
+            inside[z] = val
+            known[z] = True
+    return inside
+
+
+def crossing_edges(offsets, indices, parent, a: int, b: int):
+    """The graph edges {x, y} (x < y, rows in ascending order) that join the
+    two trees left when the tree edge {a, b} is removed.  Returns (edges, c,
+    inside) with c the endpoint on the side away from the root."""
+    c = a if parent[a] == b else b
+    assert parent[c] == (b if c == a else a), "{a, b} is not a tree edge"
+    inside = in_subtree(parent, c)
+    n = len(offsets) - 1
+    out = []
+    for x in range(n):
+        for y in indices[offsets[x]:offsets[x + 1]]:
+            y = int(y)
+            if x < y and inside[x] != inside[y]:
+                out.append((x, y))
+    return out, c, inside
+
+
+def cut_link(parent, offsets, indices, a: int, b: int, j: int):
+    """cut-link(tau, e) of section 4.2: remove the tree edge e = {a, b} and
+    join the two parts by the j-th of the crossing edges of the graph (in the
+    order of crossing_edges); the detached part is re-hung through it, so the
+    result is rooted at r again.  Returns (new parent array, d(tau) = number
+    of crossing edges)."""
+    cross, c, inside = crossing_edges(offsets, indices, parent, a, b)
+    x, y = cross[j]
+    xi, yo = (x, y) if inside[x] else (y, x)
+    new = np.array(parent, dtype=np.int32, copy=True)
+    prev, z = yo, xi
+    while True:
+        nz = int(parent[z])
+        new[z] = prev
+        if z == c:
+            break
+        prev, z = z, nz
+    return new, len(cross)
+
+
+@dataclass
+class WeightedSet:
+    """The sample set of Algorithm 3: trees with weights that sum to one."""
+    S: SampleSet
+    w: np.ndarray   # [count] float64
+    serial: int     # single-edge updates applied so far (counter of their draws)
+
+
+def ism_init(offsets, indices, seed: int, count: int, root: int = -1, threads: int = 8) -> WeightedSet:
+    S = samples_init(offsets, indices, seed, count, root, threads)
+    return WeightedSet(S, np.full(count, 1.0 / count), 0)
+
+
+def weighted_estimate(W: WeightedSet):
+    """kappa-hat = sum_t w_t f_t / 2m over the set (weights sum to one), summed
+    in slot order; its standard error sqrt(sum_t w_t^2 (f_t/2m - kappa-hat)^2)."""
+    two_m = float(W.S.two_m)
+    k = 0.0
+    for t in range(len(W.w)):
+        k += W.w[t] * float(W.S.f[t])
+    k /= two_m
+    v = 0.0
+    for t in range(len(W.w)):
+        dlt = float(W.S.f[t]) / two_m - k
+        v += W.w[t] * W.w[t] * dlt * dlt
+    return k, math.sqrt(v)
+
+
+def _normalise(w, group, target):
+    s = 0.0
+    for t in group:
+        s += w[t]
+    for t in group:
+        w[t] *= target / s
+
+
+def ism_insert(W: WeightedSet, offsets_new, indices_new, u: int, v: int):
+    """Algorithm 3, insertion of e = {u, v}.  R(u, v) on the old graph is
+    estimated from the set's own trees, weighted (the path-current count of
+    bsm_insert); R' = R / (1 + R) is the share of spanning trees of G' that
+    contain e (Theorem 4.1).  ceil(R' |S|) trees are chosen uniformly at
+    random (the slots with the smallest update_uniform(seed, slot, serial)),
+    each is taken through link-cut with the choice ism_draw(seed, slot, serial,
+    d(tau)) and its weight multiplied by d(tau) / d(tau_e), where d(tau_e) is
+    the number of edges of the old graph that join the two parts of tau_e - e
+    (Theorem 4.4).  The chosen trees' weights are then scaled to sum to R' and
+    the others' to 1 - R'; a group that is empty leaves the whole mass to the
+    other.  f is evaluated on G' for every tree.  Returns (new set, chosen)."""
+    S = W.S
+    count = S.parents.shape[0]
+    path = reference_path(S.offsets, S.indices, u, v)
+    rhat = 0.0
+    for t in range(count):
+        rhat += W.w[t] * path_current(S.parents[t], path)
+    rp = rhat / (1.0 + rhat)
+    k = min(count, int(math.ceil(rp * count)))
+    order = sorted(range(count), key=lambda t: (update_uniform(S.seed, t, W.serial), t))
+    chosen = sorted(order[:k])
+    rest = sorted(order[k:])
+    par = S.parents.copy()
+    w = W.w.copy()
+    for t in chosen:
+        up, dn = tree_path(par[t], u, v)
+        d_old = len(up) + len(dn)
+        par[t], _ = link_cut(par[t], u, v, ism_draw(S.seed, t, W.serial, d_old))
+        cross, _, _ = crossing_edges(offsets_new, indices_new, par[t], u, v)
+        d_new = len(cross) - 1          # e itself crosses in G'
+        w[t] *= float(d_old) / float(d_new)
+    if chosen and rest:
+        _normalise(w, chosen, rp)
+        _normalise(w, rest, 1.0 - rp)
+    else:
+        _normalise(w, chosen or rest, 1.0)
+    P = prepare(offsets_new, indices_new, S.root)
+    f = np.array([f_of_tree(P, t) for t in par], np.int64)
+    S2 = SampleSet(P.offsets, P.indices, P.root, S.seed, par, S.ids.copy(), S.next_id, f)
+    return WeightedSet(S2, w, W.serial + 1), len(chosen)
+
+
+def ism_delete(W: WeightedSet, offsets_new, indices_new, a: int, b: int):
+    """Algorithm 3, deletion of e = {a, b}: every tree that contains e is taken
+    through cut-link on G' with the choice ism_draw(seed, slot, serial, d(tau)),
+    d(tau) being the number of edges of G' that join the two parts of tau - e,
+    and its weight multiplied by d(tau) / d(tau'), with d(tau') the length of
+    the tree path between a and b in the new tree (Theorem 4.5).  The changed
+    trees' weights are then scaled to sum to their total before the update.
+    f is evaluated on G' for every tree.  Returns (new set, changed)."""
+    S = W.S
+    count = S.parents.shape[0]
+    par = S.parents.copy()
+    w = W.w.copy()
+    hit = [t for t in range(count) if par[t][a] == b or par[t][b] == a]
+    w_org = 0.0
+    for t in hit:
+        w_org += w[t]
+    for t in hit:
+        cross, _, _ = crossing_edges(offsets_new, indices_new, par[t], a, b)
+        d_old = len(cross)
+        par[t], _ = cut_link(par[t], offsets_new, indices_new, a, b, ism_draw(S.seed, t, W.serial, d_old))
+        up, dn = tree_path(par[t], a, b)
+        w[t] *= float(d_old) / float(len(up) + len(dn))
+    if hit:
+        _normalise(w, hit, w_org)
+    P = prepare(offsets_new, indices_new, S.root)
+    f = np.array([f_of_tree(P, t) for t in par], np.int64)
+    S2 = SampleSet(P.offsets, P.indices, P.root, S.seed, par, S.ids.copy(), S.next_id, f)
+    return WeightedSet(S2, w, W.serial + 1), len(hit)

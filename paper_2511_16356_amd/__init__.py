@@ -25,11 +25,13 @@ KC_OPT_WALKERS, KC_OPT_SLOTS, KC_OPT_TRAVERSAL, KC_OPT_STEP_LIMIT, KC_OPT_MEM_BU
 KC_OPT_START_ORDER = 6
 KC_OPT_CHAINS = 7
 KC_TAU0_BFS, KC_TAU0_DFS, KC_TAU0_GIVEN = 0, 1, 2
+KC_OPT_MAINTENANCE = 8
+KC_MAINT_BASIC, KC_MAINT_IMPROVED = 0, 1
 
 # every symbol include/kc.h declares
 EXPORTS = ("kc_graph_create", "kc_graph_destroy", "kc_graph_get_info", "kc_set_option", "kc_set_tau0",
            "kc_reserve", "kc_progress",
-           "kc_samples_init", "kc_samples_query", "kc_samples_get", "kc_apply_updates",
+           "kc_samples_init", "kc_samples_query", "kc_samples_get", "kc_samples_weights", "kc_apply_updates",
            "kc_sample_trees", "kc_estimate", "kc_evaluate_trees", "kc_status_string",
            "kc_last_error")
 
@@ -81,6 +83,8 @@ def library() -> ctypes.CDLL:
     lib.kc_samples_init.argtypes = [p, u64, i32, p]
     lib.kc_samples_query.restype = ctypes.c_int
     lib.kc_samples_query.argtypes = [p, ctypes.POINTER(_Result), p]
+    lib.kc_samples_weights.restype = ctypes.c_int
+    lib.kc_samples_weights.argtypes = [p, p]
     lib.kc_samples_get.restype = ctypes.c_int
     lib.kc_samples_get.argtypes = [p, p, p, p, p]
     lib.kc_apply_updates.restype = ctypes.c_int
@@ -219,6 +223,12 @@ class Graph:
         _check(library().kc_samples_get(self._h, _dptr(par), _dptr(f), ids.ctypes.data_as(ctypes.c_void_p),
                                         _stream(stream)))
         return par, f, ids
+
+    def samples_weights(self) -> np.ndarray:
+        """The resident trees' weights (float64 [count])."""
+        w = np.zeros(self.res_count, dtype=np.float64)
+        _check(library().kc_samples_weights(self._h, w.ctypes.data_as(ctypes.c_void_p)))
+        return w
 
     def apply_updates(self, u, v, is_insert=None, stream=None) -> int:
         """Apply a batch of edge updates; returns how many resident trees were replaced."""

@@ -294,12 +294,18 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
                 const int r = rank_in(idle);
                 const int k = r - take_q;
                 pend = false;
-                // each lane reads all four sources at clamped, always valid indices and
-                // keeps the one it needs: no load waits on another lane's
-                const int4 t = ws.queue[(q_head + max(0, min(r, take_q - 1))) & (CH - 1)];
-                const int32_t t_rq = aload(&ws.rq[(rq_head + max(0, min(k, take_r - 1))) % n]);
-                const int32_t t_ord = aload(&g.order[max(0, min(next_start + k - take_r, n - 1))]);
-                const int32_t t_hint = sh.hint[max(0, min(hint_top - 1 - (k - take_r - take_s), HINTS - 1))];
+                // a lane that takes work reads all four sources at clamped, always
+                // valid indices and keeps the one it needs, so its loads and those of
+                // the other lanes are in flight together; lanes that take nothing
+                // read nothing (a round with nothing to take has no load here)
+                int4 t = make_int4(0, 0, 0, 0);
+                int32_t t_rq = 0, t_ord = 0, t_hint = 0;
+                if (r < take_q + take_r + take_s + take_h) {
+                    t = ws.queue[(q_head + max(0, min(r, take_q - 1))) & (CH - 1)];
+                    t_rq = aload(&ws.rq[(rq_head + max(0, min(k, take_r - 1))) % n]);
+                    t_ord = aload(&g.order[max(0, min(next_start + k - take_r, n - 1))]);
+                    t_hint = sh.hint[max(0, min(hint_top - 1 - (k - take_r - take_s), HINTS - 1))];
+                }
                 if (r < take_q) {
                     chain = t.x;
                     ctag = T_CHAIN0 + (uint32_t)chain;
@@ -888,6 +894,97 @@ __device__ int64_t path_current(const SlotPtrs &sp, const int32_t *path, int len
     return wave_sum(c);
 }
 
+// Number of graph edges {x, y} that join the two trees left when the tree
+// edge {cut_u, cut_v} is removed (the side away from the root is Sub(tau, c)
+// with c the child endpoint; membership from the tree numbering).  With
+// relink, also cut-link (section 4.2): edge number j of them, in the order
+// (x ascending, row order, x < y), with j drawn by Philox on counter
+// (slot, serial, ISM_CTR_LO, ISM_CTR_HI), joins the two parts; the path from
+// its inner endpoint up to c is reversed so the tree stays rooted at r.
+__device__ int64_t crossing_edges(const GraphDev &g, const SlotPtrs &sp, const RunParams &rp, int32_t slot,
+                                  int idx) {
+    const int lane = threadIdx.x;
+    const int n = g.n;
+    const int a = rp.cut_u, b = rp.cut_v;
+    const int32_t pa = (int32_t)aload(&sp.rec[2 * (size_t)a + 1]);
+    const int32_t pb = (int32_t)aload(&sp.rec[2 * (size_t)b + 1]);
+    const int c = pa == b ? a : (pb == a ? b : -1);
+    if (c < 0) {
+        report_error(rp.ctl, DEV_BADTREE, idx);
+        return 0;
+    }
+    const uint64_t rc = aload(&sp.rec[2 * (size_t)c]);
+    const uint32_t lo = (uint32_t)rc, hi = lo + (uint32_t)(rc >> 32);
+    auto inside = [&](int x) {
+        const uint32_t t = (uint32_t)aload(&sp.rec[2 * (size_t)x]);
+        return lo <= t && t < hi;
+    };
+    auto row_count = [&](int x, bool ix) {
+        int64_t k = 0;
+        for (int64_t e = g.off[x]; e < g.off[x + 1]; ++e) {
+            const int y = g.adj[e];
+            if (y > x && inside(y) != ix) ++k;
+        }
+        return k;
+    };
+    int64_t cnt = 0;
+    for (int x = lane; x < n; x += WAVE) cnt += row_count(x, inside(x));
+    const int64_t total = wave_sum(cnt);
+    if (!rp.relink) return total;
+    if (total <= 0) {
+        report_error(rp.ctl, DEV_BADTREE, idx);
+        return 0;
+    }
+    const int64_t j = arrow_slot(rp.seed, ((uint64_t)ISM_CTR_HI << 32) | ISM_CTR_LO, rp.serial, (uint32_t)slot,
+                                 (uint32_t)total);
+    int64_t base = 0;
+    for (int x0 = 0; x0 < n; x0 += WAVE) {
+        const int x = x0 + lane;
+        const bool ix = x < n && inside(x);
+        const int64_t k = x < n ? row_count(x, ix) : 0;
+        int64_t incl = k;
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const int64_t t = __shfl_up(incl, d);
+            if (lane >= d) incl += t;
+        }
+        const int64_t chunk = __shfl(incl, WAVE - 1);
+        if (base + chunk > j) {
+            if (k > 0 && base + incl - k <= j && j < base + incl) {
+                int64_t r = j - (base + incl - k);
+                int y = -1;
+                for (int64_t e = g.off[x]; e < g.off[x + 1]; ++e) {
+                    const int z = g.adj[e];
+                    if (z > x && inside(z) != ix) {
+                        if (r == 0) { y = z; break; }
+                        --r;
+                    }
+                }
+                if (y < 0) {
+                    report_error(rp.ctl, DEV_BADTREE, idx);
+                } else {
+                    const int xi = ix ? x : y, yo = ix ? y : x;
+                    int32_t *out = rp.parents_mut + (size_t)slot * (size_t)n;
+                    int32_t prev = yo, z = xi;
+                    for (int guard = 0; guard <= n; ++guard) {
+                        const int32_t nz = (int32_t)aload(&sp.rec[2 * (size_t)z + 1]);
+                        out[z] = prev;
+                        if (z == c) break;
+                        if (nz < 0 || nz >= n) {  // c is an ancestor of xi: not reached
+                            report_error(rp.ctl, DEV_BADTREE, idx);
+                            break;
+                        }
+                        prev = z;
+                        z = nz;
+                    }
+                }
+            }
+            break;
+        }
+        base += chunk;
+    }
+    return total;
+}
+
 // ------------------------------------------------------------ the kernels
 
 // The sampler and the sweep run one after the other: one LDS block serves both.
@@ -897,7 +994,9 @@ union KernelShared {
     SweepShared sweep;
 };
 
-template <int CH>
+// CROSS: the instantiation for RUN_CROSS only (no sampler, no f), kept apart
+// so that its code does not weigh on the sampler's register allocation.
+template <int CH, bool CROSS = false>
 __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd, RunParams rp) {
     __shared__ KernelShared<CH> lds;
     const int lane = threadIdx.x;
@@ -924,12 +1023,12 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
         if (__hip_atomic_load(&rp.ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
         const uint64_t s = (uint64_t)(rp.first + idx);
         int64_t steps = 0, iters = 0;
-        if (rp.mode == RUN_SAMPLE || rp.mode == RUN_ESTIMATE) {
+        if (!CROSS && (rp.mode == RUN_SAMPLE || rp.mode == RUN_ESTIMATE)) {
             steps = sample_tree<CH>(g, sp.ws, lds.samp, rp.seed, s, rp.walkers, rp.iter_cap, rp.ctl, idx, &iters,
                                     rp.root_u, rp.root_v);
             if (steps < 0) break;
         }
-        if (rp.mode == RUN_SAMPLE) {
+        if (!CROSS && rp.mode == RUN_SAMPLE) {
             int32_t *po = rp.parents_out + (size_t)idx * n;
             uint32_t *co = rp.cnt_out ? rp.cnt_out + (size_t)idx * n : nullptr;
             for (int v = lane; v < g.n; v += WAVE) {
@@ -939,13 +1038,14 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
             }
         } else {
             // parents into rec[2v+1]
+            const size_t row = rp.rows ? (size_t)rp.rows[idx] : (size_t)idx;
             bool bad = false;
             for (int v = lane; v < g.n; v += WAVE) {
                 int32_t p;
                 if (v == g.root) {
                     p = -1;
                 } else {
-                    p = (rp.mode != RUN_ESTIMATE) ? rp.parents_in[(size_t)idx * n + v]
+                    p = (rp.mode != RUN_ESTIMATE) ? rp.parents_in[row * n + v]
                                                   : (int32_t)(uint32_t)aload(&sp.ws.arrow[v]);
                     if (p < 0 || p >= g.n || p == v) { bad = true; p = g.root; }
                 }
@@ -955,9 +1055,13 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
             bool ok = tree_numbering(g, sp);
             if (__ballot(bad) != 0ull) ok = false;
             int64_t f = 0;
-            if (rp.mode == RUN_CURRENT) f = path_current(sp, rp.path, rp.path_len);
-            else if (rp.traversal == 2) f = f_sweep(g, sp, sd.fen_len, lds.sweep);
-            else f = f_walk(g, sp);
+            if constexpr (CROSS) {
+                f = ok ? crossing_edges(g, sp, rp, (int32_t)row, idx) : 0;
+            } else {
+                if (rp.mode == RUN_CURRENT) f = path_current(sp, rp.path, rp.path_len);
+                else if (rp.traversal == 2) f = f_sweep(g, sp, sd.fen_len, lds.sweep);
+                else f = f_walk(g, sp);
+            }
             if (!ok) report_error(rp.ctl, DEV_BADTREE, idx);
             if (lane == 0) rp.f_out[idx] = f;
         }
@@ -999,6 +1103,61 @@ __global__ void reroot_kernel(int32_t *par, int32_t count, int64_t n, int32_t u,
         row[x] = prev;
         prev = x;
         x = nx;
+    }
+}
+
+// link-cut (section 4.2) on resident trees rows[t]: the tree path between u
+// and v (lengths su from u and sv from v up to their lowest common ancestor)
+// has d = su + sv edges; d_out[t] = d.  With relink, edge number j (drawn by
+// Philox on counter (slot, serial, ISM_CTR_LO, ISM_CTR_HI); edges counted
+// from u upward, then from v upward) is removed and {u, v} added: the path
+// from the endpoint on j's side up to the cut edge is reversed.  One thread
+// per tree.
+__global__ void link_cut_kernel(int32_t *par, const int32_t *rows, int32_t count, int64_t n, int32_t u,
+                                int32_t v, uint64_t seed, uint32_t serial, int relink, int64_t *d_out,
+                                int32_t *ctl) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const int32_t slot = rows[t];
+    int32_t *row = par + (int64_t)slot * n;
+    auto depth_of = [&](int32_t x) {
+        int64_t d = 0;
+        while (d <= n && row[x] != -1) {
+            x = row[x];
+            ++d;
+        }
+        return d;
+    };
+    int64_t du = depth_of(u), dv = depth_of(v);
+    if (du > n || dv > n) {
+        report_error(ctl, DEV_BADTREE, t);
+        return;
+    }
+    int32_t x = u, y = v;
+    int64_t su = 0, sv = 0;
+    for (; du > dv; --du, ++su) x = row[x];
+    for (; dv > du; --dv, ++sv) y = row[y];
+    for (; x != y; ++su, ++sv) {
+        x = row[x];
+        y = row[y];
+    }
+    const int64_t d = su + sv;
+    d_out[t] = d;
+    if (!relink) return;
+    if (d <= 0) {
+        report_error(ctl, DEV_BADTREE, t);
+        return;
+    }
+    const int64_t j = arrow_slot(seed, ((uint64_t)ISM_CTR_HI << 32) | ISM_CTR_LO, serial, (uint32_t)slot,
+                                 (uint32_t)d);
+    const bool u_side = j < su;
+    int32_t prev = u_side ? v : u, z = u_side ? u : v;
+    const int64_t steps = u_side ? j : j - su;
+    for (int64_t i = 0; i <= steps; ++i) {
+        const int32_t nz = row[z];
+        row[z] = prev;
+        prev = z;
+        z = nz;
     }
 }
 
@@ -1069,6 +1228,10 @@ bool valid_chains(int chains) {
 
 hipError_t launch_persistent(const GraphDev &g, const SlotDev &s, const RunParams &rp, int chains,
                              int slots, hipStream_t stream) {
+    if (rp.mode == RUN_CROSS) {
+        hipLaunchKernelGGL((persistent_kernel<1024, true>), dim3(slots), dim3(WAVE), 0, stream, g, s, rp);
+        return hipGetLastError();
+    }
 #define KC_CASE(C)                                                                              \
     if (chains == C) {                                                                         \
         hipLaunchKernelGGL(persistent_kernel<C>, dim3(slots), dim3(WAVE), 0, stream, g, s, rp); \
@@ -1106,6 +1269,15 @@ hipError_t launch_reroot(int32_t *par, int32_t count, int64_t n, int32_t u, int3
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(reroot_kernel, dim3((unsigned)((count + 63) / 64)), dim3(64), 0, stream, par, count, n,
                        u, v, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_link_cut(int32_t *par, const int32_t *rows, int32_t count, int64_t n, int32_t u, int32_t v,
+                           uint64_t seed, uint32_t serial, int relink, int64_t *d_out, int32_t *ctl,
+                           hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(link_cut_kernel, dim3((count + 63) / 64), dim3(64), 0, stream, par, rows, count, n, u, v,
+                       seed, serial, relink, d_out, ctl);
     return hipGetLastError();
 }
 

@@ -78,7 +78,10 @@ struct kc_graph {
     int32_t res_count = 0;
     uint64_t res_seed = 0;
     int64_t res_next = 0;             // next unused sample index
-    int64_t res_serial = 0;           // insertions applied so far (counter of their draws)
+    int64_t res_serial = 0;           // basic: insertions applied so far; improved: single-edge
+                                      // updates applied so far (the counter of their draws)
+    int32_t maint = KC_MAINT_BASIC;   // sample maintenance of the resident set
+    std::vector<double> res_w;        // improved maintenance: weight of each tree (sum 1)
     std::vector<int64_t> res_ids;     // sample index of each resident tree
     int32_t *d_res_par = nullptr;     // [res_count * n] parents
     int64_t *d_res_f = nullptr;       // [res_count] f of each tree on the current graph
@@ -742,6 +745,13 @@ kc_status kc_set_option(kc_graph *g, int option, int64_t value) {
             if (value < 0) return fail(KC_ERR_INVALID, "memory budget must be >= 0");
             g->mem_budget = value;
             return KC_OK;
+        case KC_OPT_MAINTENANCE:
+            if (value != KC_MAINT_BASIC && value != KC_MAINT_IMPROVED)
+                return fail(KC_ERR_INVALID, "maintenance must be KC_MAINT_BASIC or KC_MAINT_IMPROVED");
+            if (g->res_count > 0 && value != g->maint)
+                return fail(KC_ERR_INVALID, "choose the maintenance before kc_samples_init");
+            g->maint = (int32_t)value;
+            return KC_OK;
         case KC_OPT_START_ORDER: {
             if (value < 0 || value > 2) return fail(KC_ERR_INVALID, "start order must be 0, 1 or 2");
             const std::vector<int32_t> ord = start_order_of(g->bfs_order, (int)value);
@@ -885,6 +895,8 @@ kc_status kc_samples_init(kc_graph *g, uint64_t seed, int32_t count, void *hip_s
     g->res_next = count;
     g->res_ids.resize((size_t)count);
     for (int32_t i = 0; i < count; ++i) g->res_ids[(size_t)i] = i;
+    g->res_serial = 0;
+    g->res_w.assign((size_t)count, 1.0 / (double)count);
     return KC_OK;
 }
 
@@ -892,7 +904,33 @@ kc_status kc_samples_query(kc_graph *g, kc_result *result, void *hip_stream) {
     g_last_error.clear();
     if (!g || !result) return fail(KC_ERR_INVALID, "NULL graph or result");
     if (g->res_count < 1) return fail(KC_ERR_INVALID, "no resident samples (call kc_samples_init)");
-    return finish_reduce(g, g->res_count, g->d_res_f, nullptr, nullptr, result, (hipStream_t)hip_stream);
+    hipStream_t stream = (hipStream_t)hip_stream;
+    const kc_status st = finish_reduce(g, g->res_count, g->d_res_f, nullptr, nullptr, result, stream);
+    if (st != KC_OK || g->maint != KC_MAINT_IMPROVED) return st;
+    // Algorithm 3: kappa = sum_t w_t f_t / 2m, weights summing to one, in slot order
+    std::vector<int64_t> f((size_t)g->res_count);
+    HIP_TRY(hipMemcpyAsync(f.data(), g->d_res_f, f.size() * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    const double two_m = (double)g->two_m;
+    double k = 0.0;
+    for (size_t t = 0; t < f.size(); ++t) k += g->res_w[t] * (double)f[t];
+    k /= two_m;
+    double v = 0.0;
+    for (size_t t = 0; t < f.size(); ++t) {
+        const double d = (double)f[t] / two_m - k;
+        v += g->res_w[t] * g->res_w[t] * d * d;
+    }
+    result->kappa = k;
+    result->std_error = std::sqrt(v);
+    return KC_OK;
+}
+
+kc_status kc_samples_weights(const kc_graph *g, double *w_out) {
+    g_last_error.clear();
+    if (!g || !w_out) return fail(KC_ERR_INVALID, "NULL argument");
+    if (g->res_count < 1) return fail(KC_ERR_INVALID, "no resident samples (call kc_samples_init)");
+    std::memcpy(w_out, g->res_w.data(), g->res_w.size() * sizeof(double));
+    return KC_OK;
 }
 
 kc_status kc_samples_get(const kc_graph *g, int32_t *parents_out, int64_t *f_out, int64_t *ids_out,
@@ -909,6 +947,8 @@ kc_status kc_samples_get(const kc_graph *g, int32_t *parents_out, int64_t *f_out
     HIP_TRY(hipStreamSynchronize(stream));
     return KC_OK;
 }
+
+static kc_status ism_deletion(kc_graph *g, int32_t a, int32_t b, int32_t *changed, hipStream_t stream);
 
 // A run of deletions, applied at once (Algorithm 2, deletion case).
 static kc_status apply_deletions(kc_graph *g, const int32_t *u, const int32_t *v, int32_t count,
@@ -951,6 +991,15 @@ static kc_status apply_deletions(kc_graph *g, const int32_t *u, const int32_t *v
         PreparedGraph probe;  // G' must stay connected (section 2.1); nothing changes if not
         const kc_status st = prepare_graph(noff, nadj, g->root, kind, &g->h_tau0, &probe);
         if (st != KC_OK) return st;
+    }
+    if (g->maint == KC_MAINT_IMPROVED && g->res_count > 0) {
+        // Algorithm 3 takes one edge at a time; every intermediate graph contains
+        // the final one, so it is connected too
+        for (int32_t k = 0; k < count; ++k) {
+            const kc_status st = ism_deletion(g, u[k], v[k], resampled, stream);
+            if (st != KC_OK) return st;
+        }
+        return KC_OK;
     }
     // resident trees that use a deleted edge (Algorithm 2, deletion: they are
     // replaced; the others are uniform spanning trees of G' already, Theorem 4.2)
@@ -1011,6 +1060,71 @@ static kc_status apply_deletions(kc_graph *g, const int32_t *u, const int32_t *v
     return KC_OK;
 }
 
+// The CSR with the undirected edge {a, b} added (rows stay ascending).
+static void csr_with_edge(const std::vector<int64_t> &off, const std::vector<int32_t> &adj, int32_t a, int32_t b,
+                          std::vector<int64_t> *noff, std::vector<int32_t> *nadj) {
+    const int64_t n = (int64_t)off.size() - 1;
+    noff->assign((size_t)n + 1, 0);
+    nadj->clear();
+    nadj->reserve(adj.size() + 2);
+    for (int64_t x = 0; x < n; ++x) {
+        const int32_t add = x == a ? b : x == b ? a : -1;
+        bool done = add < 0;
+        for (int64_t e = off[(size_t)x]; e < off[(size_t)x + 1]; ++e) {
+            const int32_t y = adj[(size_t)e];
+            if (!done && add < y) { nadj->push_back(add); done = true; }
+            nadj->push_back(y);
+        }
+        if (!done) nadj->push_back(add);
+        (*noff)[(size_t)x + 1] = (int64_t)nadj->size();
+    }
+}
+
+// The CSR with the undirected edge {a, b} removed.
+static void csr_without_edge(const std::vector<int64_t> &off, const std::vector<int32_t> &adj, int32_t a,
+                             int32_t b, std::vector<int64_t> *noff, std::vector<int32_t> *nadj) {
+    const int64_t n = (int64_t)off.size() - 1;
+    noff->assign((size_t)n + 1, 0);
+    nadj->clear();
+    nadj->reserve(adj.size());
+    for (int64_t x = 0; x < n; ++x) {
+        for (int64_t e = off[(size_t)x]; e < off[(size_t)x + 1]; ++e) {
+            const int32_t y = adj[(size_t)e];
+            if (!((x == a && y == b) || (x == b && y == a))) nadj->push_back(y);
+        }
+        (*noff)[(size_t)x + 1] = (int64_t)nadj->size();
+    }
+}
+
+// R(a, b) on the current graph from the resident trees: per tree, the
+// signed count of the edges of a fixed breadth-first a -> b path that the
+// tree's own a -> b path uses (its mean over uniform trees is R(a, b)).
+static kc_status path_currents(kc_graph *g, int32_t a, int32_t b, std::vector<int64_t> *c, hipStream_t stream) {
+    const std::vector<int32_t> path = reference_path(g->h_off, g->h_adj, a, b);
+    if (path.size() < 2) return fail(KC_ERR_DEVICE, "no path between %d and %d", a, b);
+    int32_t *d_path = nullptr;
+    int64_t *d_c = nullptr;
+    HIP_TRY(dev_alloc(&d_path, path.size()));
+    HIP_TRY(dev_alloc(&d_c, (size_t)g->res_count));
+    HIP_TRY(hipMemcpyAsync(d_path, path.data(), path.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    kc::RunParams rp{};
+    rp.count = g->res_count;
+    rp.mode = kc::RUN_CURRENT;
+    rp.parents_in = g->d_res_par;
+    rp.f_out = d_c;
+    rp.path = d_path;
+    rp.path_len = (int32_t)path.size();
+    kc_status st = run_persistent(g, rp, stream);
+    c->assign((size_t)g->res_count, 0);
+    if (st == KC_OK) {
+        const hipError_t e = hipMemcpy(c->data(), d_c, c->size() * sizeof(int64_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) st = fail(KC_ERR_DEVICE, "copy failed: %s", hipGetErrorString(e));
+    }
+    dev_free(d_path);
+    dev_free(d_c);
+    return st;
+}
+
 // One insertion (Algorithm 2, insertion case; Theorem 4.1).
 static kc_status apply_insertion(kc_graph *g, int32_t a, int32_t b, int32_t *resampled, hipStream_t stream) {
     const int64_t n = g->n;
@@ -1019,20 +1133,9 @@ static kc_status apply_insertion(kc_graph *g, int32_t a, int32_t b, int32_t *res
         return fail(KC_ERR_INVALID, "edge (%d,%d) is already in the graph", a, b);
     if (g->two_m + 2 >= (1ll << 31)) return fail(KC_ERR_OVERFLOW, "2m would reach 2^31");
     // G' = G + (a, b)
-    std::vector<int64_t> noff((size_t)n + 1, 0);
+    std::vector<int64_t> noff;
     std::vector<int32_t> nadj;
-    nadj.reserve(g->h_adj.size() + 2);
-    for (int64_t x = 0; x < n; ++x) {
-        const int32_t add = x == a ? b : x == b ? a : -1;
-        bool done = add < 0;
-        for (int64_t e = g->h_off[(size_t)x]; e < g->h_off[(size_t)x + 1]; ++e) {
-            const int32_t y = g->h_adj[(size_t)e];
-            if (!done && add < y) { nadj.push_back(add); done = true; }
-            nadj.push_back(y);
-        }
-        if (!done) nadj.push_back(add);
-        noff[(size_t)x + 1] = (int64_t)nadj.size();
-    }
+    csr_with_edge(g->h_off, g->h_adj, a, b, &noff, &nadj);
     {
         PreparedGraph probe;  // tau0 of G' must pass the overflow bound; nothing changes if not
         const kc_status st = prepare_graph(noff, nadj, g->root, g->tau0_kind, &g->h_tau0, &probe);
@@ -1040,29 +1143,8 @@ static kc_status apply_insertion(kc_graph *g, int32_t a, int32_t b, int32_t *res
     }
     std::vector<int32_t> redo;
     if (g->res_count > 0) {
-        // R(a, b) on the current graph from the set's own trees
-        const std::vector<int32_t> path = reference_path(g->h_off, g->h_adj, a, b);
-        if (path.size() < 2) return fail(KC_ERR_DEVICE, "no path between %d and %d", a, b);
-        int32_t *d_path = nullptr;
-        int64_t *d_c = nullptr;
-        HIP_TRY(dev_alloc(&d_path, path.size()));
-        HIP_TRY(dev_alloc(&d_c, (size_t)g->res_count));
-        HIP_TRY(hipMemcpyAsync(d_path, path.data(), path.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
-        kc::RunParams rp{};
-        rp.count = g->res_count;
-        rp.mode = kc::RUN_CURRENT;
-        rp.parents_in = g->d_res_par;
-        rp.f_out = d_c;
-        rp.path = d_path;
-        rp.path_len = (int32_t)path.size();
-        kc_status st = run_persistent(g, rp, stream);
-        std::vector<int64_t> c((size_t)g->res_count);
-        if (st == KC_OK) {
-            const hipError_t e = hipMemcpy(c.data(), d_c, c.size() * sizeof(int64_t), hipMemcpyDeviceToHost);
-            if (e != hipSuccess) st = fail(KC_ERR_DEVICE, "copy failed: %s", hipGetErrorString(e));
-        }
-        dev_free(d_path);
-        dev_free(d_c);
+        std::vector<int64_t> c;
+        kc_status st = path_currents(g, a, b, &c, stream);
         if (st != KC_OK) return st;
         int64_t csum = 0;
         for (int64_t x : c) csum += x;
@@ -1113,6 +1195,185 @@ static kc_status apply_insertion(kc_graph *g, int32_t a, int32_t b, int32_t *res
     return KC_OK;
 }
 
+// Per-tree integers of an improved-maintenance step, computed on the device for
+// the resident trees `rows` (DEVICE copies made here).
+static kc_status ism_link_cut(kc_graph *g, const std::vector<int32_t> &rows, int32_t a, int32_t b, int relink,
+                              std::vector<int64_t> *d, hipStream_t stream) {
+    const int32_t k = (int32_t)rows.size();
+    d->assign((size_t)k, 0);
+    if (k == 0) return KC_OK;
+    int32_t *d_rows = nullptr;
+    int64_t *d_d = nullptr;
+    HIP_TRY(dev_alloc(&d_rows, (size_t)k));
+    HIP_TRY(dev_alloc(&d_d, (size_t)k));
+    HIP_TRY(hipMemcpyAsync(d_rows, rows.data(), (size_t)k * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    HIP_TRY(kc::launch_reset_ctl(g->d_ctl, stream));
+    HIP_TRY(kc::launch_link_cut(g->d_res_par, d_rows, k, g->n, a, b, g->res_seed, (uint32_t)g->res_serial, relink,
+                                d_d, g->d_ctl, stream));
+    int32_t ctl[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(ctl, g->d_ctl, sizeof(ctl), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(d->data(), d_d, (size_t)k * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    dev_free(d_rows);
+    dev_free(d_d);
+    if (ctl[1] != 0) return fail(KC_ERR_INVALID, "resident tree %d is not a tree rooted at %d", rows[(size_t)ctl[2]], g->root);
+    return KC_OK;
+}
+
+static kc_status ism_cross(kc_graph *g, const std::vector<int32_t> &rows, int32_t a, int32_t b, int relink,
+                           std::vector<int64_t> *d, hipStream_t stream) {
+    const int32_t k = (int32_t)rows.size();
+    d->assign((size_t)k, 0);
+    if (k == 0) return KC_OK;
+    int32_t *d_rows = nullptr;
+    int64_t *d_d = nullptr;
+    HIP_TRY(dev_alloc(&d_rows, (size_t)k));
+    HIP_TRY(dev_alloc(&d_d, (size_t)k));
+    HIP_TRY(hipMemcpyAsync(d_rows, rows.data(), (size_t)k * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    kc::RunParams rp{};
+    rp.count = k;
+    rp.mode = kc::RUN_CROSS;
+    rp.seed = g->res_seed;
+    rp.parents_in = g->d_res_par;
+    rp.parents_mut = g->d_res_par;
+    rp.rows = d_rows;
+    rp.f_out = d_d;
+    rp.cut_u = a;
+    rp.cut_v = b;
+    rp.relink = relink;
+    rp.serial = (uint32_t)g->res_serial;
+    kc_status st = run_persistent(g, rp, stream);
+    if (st == KC_OK) {
+        const hipError_t e = hipMemcpy(d->data(), d_d, (size_t)k * sizeof(int64_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) st = fail(KC_ERR_DEVICE, "copy failed: %s", hipGetErrorString(e));
+    }
+    dev_free(d_rows);
+    dev_free(d_d);
+    return st;
+}
+
+static void normalise(std::vector<double> &w, const std::vector<int32_t> &group, double target) {
+    double s = 0.0;
+    for (int32_t t : group) s += w[(size_t)t];
+    for (int32_t t : group) w[(size_t)t] *= target / s;
+}
+
+// One insertion by improved sample maintenance (Algorithm 3; Theorem 4.4).
+static kc_status ism_insertion(kc_graph *g, int32_t a, int32_t b, int32_t *changed, hipStream_t stream) {
+    const int64_t n = g->n;
+    if (a < 0 || a >= n || b < 0 || b >= n || a == b) return fail(KC_ERR_INVALID, "bad edge (%d,%d)", a, b);
+    if (std::binary_search(g->h_adj.begin() + g->h_off[(size_t)a], g->h_adj.begin() + g->h_off[(size_t)a + 1], b))
+        return fail(KC_ERR_INVALID, "edge (%d,%d) is already in the graph", a, b);
+    if (g->two_m + 2 >= (1ll << 31)) return fail(KC_ERR_OVERFLOW, "2m would reach 2^31");
+    std::vector<int64_t> noff;
+    std::vector<int32_t> nadj;
+    csr_with_edge(g->h_off, g->h_adj, a, b, &noff, &nadj);
+    {
+        PreparedGraph probe;
+        const kc_status st = prepare_graph(noff, nadj, g->root, g->tau0_kind, &g->h_tau0, &probe);
+        if (st != KC_OK) return st;
+    }
+    const int32_t count = g->res_count;
+    // R(a, b) from the weighted set; R' = R / (1 + R) is the share of G''s trees through e
+    std::vector<int64_t> c;
+    kc_status st = path_currents(g, a, b, &c, stream);
+    if (st != KC_OK) return st;
+    double rhat = 0.0;
+    for (int32_t t = 0; t < count; ++t) rhat += g->res_w[(size_t)t] * (double)c[(size_t)t];
+    const double rp = rhat / (1.0 + rhat);
+    const int32_t k = (int32_t)std::min<double>((double)count, std::ceil(rp * (double)count));
+    // ceil(R' |S|) trees chosen uniformly: the smallest replacement draws
+    std::vector<std::pair<double, int32_t>> key((size_t)count);
+    for (int32_t t = 0; t < count; ++t)
+        key[(size_t)t] = {update_uniform(g->res_seed, (uint32_t)t, (uint32_t)g->res_serial), t};
+    std::sort(key.begin(), key.end());
+    std::vector<int32_t> chosen, rest;
+    for (int32_t i = 0; i < count; ++i) (i < k ? chosen : rest).push_back(key[(size_t)i].second);
+    std::sort(chosen.begin(), chosen.end());
+    std::sort(rest.begin(), rest.end());
+    // link-cut in place (graph-independent); d(tau) = tree path length between a and b
+    std::vector<int64_t> d_old, d_new;
+    st = ism_link_cut(g, chosen, a, b, 1, &d_old, stream);
+    if (st != KC_OK) return st;
+    g->h_off.swap(noff);
+    g->h_adj.swap(nadj);
+    st = rebuild_graph(g, g->root, stream);
+    if (st != KC_OK) return st;
+    // d(tau_e): edges of G that join the two parts of tau_e - e (those of G' minus e itself)
+    st = ism_cross(g, chosen, a, b, 0, &d_new, stream);
+    if (st != KC_OK) return st;
+    for (size_t i = 0; i < chosen.size(); ++i)
+        g->res_w[(size_t)chosen[i]] *= (double)d_old[i] / (double)(d_new[i] - 1);
+    if (!chosen.empty() && !rest.empty()) {
+        normalise(g->res_w, chosen, rp);
+        normalise(g->res_w, rest, 1.0 - rp);
+    } else {
+        normalise(g->res_w, chosen.empty() ? rest : chosen, 1.0);
+    }
+    st = kc_evaluate_trees(g, g->d_res_par, count, g->d_res_f, (void *)stream);
+    if (st != KC_OK) return st;
+    HIP_TRY(hipStreamSynchronize(stream));
+    g->res_serial += 1;
+    if (changed) *changed += k;
+    return KC_OK;
+}
+
+// One deletion by improved sample maintenance (Algorithm 3; Theorem 4.5); the
+// graph stays connected (checked by the caller for the whole run).
+static kc_status ism_deletion(kc_graph *g, int32_t a, int32_t b, int32_t *changed, hipStream_t stream) {
+    const int32_t count = g->res_count;
+    const int64_t n = g->n;
+    std::vector<int32_t> hit;
+    {
+        int32_t eu = a, ev = b;
+        int32_t *d_eu = nullptr, *d_ev = nullptr;
+        uint8_t *d_flags = nullptr;
+        HIP_TRY(dev_alloc(&d_eu, 1));
+        HIP_TRY(dev_alloc(&d_ev, 1));
+        HIP_TRY(dev_alloc(&d_flags, (size_t)count));
+        HIP_TRY(hipMemcpyAsync(d_eu, &eu, sizeof(int32_t), hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(d_ev, &ev, sizeof(int32_t), hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemsetAsync(d_flags, 0, (size_t)count, stream));
+        HIP_TRY(kc::launch_flag_trees(g->d_res_par, count, n, d_eu, d_ev, 1, d_flags, stream));
+        std::vector<uint8_t> flags((size_t)count);
+        HIP_TRY(hipMemcpyAsync(flags.data(), d_flags, flags.size(), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        dev_free(d_eu);
+        dev_free(d_ev);
+        dev_free(d_flags);
+        for (int32_t t = 0; t < count; ++t)
+            if (flags[(size_t)t]) hit.push_back(t);
+    }
+    double w_org = 0.0;
+    for (int32_t t : hit) w_org += g->res_w[(size_t)t];
+    std::vector<int64_t> noff;
+    std::vector<int32_t> nadj;
+    csr_without_edge(g->h_off, g->h_adj, a, b, &noff, &nadj);
+    if (g->tau0_kind == KC_TAU0_GIVEN && (g->h_tau0[(size_t)a] == b || g->h_tau0[(size_t)b] == a)) {
+        g->tau0_kind = KC_TAU0_BFS;
+        g->h_tau0.clear();
+    }
+    g->h_off.swap(noff);
+    g->h_adj.swap(nadj);
+    kc_status st = rebuild_graph(g, g->root, stream);
+    if (st != KC_OK) return st;
+    // cut-link in place; d(tau) = edges of G' that join the two parts of tau - e
+    std::vector<int64_t> d_old, d_new;
+    st = ism_cross(g, hit, a, b, 1, &d_old, stream);
+    if (st != KC_OK) return st;
+    // d(tau') = tree path length between a and b in the new tree
+    st = ism_link_cut(g, hit, a, b, 0, &d_new, stream);
+    if (st != KC_OK) return st;
+    for (size_t i = 0; i < hit.size(); ++i) g->res_w[(size_t)hit[i]] *= (double)d_old[i] / (double)d_new[i];
+    if (!hit.empty()) normalise(g->res_w, hit, w_org);
+    st = kc_evaluate_trees(g, g->d_res_par, count, g->d_res_f, (void *)stream);
+    if (st != KC_OK) return st;
+    HIP_TRY(hipStreamSynchronize(stream));
+    g->res_serial += 1;
+    if (changed) *changed += (int32_t)hit.size();
+    return KC_OK;
+}
+
 kc_status kc_apply_updates(kc_graph *g, const int32_t *u, const int32_t *v, const uint8_t *is_insert,
                            int32_t count, int32_t *resampled, void *hip_stream) {
     g_last_error.clear();
@@ -1123,7 +1384,9 @@ kc_status kc_apply_updates(kc_graph *g, const int32_t *u, const int32_t *v, cons
     int32_t k = 0;
     while (k < count) {
         if (is_insert && is_insert[k]) {
-            const kc_status st = apply_insertion(g, u[k], v[k], resampled, stream);
+            const kc_status st = g->maint == KC_MAINT_IMPROVED && g->res_count > 0
+                                     ? ism_insertion(g, u[k], v[k], resampled, stream)
+                                     : apply_insertion(g, u[k], v[k], resampled, stream);
             if (st != KC_OK) return st;
             ++k;
         } else {

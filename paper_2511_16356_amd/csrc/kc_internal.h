@@ -41,7 +41,12 @@ struct SlotDev {
     int64_t fen_len; // 2m + 2 (0 if not allocated)
 };
 
-enum RunMode { RUN_SAMPLE = 0, RUN_ESTIMATE = 1, RUN_EVALUATE = 2, RUN_CURRENT = 3 };
+enum RunMode { RUN_SAMPLE = 0, RUN_ESTIMATE = 1, RUN_EVALUATE = 2, RUN_CURRENT = 3, RUN_CROSS = 4 };
+
+// Counter words 2 and 3 of the Philox draw that picks a link-cut or cut-link
+// edge: (tree slot, update number, ISM_CTR_LO, ISM_CTR_HI), a counter no tree
+// sample uses.
+constexpr uint32_t ISM_CTR_LO = 0xFFFFFFFEu, ISM_CTR_HI = 0xFFFFFFFFu;
 
 struct RunParams {
     uint64_t seed;
@@ -63,6 +68,11 @@ struct RunParams {
     int32_t root_v = -1;       // the graph's root (a forest of two trees rooted at u and v)
     const int32_t *path = nullptr;  // RUN_CURRENT: vertices of a u -> v path in the graph
     int32_t path_len = 0;           //              number of vertices (>= 2)
+    const int32_t *rows = nullptr;  // modes that read parents_in: tree idx is row rows[idx] (null: idx)
+    int32_t *parents_mut = nullptr; // RUN_CROSS with relink: the same rows, rewritten in place
+    int32_t cut_u = -1, cut_v = -1; // RUN_CROSS: the tree edge whose removal splits the tree
+    int32_t relink = 0;             // RUN_CROSS: also re-join by a drawn crossing edge
+    uint32_t serial = 0;            // RUN_CROSS: update number of that draw
 };
 
 // Device result of the exact reduction.
@@ -88,6 +98,9 @@ hipError_t launch_reduce(const int64_t *f, const int64_t *steps, const int64_t *
 hipError_t launch_zero_i64(int64_t *p, int64_t len, hipStream_t stream);
 hipError_t launch_reroot(int32_t *par, int32_t count, int64_t n, int32_t u, int32_t v, int32_t r,
                          hipStream_t stream);
+hipError_t launch_link_cut(int32_t *par, const int32_t *rows, int32_t count, int64_t n, int32_t u, int32_t v,
+                           uint64_t seed, uint32_t serial, int relink, int64_t *d_out, int32_t *ctl,
+                           hipStream_t stream);
 hipError_t launch_flag_trees(const int32_t *par, int32_t count, int64_t n, const int32_t *eu,
                              const int32_t *ev, int32_t ne, uint8_t *flags, hipStream_t stream);
 bool valid_chains(int chains);            // a built chain-table size?

@@ -442,3 +442,135 @@ def test_bsm_mixed_updates_unbiased_on_grid(gen, oracle_lib):
             S, _ = oracle_lib.bsm_delete(S, g.offsets, g.indices, [e])
         K, se, _, _ = oracle_lib.reduce_estimate(S.f, g.two_m)
         assert abs(K - E.kemeny_exact(g.offsets, g.indices)) < 4.5 * se
+
+
+# ------------------------------------- improved sample maintenance (Algorithm 3)
+
+def _ism_cases(gen):
+    # (graph, non-edge to insert), (graph, non-bridge edge to delete)
+    return [(gen.grid(3, 3), (0, 8)), (gen.cycle(6), (0, 3)), (gen.petersen(), (0, 2)),
+            (gen.gnm(7, 11, 1), None), (gen.complete(4), None)]
+
+
+def _non_edge(g):
+    for x in range(g.n):
+        row = set(int(y) for y in g.indices[g.offsets[x]:g.offsets[x + 1]])
+        for y in range(x + 1, g.n):
+            if y not in row:
+                return (x, y)
+    return None
+
+
+def test_link_cut_bipartite_theorem_4_4(gen, oracle_lib):
+    """Theorem 4.4 exactly, by enumeration.  Over all trees tau of G and all
+    d(tau) link-cut choices, every spanning tree of G' = G + e through e is
+    reached exactly d(tau_e) times (the number of edges of G joining the two
+    parts of tau_e - e); hence the weighted mean of f' with weights
+    d(tau)/d(tau_e) is the mean of f' over the trees of G' through e, and the
+    weights themselves average R/(1-R) with R the share of G''s trees through e."""
+    from oracle import exact as E
+    for g, e in _ism_cases(gen):
+        if e is None:
+            e = _non_edge(g)
+        if e is None:
+            continue
+        u, v = e
+        root = oracle_lib.prepare_graph(g).root
+        g2 = gen.add_edges(g, [e])
+        P2 = oracle_lib.prepare(g2.offsets, g2.indices, root)
+        old = E.spanning_trees(g.offsets, g.indices, root)
+        new = E.spanning_trees(g2.offsets, g2.indices, root)
+        through = {tuple(int(x) for x in t): t for t in new if t[u] == v or t[v] == u}
+        reached = {k: 0 for k in through}
+        wf = Fraction(0)
+        wsum = Fraction(0)
+        for t in old:
+            up, dn = oracle_lib.tree_path(t, u, v)
+            d = len(up) + len(dn)
+            for j in range(d):
+                te, d_old = oracle_lib.link_cut(t, u, v, j)
+                assert d_old == d
+                key = tuple(int(x) for x in te)
+                assert key in through, (g.name, "link-cut left the trees of G' through e")
+                reached[key] += 1
+                d_new = len(oracle_lib.crossing_edges(g2.offsets, g2.indices, te, u, v)[0]) - 1
+                w = Fraction(d, d_new) / d          # choice probability 1/d(tau), weight d(tau)/d(tau_e)
+                wf += w * oracle_lib.f_of_tree(P2, te)
+                wsum += w
+        for key, t in through.items():
+            assert reached[key] == len(oracle_lib.crossing_edges(g2.offsets, g2.indices, t, u, v)[0]) - 1
+        mean_through = Fraction(sum(oracle_lib.f_of_tree(P2, t) for t in through.values()), len(through))
+        assert wf / wsum == mean_through
+        assert wsum / len(old) == Fraction(len(through), len(old))   # = R / (1 - R)
+
+
+def test_cut_link_bipartite_theorem_4_5(gen, oracle_lib):
+    """Theorem 4.5 exactly, by enumeration: over all trees of G through e and all
+    cut-link choices, every spanning tree of G' = G - e is reached exactly
+    d(tau') times (the length of its tree path between the endpoints of e), so
+    weights d(tau)/d(tau') (old over new, as in the theorem) give the mean of f'
+    over all trees of G'.  The weight printed in Algorithm 3's deletion branch,
+    d(tau')/d(tau), gives a different mean on some of these graphs."""
+    from oracle import exact as E
+    printed_differs = False
+    for g, _ in _ism_cases(gen):
+        src = np.repeat(np.arange(g.n), np.diff(g.offsets))
+        cand = [(int(a), int(b)) for a, b in zip(src, g.indices) if a < b]
+        root = oracle_lib.prepare_graph(g).root
+        for a, b in cand[:: max(1, len(cand) // 3)]:
+            g2 = gen.remove_edges(g, [(a, b)])
+            if not gen.is_connected(g2):
+                continue
+            P2 = oracle_lib.prepare(g2.offsets, g2.indices, root)
+            old = [t for t in E.spanning_trees(g.offsets, g.indices, root) if t[a] == b or t[b] == a]
+            new = {tuple(int(x) for x in t): t for t in E.spanning_trees(g2.offsets, g2.indices, root)}
+            reached = {k: 0 for k in new}
+            wf = wsum = pf = psum = Fraction(0)
+            for t in old:
+                d = len(oracle_lib.crossing_edges(g2.offsets, g2.indices, t, a, b)[0])
+                for j in range(d):
+                    tn, d_old = oracle_lib.cut_link(t, g2.offsets, g2.indices, a, b, j)
+                    assert d_old == d
+                    key = tuple(int(x) for x in tn)
+                    assert key in new
+                    reached[key] += 1
+                    up, dn = oracle_lib.tree_path(tn, a, b)
+                    d_new = len(up) + len(dn)
+                    f = oracle_lib.f_of_tree(P2, tn)
+                    wf += Fraction(d, d_new) / d * f
+                    wsum += Fraction(d, d_new) / d
+                    pf += Fraction(d_new, d) / d * f
+                    psum += Fraction(d_new, d) / d
+            for key, t in new.items():
+                up, dn = oracle_lib.tree_path(t, a, b)
+                assert reached[key] == len(up) + len(dn)
+            mean_new = Fraction(sum(oracle_lib.f_of_tree(P2, t) for t in new.values()), len(new))
+            assert wf / wsum == mean_new
+            printed_differs |= pf / psum != mean_new
+    assert printed_differs
+
+
+def test_ism_estimate_tracks_exact_kemeny(gen, oracle_lib):
+    """Algorithm 3 end to end on a 4x4 grid: an insertion, then a deletion of
+    an edge, each over 120 independent sets of 24 trees.  The mean
+    weighted estimate is within 4 standard errors of the exact kappa of the
+    new graph, and the weights always sum to one."""
+    from oracle import exact as E
+    g0 = gen.grid(4, 4)
+    g1 = gen.add_edges(g0, [(0, 15)])
+    g2 = gen.remove_edges(g1, [(5, 6)])
+    k1 = E.kemeny_exact(g1.offsets, g1.indices)
+    k2 = E.kemeny_exact(g2.offsets, g2.indices)
+    e1, e2 = [], []
+    for seed in range(120):
+        W = oracle_lib.ism_init(g0.offsets, g0.indices, seed=seed, count=24, threads=1)
+        W, _ = oracle_lib.ism_insert(W, g1.offsets, g1.indices, 0, 15)
+        assert abs(sum(W.w) - 1.0) < 1e-12
+        e1.append(oracle_lib.weighted_estimate(W)[0])
+        W, _ = oracle_lib.ism_delete(W, g2.offsets, g2.indices, 5, 6)
+        assert abs(sum(W.w) - 1.0) < 1e-12
+        e2.append(oracle_lib.weighted_estimate(W)[0])
+    for est, k in ((e1, k1), (e2, k2)):
+        est = np.array(est)
+        se = est.std(ddof=1) / math.sqrt(len(est))
+        assert abs(est.mean() - k) < 4 * se + 1e-3 * k, (est.mean(), k, se)
