@@ -65,12 +65,14 @@ def cpu_baseline(g, seed: int, first: int, threads: int, per_thread: int):
                       (first, first + count - 1, per_thread, dt)}
 
 
-def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: float, duration: float):
+def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: float, duration: float,
+                maintenance: int = 0):
     """Served query and update latency on resident graphs (continuous batching,
     paper_2511_16356_amd.serve): Poisson arrivals, 80% Kemeny queries and 20%
     update batches, half deletions (sizes log-uniform in [1, 1000], batches
     that keep the graph connected) and half insertions (sizes log-uniform in
-    [1, 10]); edges drawn with probability proportional to d(u) d(v)."""
+    [1, 10]); edges drawn with probability proportional to d(u) d(v).  The
+    same seed gives the same graphs and requests for either maintenance."""
     import numpy as np
     import torch
     import graphgen
@@ -99,7 +101,7 @@ def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: fl
         else:
             plan.append((float(t), gid, "query", [], False))
     log("serving: %d graphs, %d requests planned (%.1f s)" % (graphs, n_req, time.perf_counter() - t_gen))
-    srv = Server(budget_bytes=32 << 30, update_share=4 << 30)
+    srv = Server(budget_bytes=32 << 30, update_share=4 << 30, maintenance=maintenance)
     try:
         t_init = time.perf_counter()
         for gid, g in enumerate(gs):
@@ -125,10 +127,11 @@ def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: fl
                         "80%% queries / 20%% update batches: half deletions (1-1000 edges), half "
                         "insertions (1-10 edges), edges with prob. ~ d(u)d(v)"
                         % (graphs, lo, hi, samples, rate, duration),
+            "maintenance": "improved (Algorithm 3)" if maintenance else "basic (Algorithm 2)",
             "requests": len(reqs), "errors": errors, "makespan_s": makespan,
             "throughput_req_per_s": len(reqs) / makespan,
             "query": latency_stats(reqs, "query"), "update": latency_stats(reqs, "update"),
-            "trees_replaced": int(sum(r.result for r in reqs if r.kind == "update" and not r.error)),
+            "trees_changed": int(sum(r.result for r in reqs if r.kind == "update" and not r.error)),
         }
     finally:
         srv.close()
@@ -368,6 +371,8 @@ def main():
     if not args.no_serve:
         out["served"] = serving_leg(args.seed + 7, args.serve_graphs, 10_000, 30_000, 1024,
                                     args.serve_rate, args.serve_seconds)
+        out["served_improved"] = serving_leg(args.seed + 7, args.serve_graphs, 10_000, 30_000, 1024,
+                                             args.serve_rate, args.serve_seconds, maintenance=1)
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         try:

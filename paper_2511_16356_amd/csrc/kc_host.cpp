@@ -82,6 +82,7 @@ struct kc_graph {
                                       // updates applied so far (the counter of their draws)
     int32_t maint = KC_MAINT_BASIC;   // sample maintenance of the resident set
     std::vector<double> res_w;        // improved maintenance: weight of each tree (sum 1)
+    bool res_f_stale = false;         // the graph changed since d_res_f was computed
     std::vector<int64_t> res_ids;     // sample index of each resident tree
     int32_t *d_res_par = nullptr;     // [res_count * n] parents
     int64_t *d_res_f = nullptr;       // [res_count] f of each tree on the current graph
@@ -948,7 +949,7 @@ kc_status kc_samples_get(const kc_graph *g, int32_t *parents_out, int64_t *f_out
     return KC_OK;
 }
 
-static kc_status ism_deletion(kc_graph *g, int32_t a, int32_t b, int32_t *changed, hipStream_t stream);
+static kc_status ism_deletion(kc_graph *g, int32_t a, int32_t b, int32_t *changed, hipStream_t stream, bool last);
 
 // A run of deletions, applied at once (Algorithm 2, deletion case).
 static kc_status apply_deletions(kc_graph *g, const int32_t *u, const int32_t *v, int32_t count,
@@ -996,7 +997,7 @@ static kc_status apply_deletions(kc_graph *g, const int32_t *u, const int32_t *v
         // Algorithm 3 takes one edge at a time; every intermediate graph contains
         // the final one, so it is connected too
         for (int32_t k = 0; k < count; ++k) {
-            const kc_status st = ism_deletion(g, u[k], v[k], resampled, stream);
+            const kc_status st = ism_deletion(g, u[k], v[k], resampled, stream, k == count - 1);
             if (st != KC_OK) return st;
         }
         return KC_OK;
@@ -1051,10 +1052,8 @@ static kc_status apply_deletions(kc_graph *g, const int32_t *u, const int32_t *v
             dev_free(d_tmp);
             g->res_next += k;
         }
-        // every tree's f on G' (degrees, 2m and tau0 changed)
-        st = kc_evaluate_trees(g, g->d_res_par, g->res_count, g->d_res_f, (void *)stream);
-        if (st != KC_OK) return st;
-        HIP_TRY(hipStreamSynchronize(stream));
+        // every tree's f on G' (degrees, 2m and tau0 changed), at the end of the call
+        g->res_f_stale = true;
         if (resampled) *resampled += k;
     }
     return KC_OK;
@@ -1186,9 +1185,7 @@ static kc_status apply_insertion(kc_graph *g, int32_t a, int32_t b, int32_t *res
             dev_free(d_tmp);
             g->res_next += k;
         }
-        st = kc_evaluate_trees(g, g->d_res_par, g->res_count, g->d_res_f, (void *)stream);
-        if (st != KC_OK) return st;
-        HIP_TRY(hipStreamSynchronize(stream));
+        g->res_f_stale = true;
         g->res_serial += 1;
         if (resampled) *resampled += k;
     }
@@ -1310,17 +1307,30 @@ static kc_status ism_insertion(kc_graph *g, int32_t a, int32_t b, int32_t *chang
     } else {
         normalise(g->res_w, chosen.empty() ? rest : chosen, 1.0);
     }
-    st = kc_evaluate_trees(g, g->d_res_par, count, g->d_res_f, (void *)stream);
-    if (st != KC_OK) return st;
-    HIP_TRY(hipStreamSynchronize(stream));
+    g->res_f_stale = true;
     g->res_serial += 1;
     if (changed) *changed += k;
     return KC_OK;
 }
 
+// The device CSR of an intermediate graph of a deletion run: cut-link and the
+// tree numbering read only the row offsets and neighbours, and the rows only
+// shrink, so they are copied into the arrays of the last full rebuild.
+static kc_status upload_csr_only(kc_graph *g, hipStream_t stream) {
+    HIP_TRY(hipStreamSynchronize(stream));  // no running launch reads the old rows
+    HIP_TRY(hipMemcpyAsync(g->d_off, g->h_off.data(), g->h_off.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                           stream));
+    HIP_TRY(hipMemcpyAsync(g->d_adj, g->h_adj.data(), g->h_adj.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    g->two_m = g->h_off[(size_t)g->n];
+    return KC_OK;
+}
+
 // One deletion by improved sample maintenance (Algorithm 3; Theorem 4.5); the
-// graph stays connected (checked by the caller for the whole run).
-static kc_status ism_deletion(kc_graph *g, int32_t a, int32_t b, int32_t *changed, hipStream_t stream) {
+// graph stays connected (checked by the caller for the whole run).  Only the
+// run's last edge rebuilds tau0 and the other per-graph arrays.
+static kc_status ism_deletion(kc_graph *g, int32_t a, int32_t b, int32_t *changed, hipStream_t stream, bool last) {
     const int32_t count = g->res_count;
     const int64_t n = g->n;
     std::vector<int32_t> hit;
@@ -1355,7 +1365,7 @@ static kc_status ism_deletion(kc_graph *g, int32_t a, int32_t b, int32_t *change
     }
     g->h_off.swap(noff);
     g->h_adj.swap(nadj);
-    kc_status st = rebuild_graph(g, g->root, stream);
+    kc_status st = last ? rebuild_graph(g, g->root, stream) : upload_csr_only(g, stream);
     if (st != KC_OK) return st;
     // cut-link in place; d(tau) = edges of G' that join the two parts of tau - e
     std::vector<int64_t> d_old, d_new;
@@ -1366,9 +1376,7 @@ static kc_status ism_deletion(kc_graph *g, int32_t a, int32_t b, int32_t *change
     if (st != KC_OK) return st;
     for (size_t i = 0; i < hit.size(); ++i) g->res_w[(size_t)hit[i]] *= (double)d_old[i] / (double)d_new[i];
     if (!hit.empty()) normalise(g->res_w, hit, w_org);
-    st = kc_evaluate_trees(g, g->d_res_par, count, g->d_res_f, (void *)stream);
-    if (st != KC_OK) return st;
-    HIP_TRY(hipStreamSynchronize(stream));
+    g->res_f_stale = true;
     g->res_serial += 1;
     if (changed) *changed += (int32_t)hit.size();
     return KC_OK;
@@ -1382,22 +1390,33 @@ kc_status kc_apply_updates(kc_graph *g, const int32_t *u, const int32_t *v, cons
     if (resampled) *resampled = 0;
     hipStream_t stream = (hipStream_t)hip_stream;
     int32_t k = 0;
-    while (k < count) {
+    kc_status st = KC_OK;
+    while (k < count && st == KC_OK) {
         if (is_insert && is_insert[k]) {
-            const kc_status st = g->maint == KC_MAINT_IMPROVED && g->res_count > 0
-                                     ? ism_insertion(g, u[k], v[k], resampled, stream)
-                                     : apply_insertion(g, u[k], v[k], resampled, stream);
-            if (st != KC_OK) return st;
+            st = g->maint == KC_MAINT_IMPROVED && g->res_count > 0 ? ism_insertion(g, u[k], v[k], resampled, stream)
+                                                                   : apply_insertion(g, u[k], v[k], resampled, stream);
             ++k;
         } else {
             int32_t e = k;
             while (e < count && !(is_insert && is_insert[e])) ++e;
-            const kc_status st = apply_deletions(g, u + k, v + k, e - k, resampled, stream);
-            if (st != KC_OK) return st;
+            st = apply_deletions(g, u + k, v + k, e - k, resampled, stream);
             k = e;
         }
     }
-    return KC_OK;
+    // f of every resident tree on the graph as it now stands (no update reads f,
+    // so it is computed once per call), also when a later update failed
+    if (g->res_f_stale && g->res_count > 0) {
+        const std::string err = g_last_error;
+        const kc_status st2 = kc_evaluate_trees(g, g->d_res_par, g->res_count, g->d_res_f, hip_stream);
+        if (st2 == KC_OK) {
+            g->res_f_stale = false;
+            if (st != KC_OK) g_last_error = err;
+        } else if (st == KC_OK) {
+            st = st2;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(stream));
+    return st;
 }
 
 }  // extern "C"

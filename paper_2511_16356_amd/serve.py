@@ -3,7 +3,8 @@
 Each graph keeps its CSR, tau0 and a resident sample set on the device
 (``kc_samples_init``).  A query answers the estimate of Theorem 3.3 over the
 graph's current trees (``kc_samples_query``); an update batch applies basic
-sample maintenance (section 4.1, Algorithm 2; ``kc_apply_updates``).
+(section 4.1, Algorithm 2) or improved (section 4.2, Algorithm 3) sample
+maintenance (``kc_apply_updates``).
 
 Scheduling (continuous batching): every graph has its own HIP stream and one
 worker thread that takes that graph's requests in arrival order, so requests
@@ -26,7 +27,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import Graph, KC_OPT_MEM_BUDGET, KcError
+from . import Graph, KC_OPT_MEM_BUDGET, KC_OPT_MAINTENANCE, KC_MAINT_BASIC, KcError
 
 
 @dataclass
@@ -67,9 +68,10 @@ class _Budget:
 class Server:
     """Resident graphs and their request workers."""
 
-    def __init__(self, budget_bytes: int, update_share: int):
+    def __init__(self, budget_bytes: int, update_share: int, maintenance: int = KC_MAINT_BASIC):
         self.budget = _Budget(budget_bytes)
         self.update_share = update_share   # device bytes one update may use
+        self.maintenance = maintenance     # KC_MAINT_BASIC (Algorithm 2) or KC_MAINT_IMPROVED (Algorithm 3)
         self.graphs = {}
         self.queues = {}
         self.threads = {}
@@ -83,6 +85,7 @@ class Server:
         stream = torch.cuda.Stream()
         G = Graph.from_graph(g, stream=stream)
         G.set_option(KC_OPT_MEM_BUDGET, self.update_share)
+        G.set_option(KC_OPT_MAINTENANCE, self.maintenance)
         G.samples_init(seed, samples, stream=stream)
         self.graphs[gid] = G
         self.streams[gid] = stream

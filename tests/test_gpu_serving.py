@@ -41,9 +41,9 @@ def _ops(gen, g, seed, rounds):
     return ops
 
 
-def _serve(kc, graphs, ops, order):
+def _serve(kc, graphs, ops, order, maintenance=0):
     from paper_2511_16356_amd.serve import Server, Request
-    srv = Server(budget_bytes=8 << 30, update_share=2 << 30)
+    srv = Server(budget_bytes=8 << 30, update_share=2 << 30, maintenance=maintenance)
     try:
         for gid in graphs:
             srv.add_graph(gid, graphs[gid], seed=100 + gid, samples=128)
@@ -67,15 +67,16 @@ def _serve(kc, graphs, ops, order):
         srv.close()
 
 
-def test_same_alone_and_in_the_mix(kc, gen):
+@pytest.mark.parametrize("maintenance", [0, 1], ids=["basic", "improved"])
+def test_same_alone_and_in_the_mix(kc, gen, maintenance):
     graphs = {0: gen.grid(40, 40), 1: gen.road_like(3000, seed=4), 2: gen.chung_lu(2000, 2.2, 10.0, 200.0, seed=6)}
     ops = {gid: _ops(gen, graphs[gid], 10 + gid, 4) for gid in graphs}
     # interleaved arrival across graphs (round robin), all submitted at once
     steps = max(len(v) for v in ops.values())
     mixed_order = [(gid, k) for k in range(steps) for gid in graphs if k < len(ops[gid])]
     _say("mix", len(mixed_order), "requests")
-    mixed = _serve(kc, graphs, ops, mixed_order)
+    mixed = _serve(kc, graphs, ops, mixed_order, maintenance)
     for gid in graphs:
         _say("alone", gid)
-        alone = _serve(kc, {gid: graphs[gid]}, ops, [(gid, k) for k in range(len(ops[gid]))])
+        alone = _serve(kc, {gid: graphs[gid]}, ops, [(gid, k) for k in range(len(ops[gid]))], maintenance)
         assert alone[gid] == mixed[gid]
