@@ -66,7 +66,7 @@ def cpu_baseline(g, seed: int, first: int, threads: int, per_thread: int):
 
 
 def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: float, duration: float,
-                maintenance: int = 0):
+                maintenance: int = 0, one_at_a_time: bool = False):
     """Served query and update latency on resident graphs (continuous batching,
     paper_2511_16356_amd.serve): Poisson arrivals, 80% Kemeny queries and 20%
     update batches, half deletions (sizes log-uniform in [1, 1000], batches
@@ -101,7 +101,8 @@ def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: fl
         else:
             plan.append((float(t), gid, "query", [], False))
     log("serving: %d graphs, %d requests planned (%.1f s)" % (graphs, n_req, time.perf_counter() - t_gen))
-    srv = Server(budget_bytes=32 << 30, update_share=4 << 30, maintenance=maintenance)
+    srv = Server(budget_bytes=32 << 30, update_share=4 << 30, maintenance=maintenance,
+                 one_at_a_time=one_at_a_time)
     try:
         t_init = time.perf_counter()
         for gid, g in enumerate(gs):
@@ -128,6 +129,8 @@ def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: fl
                         "insertions (1-10 edges), edges with prob. ~ d(u)d(v)"
                         % (graphs, lo, hi, samples, rate, duration),
             "maintenance": "improved (Algorithm 3)" if maintenance else "basic (Algorithm 2)",
+            "scheduling": "one request at a time (plain form)" if one_at_a_time else
+                          "per-graph workers and streams, requests on different graphs overlap",
             "requests": len(reqs), "errors": errors, "makespan_s": makespan,
             "throughput_req_per_s": len(reqs) / makespan,
             "query": latency_stats(reqs, "query"), "update": latency_stats(reqs, "update"),
@@ -135,6 +138,75 @@ def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: fl
         }
     finally:
         srv.close()
+
+
+def exact_kemeny(offsets, indices) -> float:
+    """kappa = sum over the non-unit eigenvalues of D^-1 A of 1 / (1 - lambda)
+    (Eq. 1), by a dense FP64 eigensolve of the similar matrix D^-1/2 A D^-1/2."""
+    import numpy as np
+    n = len(offsets) - 1
+    a = np.zeros((n, n))
+    src = np.repeat(np.arange(n), np.diff(offsets))
+    a[src, indices] = 1.0
+    s = 1.0 / np.sqrt(a.sum(axis=1))
+    lam = np.sort(np.linalg.eigvalsh(a * s[:, None] * s[None, :]))[:-1]
+    return float(np.sum(1.0 / (1.0 - lam)))
+
+
+def accuracy_leg(seed: int, samples: int, plain: int):
+    """K-hat against exact K on the 32x32 grid (1,024 vertices, 1,984 edges),
+    and the batched form against the plain one-sample-at-a-time GPU form
+    (one kc_estimate call per sample) on the same trees."""
+    import torch
+    import graphgen
+    import paper_2511_16356_amd as kc
+    g = graphgen.grid(32, 32)
+    k_exact = exact_kemeny(g.offsets, g.indices)
+    with kc.Graph.from_graph(g) as G:
+        G.reserve(samples)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        est = G.estimate(seed, 0, samples)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        est_b = G.estimate(seed, 0, plain)
+        torch.cuda.synchronize()
+        t_batch_plain = time.perf_counter() - t0
+        s1 = 0
+        t0 = time.perf_counter()
+        for s in range(plain):
+            s1 += G.estimate(seed, s, 1).sum_f
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+    assert s1 == est_b.sum_f  # the same trees, one at a time or batched
+    rel = est.kappa / k_exact - 1.0
+    ci = 1.959963984540054 * est.std_error / est.kappa
+    log("accuracy: K-hat %.3f exact %.3f rel %.4f ci95 %.4f; plain %.1f vs batched %.1f samples/s" %
+        (est.kappa, k_exact, rel, ci, plain / t_plain, plain / t_batch_plain))
+    return {"graph": "grid 32x32 (n=1024, m=1984), Philox seed %d" % seed, "samples": samples,
+            "kappa": est.kappa, "kappa_exact": k_exact, "rel_error": rel, "rel_ci95": ci,
+            "within_eps_0.01": bool(abs(rel) <= 0.01 and ci <= 0.01),
+            "batched_samples_per_s": samples / t_batch,
+            "plain_vs_batched": {"samples": plain, "plain_samples_per_s": plain / t_plain,
+                                 "batched_samples_per_s": plain / t_batch_plain,
+                                 "speedup": t_plain / t_batch_plain}}
+
+
+def plain_leg(G, seed: int, count: int):
+    """The plain one-sample-at-a-time GPU form on the benchmark graph: one
+    kc_estimate call per sample, for a bounded number of sample ids."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    draws = 0
+    for s in range(count):
+        draws += G.estimate(seed, s, 1).total_steps
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log("plain: %d samples one at a time in %.1f s" % (count, dt))
+    return {"samples": count, "sample_ids": "0..%d" % (count - 1), "seconds": dt, "samples_per_s": count / dt,
+            "draws_per_sample": draws / count}
 
 
 def study_graphs(points: int):
@@ -243,6 +315,9 @@ def main():
     ap.add_argument("--serve-graphs", type=int, default=8)
     ap.add_argument("--serve-rate", type=float, default=5.0, help="requests per second")
     ap.add_argument("--serve-seconds", type=float, default=12.0)
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the exact-K and plain-form legs")
+    ap.add_argument("--plain-samples", type=int, default=2,
+                    help="sample ids run one launch each on the benchmark graph (plain form)")
     ap.add_argument("--study", choices=["tau0", "root"], default=None,
                     help="instead of the benchmark, run the reference-tree (Exp-II) or root-degree "
                          "(Exp-III) study on reduced graphs and print its JSON line")
@@ -368,11 +443,18 @@ def main():
             "algorithmic_bytes_per_launch": alg / args.steps,
         },
     }
+    if not args.no_accuracy:
+        out["plain_one_at_a_time"] = plain_leg(G, args.seed, args.plain_samples)
+        out["plain_one_at_a_time"]["batched_samples_per_s"] = value
+        out["accuracy"] = accuracy_leg(args.seed, 8192, 2000)
     if not args.no_serve:
         out["served"] = serving_leg(args.seed + 7, args.serve_graphs, 10_000, 30_000, 1024,
                                     args.serve_rate, args.serve_seconds)
         out["served_improved"] = serving_leg(args.seed + 7, args.serve_graphs, 10_000, 30_000, 1024,
                                              args.serve_rate, args.serve_seconds, maintenance=1)
+        out["served_improved_one_at_a_time"] = serving_leg(args.seed + 7, args.serve_graphs, 10_000, 30_000, 1024,
+                                                           args.serve_rate, args.serve_seconds, maintenance=1,
+                                                           one_at_a_time=True)
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         try:

@@ -539,43 +539,83 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
         }
         __syncthreads();
 
-        // ---- new parks, one at a time: look for a cycle of parked chains through
-        // the new edge (a chain woken above is no longer parked)
-        uint64_t pm = pm0;
-        while (pm != 0ull) {
-            const int L = __ffsll((unsigned long long)pm) - 1;
-            pm &= pm - 1;
-            int ncyc = 0;
-            if (lane == L) {
-                const int c = chain;
-                if (sh.state[c] == CS_PARKED) {
-                    int x = sh.up[c], len = 0;
-                    while (x != c && sh.state[x] == CS_PARKED && len < CH) { x = sh.up[x]; ++len; }
-                    if (x == c) {
-                        // the chains c -> up(c) -> ... -> c form a cycle of arrows: pop all
-                        // of them; each keeps the vertex where its predecessor entered it
-                        // and leaves the waiter list of the vertex it was parked on
-                        int prev = c, m;
-                        do {
-                            m = sh.up[prev];
-                            const int wp = sh.wprev[m], wn = sh.wnext[m];
-                            if (wp >= 0) sh.wnext[wp] = (int16_t)wn;
-                            else astore(tag_high(&tagw[sh.block[m]]), (uint32_t)(wn + 1));
-                            if (wn >= 0) sh.wprev[wn] = (int16_t)wp;
-                            ws.queue[(q_tail + ncyc) & (CH - 1)] = make_int4(m, T_POP, sh.block[prev], sh.block[m]);
-                            sh.state[m] = CS_QUEUED;
-                            ++ncyc;
-                            prev = m;
-                        } while (m != c && ncyc <= CH);
+        // ---- new parks: each looks for a cycle of parked chains through its own
+        // new owner link, all lanes in lockstep (a chain woken above is no longer
+        // parked).  A walk that runs into a cycle closed by another new park
+        // stops there (Brent's cycle finding), so every walk ends within a few
+        // times the number of chains.  A cycle is found by each new park on it;
+        // its smallest chain index identifies it, and the lowest such lane pops
+        // it, one cycle at a time.  (Most rounds park nothing and skip this.)
+        if (pm0 != 0ull) {
+            const int c = chain;
+            bool walking = ((pm0 >> lane) & 1ull) != 0ull && sh.state[c] == CS_PARKED;
+            bool on_cycle = false;
+            int hare = 0, tort = 0, cmin = c, power = 1, lam = 1;
+            if (walking) {
+                const int x0 = sh.up[c];
+                if (sh.state[x0] != CS_PARKED) {
+                    walking = false;
+                } else {
+                    cmin = min(c, x0);
+                    tort = x0;
+                    hare = sh.up[x0];
+                }
+            }
+#pragma unroll 1
+            for (int step = 0; __ballot(walking) != 0ull; ++step) {
+                if (walking) {
+                    if (hare == c) {
+                        on_cycle = true;
+                        walking = false;
+                    } else if (sh.state[hare] != CS_PARKED || hare == tort) {
+                        walking = false;  // reaches a walking chain, or another new cycle
+                    } else if (step >= 4 * CH) {
+                        err = DEV_PROTOCOL;  // longer than any walk through the chain table
+                        walking = false;
+                    } else {
+                        cmin = min(cmin, hare);
+                        if (power == lam) {
+                            tort = hare;
+                            power <<= 1;
+                            lam = 0;
+                        }
+                        hare = sh.up[hare];
+                        ++lam;
                     }
                 }
+            }
+            uint64_t todo = __ballot(on_cycle);
+            while (todo != 0ull) {
+                const int L = __ffsll((unsigned long long)todo) - 1;
+                const int key = __shfl(cmin, L);
+                todo &= ~__ballot(on_cycle && cmin == key);
+                int ncyc = 0;
+                if (lane == L) {
+                    // the chains c -> up(c) -> ... -> c form a cycle of arrows: pop all
+                    // of them; each keeps the vertex where its predecessor entered it
+                    // and leaves the waiter list of the vertex it was parked on
+                    int prev = c, m;
+                    do {
+                        m = sh.up[prev];
+                        const int wp = sh.wprev[m], wn = sh.wnext[m];
+                        if (wp >= 0) sh.wnext[wp] = (int16_t)wn;
+                        else astore(tag_high(&tagw[sh.block[m]]), (uint32_t)(wn + 1));
+                        if (wn >= 0) sh.wprev[wn] = (int16_t)wp;
+                        ws.queue[(q_tail + ncyc) & (CH - 1)] = make_int4(m, T_POP, sh.block[prev], sh.block[m]);
+                        sh.state[m] = CS_QUEUED;
+                        ++ncyc;
+                        prev = m;
+                    } while (m != c && ncyc <= CH);
+                }
+                ncyc = __shfl(ncyc, L);
+                parked -= ncyc;
+                q_tail += ncyc;
+                __syncthreads();
+            }
+            if (((pm0 >> lane) & 1ull) != 0ull) {
                 mode = M_IDLE;
                 chain = -1;
             }
-            ncyc = __shfl(ncyc, L);
-            parked -= ncyc;
-            q_tail += ncyc;
-            __syncthreads();
         }
         fence_wg();
         if (__ballot(err != 0) != 0ull) break;

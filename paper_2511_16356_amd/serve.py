@@ -14,6 +14,8 @@ Admission is by HBM footprint: an update may allocate at most its share of
 the device budget (``KC_OPT_MEM_BUDGET``), and it starts only when that
 share is free; queries need no workspace.  Requests on one graph run in
 arrival order, so every graph's results are the same alone and in any mix.
+For comparison, ``one_at_a_time`` serves every request in one worker, one
+after another (the plain form).
 
 This module only orchestrates calls into the HIP library; every step of the
 estimator and of the maintenance runs in the library's kernels.
@@ -68,7 +70,11 @@ class _Budget:
 class Server:
     """Resident graphs and their request workers."""
 
-    def __init__(self, budget_bytes: int, update_share: int, maintenance: int = KC_MAINT_BASIC):
+    def __init__(self, budget_bytes: int, update_share: int, maintenance: int = KC_MAINT_BASIC,
+                 one_at_a_time: bool = False):
+        """one_at_a_time: the plain form for comparison, one worker for all
+        graphs, so requests run strictly one after another in arrival order."""
+        self.one_at_a_time = one_at_a_time
         self.budget = _Budget(budget_bytes)
         self.update_share = update_share   # device bytes one update may use
         self.maintenance = maintenance     # KC_MAINT_BASIC (Algorithm 2) or KC_MAINT_IMPROVED (Algorithm 3)
@@ -89,9 +95,12 @@ class Server:
         G.samples_init(seed, samples, stream=stream)
         self.graphs[gid] = G
         self.streams[gid] = stream
+        if self.one_at_a_time and self.threads:
+            self.queues[gid] = next(iter(self.queues.values()))
+            return
         q = queue.Queue()
         self.queues[gid] = q
-        t = threading.Thread(target=self._worker, args=(gid,), daemon=True)
+        t = threading.Thread(target=self._worker, args=(q,), daemon=True)
         self.threads[gid] = t
         t.start()
 
@@ -101,14 +110,13 @@ class Server:
         req.t_arrive = time.perf_counter()
         self.queues[req.gid].put(req)
 
-    def _worker(self, gid: int):
-        G = self.graphs[gid]
-        stream = self.streams[gid]
-        q = self.queues[gid]
+    def _worker(self, q):
         while True:
             req = q.get()
             if req is None:
                 return
+            G = self.graphs[req.gid]
+            stream = self.streams[req.gid]
             held = 0
             try:
                 if req.kind == "update":
@@ -142,7 +150,7 @@ class Server:
             return len(self.done)
 
     def close(self):
-        for q in self.queues.values():
+        for q in {id(q): q for q in self.queues.values()}.values():
             q.put(None)
         for t in self.threads.values():
             t.join()

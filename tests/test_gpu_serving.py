@@ -41,9 +41,9 @@ def _ops(gen, g, seed, rounds):
     return ops
 
 
-def _serve(kc, graphs, ops, order, maintenance=0):
+def _serve(kc, graphs, ops, order, maintenance=0, one_at_a_time=False):
     from paper_2511_16356_amd.serve import Server, Request
-    srv = Server(budget_bytes=8 << 30, update_share=2 << 30, maintenance=maintenance)
+    srv = Server(budget_bytes=8 << 30, update_share=2 << 30, maintenance=maintenance, one_at_a_time=one_at_a_time)
     try:
         for gid in graphs:
             srv.add_graph(gid, graphs[gid], seed=100 + gid, samples=128)
@@ -76,6 +76,8 @@ def test_same_alone_and_in_the_mix(kc, gen, maintenance):
     mixed_order = [(gid, k) for k in range(steps) for gid in graphs if k < len(ops[gid])]
     _say("mix", len(mixed_order), "requests")
     mixed = _serve(kc, graphs, ops, mixed_order, maintenance)
+    _say("one at a time", len(mixed_order), "requests")
+    assert _serve(kc, graphs, ops, mixed_order, maintenance, one_at_a_time=True) == mixed
     for gid in graphs:
         _say("alone", gid)
         alone = _serve(kc, {gid: graphs[gid]}, ops, [(gid, k) for k in range(len(ops[gid]))], maintenance)
