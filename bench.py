@@ -41,6 +41,12 @@ MEASURED_TRAFFIC = {
 }
 
 
+# Measured ceilings of the device (bench.py --calibrate-random 16, libkc_probe.so;
+# profiles/memory_ceilings_mi355x.md): a streaming read and independent random
+# reads of whole 64-byte lines over a 16 GiB buffer.
+MEASURED_CEILINGS = {"stream_read_GBps": 5207.0, "random_64B_read_GBps": 1262.0}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -301,6 +307,34 @@ def calibrate_copy(mib: int):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}), flush=True)
 
 
+def calibrate_random(gib: int):
+    """Measured ceilings for the roofline discussion (libkc_probe.so): a
+    streaming read of a `gib` GiB buffer, and independent random reads of whole
+    64-byte lines from it.  Prints one JSON line."""
+    import ctypes
+    import torch
+    from paper_2511_16356_amd import build_lib
+    lib = ctypes.CDLL(build_lib.PROBE_LIB)
+    lib.kc_probe_stream_read.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_double)]
+    lib.kc_probe_random_read.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_double)]
+    nbytes = gib << 30
+    buf = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    gbps, sps = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc1 = lib.kc_probe_stream_read(ctypes.c_void_p(buf.data_ptr()), nbytes, ctypes.c_void_p(sink.data_ptr()),
+                                   ctypes.byref(gbps))
+    rc2 = lib.kc_probe_random_read(ctypes.c_void_p(buf.data_ptr()), nbytes, 1 << 28, ctypes.c_void_p(sink.data_ptr()),
+                                   ctypes.byref(sps))
+    if rc1 != 0 or rc2 != 0:
+        raise RuntimeError("probe failed (%d, %d)" % (rc1, rc2))
+    print(json.dumps({"buffer_GiB": gib, "stream_read_GBps": gbps.value,
+                      "random_64B_lines_per_s": sps.value, "random_64B_read_GBps": sps.value * 64 / 1e9}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -323,9 +357,14 @@ def main():
                          "(Exp-III) study on reduced graphs and print its JSON line")
     ap.add_argument("--study-points", type=int, default=100_000)
     ap.add_argument("--study-samples", type=int, default=512)
+    ap.add_argument("--calibrate-random", type=int, default=0, metavar="GIB",
+                    help="only measure streaming and random 64-byte reads over a GIB GiB buffer and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
+    if args.calibrate_random:
+        calibrate_random(args.calibrate_random)
+        return
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
         return
@@ -441,6 +480,8 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "algorithmic_bytes_per_launch": alg / args.steps,
+            "measured_ceilings": dict(MEASURED_CEILINGS),
+            "frac_of_random_64B_ceiling": achieved / MEASURED_CEILINGS["random_64B_read_GBps"],
         },
     }
     if not args.no_accuracy:

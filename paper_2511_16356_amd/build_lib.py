@@ -10,6 +10,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkc_mi355x.so")
 SOURCES = ["kc_device.hip", "kc_host.cpp"]
+# memory-ceiling probes used by the benchmark's roofline calibration
+PROBE_LIB = os.path.join(HERE, "libkc_probe.so")
+PROBE_SOURCES = ["kc_probe.hip"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are disabled on purpose
@@ -26,9 +29,14 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every HIP/C++ source of the library (always recompiles)."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp%d" % os.getpid()
+    """Compile every HIP/C++ source of both libraries (always recompiles)."""
+    _build_one(PROBE_LIB, PROBE_SOURCES, verbose)
+    return _build_one(LIB, SOURCES, verbose)
+
+
+def _build_one(lib: str, sources, verbose: bool) -> str:
+    srcs = [os.path.join(CSRC, s) for s in sources]
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(HERE, "..", "include"), "-o", tmp] + srcs
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -39,8 +47,8 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed:\n" + "\n".join(noise))
     if noise and verbose:
         print("\n".join(noise), file=sys.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -77,3 +77,17 @@ def test_binding_fails_loudly_without_library(kc, monkeypatch, tmp_path):
     monkeypatch.setattr(kc, "_lib", None)
     with pytest.raises(kc.KcError):
         kc.library()
+
+
+def test_probe_library_exports_its_header():
+    """libkc_probe.so (measured memory ceilings) exports what include/kc_probe.h declares."""
+    from paper_2511_16356_amd import build_lib
+    if not os.path.exists(build_lib.PROBE_LIB):
+        build_lib.build()
+    text = open(os.path.join(ROOT, "include", "kc_probe.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    decl = set(re.findall(r"\b(kc_[a-z0-9_]+)\s*\(", text))
+    assert decl == {"kc_probe_stream_read", "kc_probe_random_read"}
+    lib = ctypes.CDLL(build_lib.PROBE_LIB)
+    for name in decl:
+        assert hasattr(lib, name), name
