@@ -316,7 +316,10 @@ kc_status kc_samples_get(const kc_graph *g, int32_t *parents_out, int64_t *f_out
  * run, an insertion of an existing edge, a bad vertex), KC_ERR_DISCONNECTED
  * (a deletion run would disconnect the graph), KC_ERR_OVERFLOW (2m would
  * reach 2^31), and those of kc_sample_trees.  Updates before the failing one
- * stay applied; the failing one changes nothing.
+ * stay applied; the failing one changes nothing, also when it fails on the
+ * device after the graph was switched (the previous graph and trees are put
+ * back).  A run of deletions counts as one update under KC_MAINT_BASIC and
+ * as one update per edge under KC_MAINT_IMPROVED.
  */
 kc_status kc_apply_updates(kc_graph *g, const int32_t *u, const int32_t *v, const uint8_t *is_insert,
                            int32_t count, int32_t *resampled, void *hip_stream);

@@ -49,6 +49,18 @@ hipError_t dev_alloc(T **p, size_t count) {
     return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
 }
 
+// A temporary device buffer freed when it goes out of scope (also on the
+// early returns of HIP_TRY).
+template <typename T>
+struct DevTmp {
+    T *p = nullptr;
+    DevTmp() = default;
+    DevTmp(const DevTmp &) = delete;
+    DevTmp &operator=(const DevTmp &) = delete;
+    ~DevTmp() { dev_free(p); }
+    hipError_t alloc(size_t count) { return dev_alloc(&p, count); }
+};
+
 }  // namespace
 
 struct PreparedGraph {
@@ -951,6 +963,86 @@ kc_status kc_samples_get(const kc_graph *g, int32_t *parents_out, int64_t *f_out
 
 static kc_status ism_deletion(kc_graph *g, int32_t a, int32_t b, int32_t *changed, hipStream_t stream, bool last);
 
+// Moves g to a new CSR and keeps the old one; undo() puts back the old CSR
+// and tau0 rule and rebuilds every per-graph array, so that an update that
+// fails after the switch leaves the graph as it was.  It returns the status
+// of the failure and keeps its message.
+struct GraphSwitch {
+    kc_graph *g;
+    std::vector<int64_t> old_off;
+    std::vector<int32_t> old_adj;
+    int32_t old_kind;
+    std::vector<int32_t> old_tau0;
+    GraphSwitch(kc_graph *g_, std::vector<int64_t> &&noff, std::vector<int32_t> &&nadj)
+        : g(g_), old_kind(g_->tau0_kind), old_tau0(g_->h_tau0) {
+        old_off.swap(g->h_off);
+        old_adj.swap(g->h_adj);
+        g->h_off = std::move(noff);
+        g->h_adj = std::move(nadj);
+    }
+    kc_status undo(kc_status st, hipStream_t stream) {
+        const std::string err = g_last_error;
+        g->h_off.swap(old_off);
+        g->h_adj.swap(old_adj);
+        g->tau0_kind = old_kind;
+        g->h_tau0 = old_tau0;
+        if (rebuild_graph(g, g->root, stream) != KC_OK) {
+            g_last_error = err + "; restoring the previous graph failed too: " + g_last_error;
+            return st;
+        }
+        g_last_error = err;
+        return st;
+    }
+};
+
+// flags[t] = 1 for the resident trees that contain one of the edges {eu[k], ev[k]}.
+static std::vector<uint8_t> trees_with_edges(kc_graph *g, const std::vector<int32_t> &eu,
+                                             const std::vector<int32_t> &ev, hipStream_t stream, kc_status *st) {
+    std::vector<uint8_t> flags((size_t)g->res_count, 0);
+    *st = KC_OK;
+    DevTmp<int32_t> d_eu, d_ev;
+    DevTmp<uint8_t> d_flags;
+    hipError_t e = d_eu.alloc(eu.size());
+    if (e == hipSuccess) e = d_ev.alloc(ev.size());
+    if (e == hipSuccess) e = d_flags.alloc((size_t)g->res_count);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_eu.p, eu.data(), eu.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_ev.p, ev.data(), ev.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d_flags.p, 0, (size_t)g->res_count, stream);
+    if (e == hipSuccess)
+        e = kc::launch_flag_trees(g->d_res_par, g->res_count, g->n, d_eu.p, d_ev.p, (int32_t)eu.size(), d_flags.p,
+                                  stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(flags.data(), d_flags.p, flags.size(), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess)
+        *st = fail(e == hipErrorOutOfMemory ? KC_ERR_NOMEM : KC_ERR_DEVICE, "flagging trees failed: %s",
+                   hipGetErrorString(e));
+    return flags;
+}
+
+// A device copy of resident rows, to put them back if an update fails after
+// changing them in place.
+struct RowBackup {
+    DevTmp<int32_t> buf;
+    std::vector<int32_t> rows;
+    kc_status save(kc_graph *g, const std::vector<int32_t> &r, hipStream_t stream) {
+        rows = r;
+        if (rows.empty()) return KC_OK;
+        HIP_TRY(buf.alloc(rows.size() * (size_t)g->n));
+        for (size_t i = 0; i < rows.size(); ++i)
+            HIP_TRY(hipMemcpyAsync(buf.p + i * (size_t)g->n, g->d_res_par + (size_t)rows[i] * (size_t)g->n,
+                                   (size_t)g->n * sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
+        return KC_OK;
+    }
+    void restore(kc_graph *g, hipStream_t stream) {
+        for (size_t i = 0; i < rows.size(); ++i)
+            (void)hipMemcpyAsync(g->d_res_par + (size_t)rows[i] * (size_t)g->n, buf.p + i * (size_t)g->n,
+                                 (size_t)g->n * sizeof(int32_t), hipMemcpyDeviceToDevice, stream);
+        (void)hipStreamSynchronize(stream);
+    }
+};
+
 // A run of deletions, applied at once (Algorithm 2, deletion case).
 static kc_status apply_deletions(kc_graph *g, const int32_t *u, const int32_t *v, int32_t count,
                                  int32_t *resampled, hipStream_t stream) {
@@ -1005,51 +1097,39 @@ static kc_status apply_deletions(kc_graph *g, const int32_t *u, const int32_t *v
     // resident trees that use a deleted edge (Algorithm 2, deletion: they are
     // replaced; the others are uniform spanning trees of G' already, Theorem 4.2)
     std::vector<int32_t> redo;
+    kc_status st0 = KC_OK;
     if (g->res_count > 0) {
         std::vector<int32_t> eu(del.size()), ev(del.size());
         for (size_t k = 0; k < del.size(); ++k) { eu[k] = del[k].first; ev[k] = del[k].second; }
-        int32_t *d_eu = nullptr, *d_ev = nullptr;
-        uint8_t *d_flags = nullptr;
-        HIP_TRY(dev_alloc(&d_eu, del.size()));
-        HIP_TRY(dev_alloc(&d_ev, del.size()));
-        HIP_TRY(dev_alloc(&d_flags, (size_t)g->res_count));
-        HIP_TRY(hipMemcpyAsync(d_eu, eu.data(), eu.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipMemcpyAsync(d_ev, ev.data(), ev.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipMemsetAsync(d_flags, 0, (size_t)g->res_count, stream));
-        HIP_TRY(kc::launch_flag_trees(g->d_res_par, g->res_count, n, d_eu, d_ev, (int32_t)del.size(), d_flags, stream));
-        std::vector<uint8_t> flags((size_t)g->res_count);
-        HIP_TRY(hipMemcpyAsync(flags.data(), d_flags, flags.size(), hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipStreamSynchronize(stream));
-        dev_free(d_eu);
-        dev_free(d_ev);
-        dev_free(d_flags);
+        const std::vector<uint8_t> flags = trees_with_edges(g, eu, ev, stream, &st0);
+        if (st0 != KC_OK) return st0;
         for (int32_t t = 0; t < g->res_count; ++t)
             if (flags[(size_t)t]) redo.push_back(t);
     }
     // switch to G'
-    g->h_off.swap(noff);
-    g->h_adj.swap(nadj);
+    GraphSwitch sw(g, std::move(noff), std::move(nadj));
     if (kind != g->tau0_kind) {
         g->tau0_kind = kind;
         g->h_tau0.clear();
     }
     kc_status st = rebuild_graph(g, g->root, stream);
-    if (st != KC_OK) return st;
+    if (st != KC_OK) return sw.undo(st, stream);
     if (g->res_count > 0) {
         // fresh trees of G' for the replaced ones: the next unused sample indices, in slot order
         const int32_t k = (int32_t)redo.size();
         if (k > 0) {
-            int32_t *d_tmp = nullptr;
-            HIP_TRY(dev_alloc(&d_tmp, (size_t)k * (size_t)n));
-            st = kc_sample_trees(g, g->res_seed, g->res_next, k, d_tmp, nullptr, nullptr, (void *)stream);
-            if (st != KC_OK) { dev_free(d_tmp); return st; }
+            DevTmp<int32_t> tmp;
+            hipError_t e = tmp.alloc((size_t)k * (size_t)n);
+            if (e != hipSuccess) return sw.undo(fail(KC_ERR_NOMEM, "allocation failed: %s", hipGetErrorString(e)), stream);
+            st = kc_sample_trees(g, g->res_seed, g->res_next, k, tmp.p, nullptr, nullptr, (void *)stream);
+            if (st != KC_OK) return sw.undo(st, stream);
+            // from here on nothing can fail before the set is consistent with G'
             for (int32_t i = 0; i < k; ++i) {
-                HIP_TRY(hipMemcpyAsync(g->d_res_par + (size_t)redo[(size_t)i] * (size_t)n, d_tmp + (size_t)i * (size_t)n,
+                HIP_TRY(hipMemcpyAsync(g->d_res_par + (size_t)redo[(size_t)i] * (size_t)n, tmp.p + (size_t)i * (size_t)n,
                                        (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
                 g->res_ids[(size_t)redo[(size_t)i]] = g->res_next + i;
             }
             HIP_TRY(hipStreamSynchronize(stream));
-            dev_free(d_tmp);
             g->res_next += k;
         }
         // every tree's f on G' (degrees, 2m and tau0 changed), at the end of the call
@@ -1101,26 +1181,24 @@ static void csr_without_edge(const std::vector<int64_t> &off, const std::vector<
 static kc_status path_currents(kc_graph *g, int32_t a, int32_t b, std::vector<int64_t> *c, hipStream_t stream) {
     const std::vector<int32_t> path = reference_path(g->h_off, g->h_adj, a, b);
     if (path.size() < 2) return fail(KC_ERR_DEVICE, "no path between %d and %d", a, b);
-    int32_t *d_path = nullptr;
-    int64_t *d_c = nullptr;
-    HIP_TRY(dev_alloc(&d_path, path.size()));
-    HIP_TRY(dev_alloc(&d_c, (size_t)g->res_count));
-    HIP_TRY(hipMemcpyAsync(d_path, path.data(), path.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    DevTmp<int32_t> d_path;
+    DevTmp<int64_t> d_c;
+    HIP_TRY(d_path.alloc(path.size()));
+    HIP_TRY(d_c.alloc((size_t)g->res_count));
+    HIP_TRY(hipMemcpyAsync(d_path.p, path.data(), path.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
     kc::RunParams rp{};
     rp.count = g->res_count;
     rp.mode = kc::RUN_CURRENT;
     rp.parents_in = g->d_res_par;
-    rp.f_out = d_c;
-    rp.path = d_path;
+    rp.f_out = d_c.p;
+    rp.path = d_path.p;
     rp.path_len = (int32_t)path.size();
     kc_status st = run_persistent(g, rp, stream);
     c->assign((size_t)g->res_count, 0);
     if (st == KC_OK) {
-        const hipError_t e = hipMemcpy(c->data(), d_c, c->size() * sizeof(int64_t), hipMemcpyDeviceToHost);
+        const hipError_t e = hipMemcpy(c->data(), d_c.p, c->size() * sizeof(int64_t), hipMemcpyDeviceToHost);
         if (e != hipSuccess) st = fail(KC_ERR_DEVICE, "copy failed: %s", hipGetErrorString(e));
     }
-    dev_free(d_path);
-    dev_free(d_c);
     return st;
 }
 
@@ -1152,37 +1230,36 @@ static kc_status apply_insertion(kc_graph *g, int32_t a, int32_t b, int32_t *res
         for (int32_t t = 0; t < g->res_count; ++t)
             if (update_uniform(g->res_seed, (uint32_t)t, (uint32_t)g->res_serial) < p) redo.push_back(t);
     }
-    g->h_off.swap(noff);
-    g->h_adj.swap(nadj);
+    GraphSwitch sw(g, std::move(noff), std::move(nadj));
     kc_status st = rebuild_graph(g, g->root, stream);
-    if (st != KC_OK) return st;
+    if (st != KC_OK) return sw.undo(st, stream);
     if (g->res_count > 0) {
         const int32_t k = (int32_t)redo.size();
         if (k > 0) {
             // uniform spanning trees of G' through (a, b): a and b start in the tree
-            int32_t *d_tmp = nullptr;
-            HIP_TRY(dev_alloc(&d_tmp, (size_t)k * (size_t)n));
+            DevTmp<int32_t> tmp;
+            hipError_t e = tmp.alloc((size_t)k * (size_t)n);
+            if (e != hipSuccess) return sw.undo(fail(KC_ERR_NOMEM, "allocation failed: %s", hipGetErrorString(e)), stream);
             kc::RunParams rp{};
             rp.seed = g->res_seed;
             rp.first = g->res_next;
             rp.count = k;
             rp.mode = kc::RUN_SAMPLE;
-            rp.parents_out = d_tmp;
+            rp.parents_out = tmp.p;
             rp.root_u = a;
             rp.root_v = b;
             st = run_persistent(g, rp, stream);
             if (st == KC_OK) {
-                const hipError_t e = kc::launch_reroot(d_tmp, k, n, a, b, g->root, stream);
+                e = kc::launch_reroot(tmp.p, k, n, a, b, g->root, stream);
                 if (e != hipSuccess) st = fail(KC_ERR_DEVICE, "reroot failed: %s", hipGetErrorString(e));
             }
-            if (st != KC_OK) { dev_free(d_tmp); return st; }
+            if (st != KC_OK) return sw.undo(st, stream);
             for (int32_t i = 0; i < k; ++i) {
-                HIP_TRY(hipMemcpyAsync(g->d_res_par + (size_t)redo[(size_t)i] * (size_t)n, d_tmp + (size_t)i * (size_t)n,
+                HIP_TRY(hipMemcpyAsync(g->d_res_par + (size_t)redo[(size_t)i] * (size_t)n, tmp.p + (size_t)i * (size_t)n,
                                        (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
                 g->res_ids[(size_t)redo[(size_t)i]] = g->res_next + i;
             }
             HIP_TRY(hipStreamSynchronize(stream));
-            dev_free(d_tmp);
             g->res_next += k;
         }
         g->res_f_stale = true;
@@ -1199,20 +1276,18 @@ static kc_status ism_link_cut(kc_graph *g, const std::vector<int32_t> &rows, int
     const int32_t k = (int32_t)rows.size();
     d->assign((size_t)k, 0);
     if (k == 0) return KC_OK;
-    int32_t *d_rows = nullptr;
-    int64_t *d_d = nullptr;
-    HIP_TRY(dev_alloc(&d_rows, (size_t)k));
-    HIP_TRY(dev_alloc(&d_d, (size_t)k));
-    HIP_TRY(hipMemcpyAsync(d_rows, rows.data(), (size_t)k * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    DevTmp<int32_t> d_rows;
+    DevTmp<int64_t> d_d;
+    HIP_TRY(d_rows.alloc((size_t)k));
+    HIP_TRY(d_d.alloc((size_t)k));
+    HIP_TRY(hipMemcpyAsync(d_rows.p, rows.data(), (size_t)k * sizeof(int32_t), hipMemcpyHostToDevice, stream));
     HIP_TRY(kc::launch_reset_ctl(g->d_ctl, stream));
-    HIP_TRY(kc::launch_link_cut(g->d_res_par, d_rows, k, g->n, a, b, g->res_seed, (uint32_t)g->res_serial, relink,
-                                d_d, g->d_ctl, stream));
+    HIP_TRY(kc::launch_link_cut(g->d_res_par, d_rows.p, k, g->n, a, b, g->res_seed, (uint32_t)g->res_serial, relink,
+                                d_d.p, g->d_ctl, stream));
     int32_t ctl[4] = {0, 0, 0, 0};
     HIP_TRY(hipMemcpyAsync(ctl, g->d_ctl, sizeof(ctl), hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipMemcpyAsync(d->data(), d_d, (size_t)k * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(d->data(), d_d.p, (size_t)k * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    dev_free(d_rows);
-    dev_free(d_d);
     if (ctl[1] != 0) return fail(KC_ERR_INVALID, "resident tree %d is not a tree rooted at %d", rows[(size_t)ctl[2]], g->root);
     return KC_OK;
 }
@@ -1222,30 +1297,28 @@ static kc_status ism_cross(kc_graph *g, const std::vector<int32_t> &rows, int32_
     const int32_t k = (int32_t)rows.size();
     d->assign((size_t)k, 0);
     if (k == 0) return KC_OK;
-    int32_t *d_rows = nullptr;
-    int64_t *d_d = nullptr;
-    HIP_TRY(dev_alloc(&d_rows, (size_t)k));
-    HIP_TRY(dev_alloc(&d_d, (size_t)k));
-    HIP_TRY(hipMemcpyAsync(d_rows, rows.data(), (size_t)k * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    DevTmp<int32_t> d_rows;
+    DevTmp<int64_t> d_d;
+    HIP_TRY(d_rows.alloc((size_t)k));
+    HIP_TRY(d_d.alloc((size_t)k));
+    HIP_TRY(hipMemcpyAsync(d_rows.p, rows.data(), (size_t)k * sizeof(int32_t), hipMemcpyHostToDevice, stream));
     kc::RunParams rp{};
     rp.count = k;
     rp.mode = kc::RUN_CROSS;
     rp.seed = g->res_seed;
     rp.parents_in = g->d_res_par;
     rp.parents_mut = g->d_res_par;
-    rp.rows = d_rows;
-    rp.f_out = d_d;
+    rp.rows = d_rows.p;
+    rp.f_out = d_d.p;
     rp.cut_u = a;
     rp.cut_v = b;
     rp.relink = relink;
     rp.serial = (uint32_t)g->res_serial;
     kc_status st = run_persistent(g, rp, stream);
     if (st == KC_OK) {
-        const hipError_t e = hipMemcpy(d->data(), d_d, (size_t)k * sizeof(int64_t), hipMemcpyDeviceToHost);
+        const hipError_t e = hipMemcpy(d->data(), d_d.p, (size_t)k * sizeof(int64_t), hipMemcpyDeviceToHost);
         if (e != hipSuccess) st = fail(KC_ERR_DEVICE, "copy failed: %s", hipGetErrorString(e));
     }
-    dev_free(d_rows);
-    dev_free(d_d);
     return st;
 }
 
@@ -1288,17 +1361,25 @@ static kc_status ism_insertion(kc_graph *g, int32_t a, int32_t b, int32_t *chang
     for (int32_t i = 0; i < count; ++i) (i < k ? chosen : rest).push_back(key[(size_t)i].second);
     std::sort(chosen.begin(), chosen.end());
     std::sort(rest.begin(), rest.end());
-    // link-cut in place (graph-independent); d(tau) = tree path length between a and b
+    // link-cut in place (graph-independent); d(tau) = tree path length between a and b.
+    // The chosen rows are saved first, so that a failure changes nothing.
+    RowBackup saved;
+    st = saved.save(g, chosen, stream);
+    if (st != KC_OK) return st;
     std::vector<int64_t> d_old, d_new;
     st = ism_link_cut(g, chosen, a, b, 1, &d_old, stream);
-    if (st != KC_OK) return st;
-    g->h_off.swap(noff);
-    g->h_adj.swap(nadj);
+    if (st != KC_OK) {
+        saved.restore(g, stream);
+        return st;
+    }
+    GraphSwitch sw(g, std::move(noff), std::move(nadj));
     st = rebuild_graph(g, g->root, stream);
-    if (st != KC_OK) return st;
     // d(tau_e): edges of G that join the two parts of tau_e - e (those of G' minus e itself)
-    st = ism_cross(g, chosen, a, b, 0, &d_new, stream);
-    if (st != KC_OK) return st;
+    if (st == KC_OK) st = ism_cross(g, chosen, a, b, 0, &d_new, stream);
+    if (st != KC_OK) {
+        saved.restore(g, stream);
+        return sw.undo(st, stream);
+    }
     for (size_t i = 0; i < chosen.size(); ++i)
         g->res_w[(size_t)chosen[i]] *= (double)d_old[i] / (double)(d_new[i] - 1);
     if (!chosen.empty() && !rest.empty()) {
@@ -1332,48 +1413,39 @@ static kc_status upload_csr_only(kc_graph *g, hipStream_t stream) {
 // run's last edge rebuilds tau0 and the other per-graph arrays.
 static kc_status ism_deletion(kc_graph *g, int32_t a, int32_t b, int32_t *changed, hipStream_t stream, bool last) {
     const int32_t count = g->res_count;
-    const int64_t n = g->n;
     std::vector<int32_t> hit;
     {
-        int32_t eu = a, ev = b;
-        int32_t *d_eu = nullptr, *d_ev = nullptr;
-        uint8_t *d_flags = nullptr;
-        HIP_TRY(dev_alloc(&d_eu, 1));
-        HIP_TRY(dev_alloc(&d_ev, 1));
-        HIP_TRY(dev_alloc(&d_flags, (size_t)count));
-        HIP_TRY(hipMemcpyAsync(d_eu, &eu, sizeof(int32_t), hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipMemcpyAsync(d_ev, &ev, sizeof(int32_t), hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipMemsetAsync(d_flags, 0, (size_t)count, stream));
-        HIP_TRY(kc::launch_flag_trees(g->d_res_par, count, n, d_eu, d_ev, 1, d_flags, stream));
-        std::vector<uint8_t> flags((size_t)count);
-        HIP_TRY(hipMemcpyAsync(flags.data(), d_flags, flags.size(), hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipStreamSynchronize(stream));
-        dev_free(d_eu);
-        dev_free(d_ev);
-        dev_free(d_flags);
+        kc_status st0 = KC_OK;
+        const std::vector<uint8_t> flags = trees_with_edges(g, {a}, {b}, stream, &st0);
+        if (st0 != KC_OK) return st0;
         for (int32_t t = 0; t < count; ++t)
             if (flags[(size_t)t]) hit.push_back(t);
+    }
+    RowBackup saved;  // cut-link rewrites these rows in place; a failure puts them back
+    {
+        const kc_status st0 = saved.save(g, hit, stream);
+        if (st0 != KC_OK) return st0;
     }
     double w_org = 0.0;
     for (int32_t t : hit) w_org += g->res_w[(size_t)t];
     std::vector<int64_t> noff;
     std::vector<int32_t> nadj;
     csr_without_edge(g->h_off, g->h_adj, a, b, &noff, &nadj);
+    GraphSwitch sw(g, std::move(noff), std::move(nadj));
     if (g->tau0_kind == KC_TAU0_GIVEN && (g->h_tau0[(size_t)a] == b || g->h_tau0[(size_t)b] == a)) {
         g->tau0_kind = KC_TAU0_BFS;
         g->h_tau0.clear();
     }
-    g->h_off.swap(noff);
-    g->h_adj.swap(nadj);
     kc_status st = last ? rebuild_graph(g, g->root, stream) : upload_csr_only(g, stream);
-    if (st != KC_OK) return st;
     // cut-link in place; d(tau) = edges of G' that join the two parts of tau - e
     std::vector<int64_t> d_old, d_new;
-    st = ism_cross(g, hit, a, b, 1, &d_old, stream);
-    if (st != KC_OK) return st;
+    if (st == KC_OK) st = ism_cross(g, hit, a, b, 1, &d_old, stream);
     // d(tau') = tree path length between a and b in the new tree
-    st = ism_link_cut(g, hit, a, b, 0, &d_new, stream);
-    if (st != KC_OK) return st;
+    if (st == KC_OK) st = ism_link_cut(g, hit, a, b, 0, &d_new, stream);
+    if (st != KC_OK) {
+        saved.restore(g, stream);
+        return sw.undo(st, stream);
+    }
     for (size_t i = 0; i < hit.size(); ++i) g->res_w[(size_t)hit[i]] *= (double)d_old[i] / (double)d_new[i];
     if (!hit.empty()) normalise(g->res_w, hit, w_org);
     g->res_f_stale = true;

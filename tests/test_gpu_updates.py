@@ -105,6 +105,41 @@ def test_rejected_updates_change_nothing(kc, gen):
         assert np.array_equal(ids0, ids1) and G.two_m == g.two_m
 
 
+def test_update_failing_after_the_switch_changes_nothing(kc, oracle_lib, gen):
+    """A deletion whose replacement trees hit the step limit (forced from the
+    host: a limit of 50 sampler rounds) fails after the graph was switched;
+    the graph, the trees and their f are then as before, and the same update
+    succeeds once the limit is lifted.  Earlier updates of the same call stay
+    applied."""
+    from test_gpu_parity import small_graphs
+    g = small_graphs(gen)["road3k"]
+    count = 32
+    S = oracle_lib.samples_init(g.offsets, g.indices, seed=4, count=count)
+    b1, b2 = deletion_batches(gen, g, [3, 40], seed=12)
+    with kc.Graph.from_graph(g) as G:
+        G.samples_init(4, count)
+        G.set_option(kc.KC_OPT_STEP_LIMIT, 50)
+        with pytest.raises(kc.KcError) as ei:
+            G.apply_updates([a for a, _ in b1], [b for _, b in b1])
+        assert ei.value.status == 6
+        _compare(G, S, g.two_m)
+        # lifted: the same run applies; then a failing run after a good one
+        G.set_option(kc.KC_OPT_STEP_LIMIT, 0)
+        G.apply_updates([a for a, _ in b1], [b for _, b in b1])
+        g = gen.remove_edges(g, b1)
+        S, _ = oracle_lib.bsm_delete(S, g.offsets, g.indices, b1)
+        _compare(G, S, g.two_m)
+        G.set_option(kc.KC_OPT_STEP_LIMIT, 50)
+        with pytest.raises(kc.KcError) as ei:
+            G.apply_updates([a for a, _ in b2], [b for _, b in b2])
+        assert ei.value.status == 6
+        _compare(G, S, g.two_m)
+        est = G.samples_query()
+        K, se, s1, s2 = oracle_lib.reduce_estimate(S.f, g.two_m)
+        assert est.sum_f == s1 and est.kappa == K
+        G.set_option(kc.KC_OPT_STEP_LIMIT, 0)
+
+
 def _mixed_plan(gen, g, seed, steps):
     """A seeded list of updates: runs of deletions (that keep the graph connected)
     and single insertions of new edges."""
