@@ -369,8 +369,8 @@ def main():
         calibrate_copy(args.calibrate_copy)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(samples shard trivially by index; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (samples would "
+              "shard by index range, with one 32-byte all-reduce of the sums at the end)", file=sys.stderr)
         sys.exit(2)
     if args.study:
         import torch

@@ -15,7 +15,7 @@ PROBE_LIB = os.path.join(HERE, "libkc_probe.so")
 PROBE_SOURCES = ["kc_probe.hip"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # packed FP32 instructions are disabled on purpose
+    # no packed FP32 instructions (v_pk_add/mul/fma_f32): the library is built without them
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
