@@ -1,0 +1,179 @@
+"""Host logic of the serving loop (paper_2511_16356_amd.serve), on the CPU:
+the graphs and streams are replaced by stand-ins that record what runs when,
+so the scheduling rules can be checked without a device.  Also the
+benchmark's exact-kappa helper against closed forms."""
+import threading
+import time
+
+import pytest
+
+
+class _FakeStream:
+    cuda_stream = 0
+
+
+class _FakeGraph:
+    """Records (gid, kind, start, end) of every call; updates take longer."""
+    log = []
+    lock = threading.Lock()
+    running = 0
+    max_running = 0
+
+    def __init__(self, gid):
+        self.gid = gid
+        self.options = {}
+        self.inits = 0
+
+    @classmethod
+    def from_graph(cls, g, stream=None):
+        return cls(g)
+
+    def set_option(self, opt, value):
+        self.options[opt] = value
+
+    def samples_init(self, seed, count, stream=None):
+        self.inits += 1
+
+    def _run(self, kind, seconds):
+        with _FakeGraph.lock:
+            _FakeGraph.running += 1
+            _FakeGraph.max_running = max(_FakeGraph.max_running, _FakeGraph.running)
+            t0 = time.perf_counter()
+        time.sleep(seconds)
+        with _FakeGraph.lock:
+            _FakeGraph.running -= 1
+            _FakeGraph.log.append((self.gid, kind, t0, time.perf_counter()))
+
+    def samples_query(self, stream=None):
+        self._run("query", 0.01)
+        return "estimate"
+
+    def apply_updates(self, u, v, is_insert, stream=None):
+        if u and u[0] < 0:
+            from paper_2511_16356_amd import KcError
+            raise KcError(1, "bad edge")
+        self._run("update", 0.05)
+        return len(u)
+
+    def close(self):
+        pass
+
+
+@pytest.fixture
+def serve(monkeypatch):
+    import torch
+    import paper_2511_16356_amd.serve as serve
+    monkeypatch.setattr(serve, "Graph", _FakeGraph)
+    monkeypatch.setattr(torch.cuda, "Stream", lambda *a, **k: _FakeStream())
+    _FakeGraph.log = []
+    _FakeGraph.running = 0
+    _FakeGraph.max_running = 0
+    return serve
+
+
+def _submit_all(srv, serve, plan):
+    reqs = []
+    for gid, kind in plan:
+        r = serve.Request(gid, kind, [(1, 2)] if kind == "update" else [])
+        reqs.append(r)
+        srv.submit(r)
+    assert srv.drain(timeout=30.0) == len(reqs)
+    return reqs
+
+
+def test_requests_on_one_graph_keep_their_order(serve):
+    srv = serve.Server(budget_bytes=1 << 30, update_share=1 << 20)
+    try:
+        for gid in range(3):
+            srv.add_graph(gid, gid, seed=gid, samples=8)
+        plan = [(k % 3, "update" if k % 4 == 1 else "query") for k in range(24)]
+        reqs = _submit_all(srv, serve, plan)
+        assert all(not r.error for r in reqs)
+        for gid in range(3):
+            mine = [r for r in reqs if r.gid == gid]
+            starts = [r.t_start for r in mine]
+            assert starts == sorted(starts)
+            for a, b in zip(mine, mine[1:]):
+                assert a.t_done <= b.t_start + 1e-6  # one after another on a graph
+        # different graphs overlap
+        assert _FakeGraph.max_running > 1
+    finally:
+        srv.close()
+
+
+def test_update_budget_admits_one_update_at_a_time(serve):
+    # a budget that holds exactly one update share: updates never overlap
+    srv = serve.Server(budget_bytes=1 << 20, update_share=1 << 20)
+    try:
+        for gid in range(4):
+            srv.add_graph(gid, gid, seed=gid, samples=8)
+        reqs = _submit_all(srv, serve, [(gid, "update") for gid in range(4)] * 2)
+        ups = sorted((s, e) for g, k, s, e in _FakeGraph.log if k == "update")
+        assert len(ups) == 8
+        for (s0, e0), (s1, e1) in zip(ups, ups[1:]):
+            assert e0 <= s1 + 1e-6
+        assert srv.budget.free == srv.budget.total
+        assert all(r.result == 1 for r in reqs)
+    finally:
+        srv.close()
+
+
+def test_one_at_a_time_runs_in_arrival_order(serve):
+    srv = serve.Server(budget_bytes=1 << 30, update_share=1 << 20, one_at_a_time=True)
+    try:
+        for gid in range(3):
+            srv.add_graph(gid, gid, seed=gid, samples=8)
+        assert len(srv.threads) == 1
+        plan = [(k % 3, "update" if k % 3 == 0 else "query") for k in range(12)]
+        reqs = _submit_all(srv, serve, plan)
+        assert _FakeGraph.max_running == 1
+        for a, b in zip(reqs, reqs[1:]):
+            assert a.t_done <= b.t_start + 1e-6
+    finally:
+        srv.close()
+
+
+def test_errors_are_reported_and_release_the_budget(serve):
+    srv = serve.Server(budget_bytes=1 << 20, update_share=1 << 20)
+    try:
+        srv.add_graph(0, 0, seed=0, samples=8)
+        bad = serve.Request(0, "update", [(-1, 2)])
+        good = serve.Request(0, "update", [(1, 2)])
+        srv.submit(bad)
+        srv.submit(good)
+        assert srv.drain(timeout=30.0) == 2
+        assert "KC_ERR_INVALID" in bad.error and good.error == "" and good.result == 1
+        assert srv.budget.free == srv.budget.total
+    finally:
+        srv.close()
+
+
+def test_maintenance_option_reaches_every_graph(serve):
+    from paper_2511_16356_amd import KC_OPT_MAINTENANCE, KC_MAINT_IMPROVED
+    srv = serve.Server(budget_bytes=1 << 30, update_share=1 << 20, maintenance=KC_MAINT_IMPROVED)
+    try:
+        for gid in range(2):
+            srv.add_graph(gid, gid, seed=gid, samples=8)
+        for G in srv.graphs.values():
+            assert G.options[KC_OPT_MAINTENANCE] == KC_MAINT_IMPROVED and G.inits == 1
+    finally:
+        srv.close()
+
+
+def test_bench_exact_kemeny_closed_forms(gen):
+    import bench
+    for n in (3, 5, 9):
+        g = gen.complete(n)
+        assert bench.exact_kemeny(g.offsets, g.indices) == pytest.approx((n - 1) ** 2 / n, rel=1e-12)
+    for n in (5, 8, 13):
+        g = gen.cycle(n)
+        assert bench.exact_kemeny(g.offsets, g.indices) == pytest.approx((n * n - 1) / 6, rel=1e-12)
+    g = gen.grid(32, 32)
+    assert bench.exact_kemeny(g.offsets, g.indices) == pytest.approx(3400.358743308690, rel=1e-12)
+
+
+def test_bench_algorithmic_bytes():
+    import bench
+    # one sector per draw, per vertex (retrace), and per path-mapping term
+    assert bench.algorithmic_bytes(draws=100, n=8, depth0=2, samples=3) == 64 * (100 + 3 * (8 + 8 * 2))
+    assert bench.algorithmic_bytes(draws=0, n=1024, depth0=60, samples=1) == 64 * (1024 + 1024 * 10)
