@@ -72,7 +72,7 @@ def cpu_baseline(g, seed: int, first: int, threads: int, per_thread: int):
 
 
 def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: float, duration: float,
-                maintenance: int = 0, one_at_a_time: bool = False):
+                maintenance: int = 0, one_at_a_time: bool = False, n_req: int = 0, saturate: bool = False):
     """Served query and update latency on resident graphs (continuous batching,
     paper_2511_16356_amd.serve): Poisson arrivals, 80% Kemeny queries and 20%
     update batches, half deletions (sizes log-uniform in [1, 1000], batches
@@ -86,8 +86,11 @@ def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: fl
     t_gen = time.perf_counter()
     gs = graphgen.serving_graphs(graphs, lo, hi, seed)
     rng = np.random.default_rng(seed + 1)
-    n_req = int(rate * duration)
-    times = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    n_req = n_req or int(rate * duration)
+    # unit-rate gaps scaled by the rate: the same requests at every rate
+    times = np.cumsum(rng.exponential(1.0, size=n_req)) / rate
+    if saturate:
+        times = np.zeros(n_req)  # everything arrives at once: the makespan gives the capacity
     upd = rng.random(n_req) < 0.2
     gids = rng.integers(0, graphs, size=n_req)
     cur = list(gs)
@@ -213,6 +216,28 @@ def plain_leg(G, seed: int, count: int):
     log("plain: %d samples one at a time in %.1f s" % (count, dt))
     return {"samples": count, "sample_ids": "0..%d" % (count - 1), "seconds": dt, "samples_per_s": count / dt,
             "draws_per_sample": draws / count}
+
+
+def serve_sweep(seed: int, graphs: int, samples: int, n_req: int):
+    """Served latency against offered load under improved maintenance: first
+    the capacity (all requests at once, requests per second over the
+    makespan), then Poisson arrivals at 0.25, 0.5 and 0.8 of it; the same
+    graphs and requests every time."""
+    sat = serving_leg(seed, graphs, 10_000, 30_000, samples, 1.0, 0.0, maintenance=1, n_req=n_req,
+                      saturate=True)
+    cap = sat["throughput_req_per_s"]
+    levels = []
+    for frac in (0.25, 0.5, 0.8):
+        rate = frac * cap
+        leg = serving_leg(seed, graphs, 10_000, 30_000, samples, rate, n_req / rate, maintenance=1, n_req=n_req)
+        levels.append({"load": frac, "rate_req_per_s": rate, "query": leg["query"], "update": leg["update"],
+                       "throughput_req_per_s": leg["throughput_req_per_s"], "errors": leg["errors"]})
+        log("sweep: load %.2f (%.1f req/s): query p99 %.2f ms, update p99 %.1f ms" %
+            (frac, rate, leg["query"]["p99_ms"], leg["update"]["p99_ms"]))
+    return {"sweep": "served latency vs offered load, improved maintenance (Algorithm 3)",
+            "workload": sat["workload"].split(";")[0] + "; %d requests per level, same mix" % n_req,
+            "capacity_req_per_s": cap, "saturated": {"query": sat["query"], "update": sat["update"]},
+            "levels": levels}
 
 
 def study_graphs(points: int):
@@ -355,6 +380,8 @@ def main():
     ap.add_argument("--study", choices=["tau0", "root"], default=None,
                     help="instead of the benchmark, run the reference-tree (Exp-II) or root-degree "
                          "(Exp-III) study on reduced graphs and print its JSON line")
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="instead of the benchmark, measure served latency against offered load")
     ap.add_argument("--study-points", type=int, default=100_000)
     ap.add_argument("--study-samples", type=int, default=512)
     ap.add_argument("--calibrate-random", type=int, default=0, metavar="GIB",
@@ -372,6 +399,11 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path (samples would "
               "shard by index range, with one 32-byte all-reduce of the sums at the end)", file=sys.stderr)
         sys.exit(2)
+    if args.serve_sweep:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps(serve_sweep(args.seed + 7, args.serve_graphs, 1024, 60)), flush=True)
+        return
     if args.study:
         import torch
         torch.cuda.set_device(0)
