@@ -177,3 +177,14 @@ def test_bench_algorithmic_bytes():
     # one sector per draw, per vertex (retrace), and per path-mapping term
     assert bench.algorithmic_bytes(draws=100, n=8, depth0=2, samples=3) == 64 * (100 + 3 * (8 + 8 * 2))
     assert bench.algorithmic_bytes(draws=0, n=1024, depth0=60, samples=1) == 64 * (1024 + 1024 * 10)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
