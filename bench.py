@@ -532,6 +532,8 @@ def main():
         threads = min(16, os.cpu_count() or 1)
         try:
             out["cpu_baseline"] = cpu_baseline(g, args.seed, 0, threads, args.cpu_per_thread)
+            # the same oracle on one thread, samples 0..1
+            out["cpu_baseline_1thread"] = cpu_baseline(g, args.seed, 0, 1, 2)
         except Exception as exc:  # the oracle is test infrastructure; report, never fall back
             out["cpu_baseline"] = {"error": str(exc)}
     G.close()
