@@ -379,7 +379,7 @@ def bsm_insert(S: SampleSet, offsets_new, indices_new, u: int, v: int, serial: i
     csum = sum(path_current(t, path) for t in S.parents)
     count = S.parents.shape[0]
     rhat = csum / count
-    p = rhat / (1.0 + rhat)
+    p = rhat / (1.0 + rhat) if rhat > 0.0 else 0.0  # a share of trees: an estimate R <= 0 replaces none
     redo = [t for t in range(count) if update_uniform(S.seed, t, serial) < p]
     P = prepare(offsets_new, indices_new, S.root)
     par = S.parents.copy()
@@ -560,7 +560,7 @@ def ism_insert(W: WeightedSet, offsets_new, indices_new, u: int, v: int):
     rhat = 0.0
     for t in range(count):
         rhat += W.w[t] * path_current(S.parents[t], path)
-    rp = rhat / (1.0 + rhat)
+    rp = rhat / (1.0 + rhat) if rhat > 0.0 else 0.0
     k = min(count, int(math.ceil(rp * count)))
     order = sorted(range(count), key=lambda t: (update_uniform(S.seed, t, W.serial), t))
     chosen = sorted(order[:k])

@@ -1226,7 +1226,9 @@ static kc_status apply_insertion(kc_graph *g, int32_t a, int32_t b, int32_t *res
         int64_t csum = 0;
         for (int64_t x : c) csum += x;
         const double rhat = (double)csum / (double)g->res_count;
-        const double p = rhat / (1.0 + rhat);  // R_G'(e), Theorem 4.1
+        // R_G'(e) = R / (1 + R), Theorem 4.1; an estimate R <= 0 (possible for a
+        // small set) means no tree is replaced
+        const double p = rhat > 0.0 ? rhat / (1.0 + rhat) : 0.0;
         for (int32_t t = 0; t < g->res_count; ++t)
             if (update_uniform(g->res_seed, (uint32_t)t, (uint32_t)g->res_serial) < p) redo.push_back(t);
     }
@@ -1350,7 +1352,7 @@ static kc_status ism_insertion(kc_graph *g, int32_t a, int32_t b, int32_t *chang
     if (st != KC_OK) return st;
     double rhat = 0.0;
     for (int32_t t = 0; t < count; ++t) rhat += g->res_w[(size_t)t] * (double)c[(size_t)t];
-    const double rp = rhat / (1.0 + rhat);
+    const double rp = rhat > 0.0 ? rhat / (1.0 + rhat) : 0.0;  // as in the basic case
     const int32_t k = (int32_t)std::min<double>((double)count, std::ceil(rp * (double)count));
     // ceil(R' |S|) trees chosen uniformly: the smallest replacement draws
     std::vector<std::pair<double, int32_t>> key((size_t)count);
