@@ -367,6 +367,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--samples", type=int, default=4096, help="tree samples per step")
     ap.add_argument("--points", type=int, default=1_000_000)
+    ap.add_argument("--workload", choices=["road", "social"], default="road",
+                    help="road: the benchmark workload; social: the Chung-Lu power-law graph")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-per-thread", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
@@ -417,7 +419,10 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    g = graphgen.road_like(args.points, seed=0)
+    if args.workload == "road":
+        g = graphgen.road_like(args.points, seed=0)
+    else:
+        g = graphgen.chung_lu(1_000_000, 2.2, 10.0, 5000.0, seed=0)
     log("graph: n=%d 2m=%d (%.1f s)" % (g.n, g.two_m, time.perf_counter() - t0))
     G = kc.Graph.from_graph(g)
     info = G.info
@@ -475,7 +480,7 @@ def main():
     achieved = alg / (gpu_ms / 1e3) / 1e9  # GB/s: algorithmic bytes over the timed launches
     meas = MEASURED_TRAFFIC.get(kernel_sha())
     traffic = None  # HBM bytes per launch, when counters exist for this kernel and workload
-    if meas and (meas["samples"], meas["points"], meas["seed"]) == (B, args.points, args.seed):
+    if meas and args.workload == "road" and (meas["samples"], meas["points"], meas["seed"]) == (B, args.points, args.seed):
         traffic = meas["bytes"]
     out = {
         "metric": METRIC,
@@ -491,10 +496,15 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {
-            "workload": "road-like: thinned random geometric graph, %d uniform points, radius for "
-                        "mean degree 12, edges kept w.p. 0.2055, largest component (n=%d, m=%d, "
-                        "depth0=%d), int32 CSR; %d tree samples per step, Philox seed %d"
-                        % (args.points, g.n, g.two_m // 2, info["depth0"], B, args.seed),
+            "workload": ("road-like: thinned random geometric graph, %d uniform points, radius for "
+                         "mean degree 12, edges kept w.p. 0.2055, largest component (n=%d, m=%d, "
+                         "depth0=%d), int32 CSR; %d tree samples per step, Philox seed %d"
+                         % (args.points, g.n, g.two_m // 2, info["depth0"], B, args.seed))
+                        if args.workload == "road" else
+                        ("social-like: Chung-Lu, 1,000,000 vertices, power-law expected degrees "
+                         "(exponent 2.2, mean 10, cap 5,000), largest component (n=%d, m=%d, depth0=%d), "
+                         "int32 CSR; %d tree samples per step, Philox seed %d"
+                         % (g.n, g.two_m // 2, info["depth0"], B, args.seed)),
             "samples_per_step": B,
             "parallelism": "1 GPU, one wavefront per sample in flight",
         },
