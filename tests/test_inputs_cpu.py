@@ -1,0 +1,59 @@
+"""The seeded synthetic inputs (graphgen) are reproducible and have the
+shapes the measurements were quoted on; every generated graph is a valid
+input (simple, symmetric, rows ascending, connected)."""
+import numpy as np
+import pytest
+
+
+def _valid(g):
+    n = g.n
+    off, adj = g.offsets, g.indices
+    assert off[0] == 0 and off[-1] == adj.shape[0]
+    src = np.repeat(np.arange(n), np.diff(off))
+    assert not np.any(src == adj)                       # no self-loops
+    for v in range(0, n, max(1, n // 200)):             # rows strictly ascending (sampled rows)
+        row = adj[off[v]:off[v + 1]]
+        assert np.all(np.diff(row) > 0)
+    key = src.astype(np.int64) * n + adj
+    rev = adj.astype(np.int64) * n + src
+    assert np.array_equal(np.sort(key), np.sort(rev))   # symmetric
+
+
+def test_benchmark_graph_shape(gen):
+    g = gen.road_like(1_000_000, seed=0)
+    assert (g.n, g.two_m // 2) == (792_324, 1_109_640)
+    _valid(g)
+    assert gen.is_connected(g)
+    h = gen.road_like(1_000_000, seed=0)
+    assert np.array_equal(g.offsets, h.offsets) and np.array_equal(g.indices, h.indices)
+
+
+def test_social_graph_shape(gen):
+    g = gen.chung_lu(1_000_000, 2.2, 10.0, 5000.0, seed=0)
+    assert (g.n, g.two_m // 2) == (962_425, 5_035_660)
+    _valid(g)
+    assert gen.is_connected(g)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_serving_graphs_valid(gen, seed):
+    for g in gen.serving_graphs(6, 2_000, 6_000, seed):
+        _valid(g)
+        assert gen.is_connected(g)
+        assert 1_000 <= g.n <= 6_000
+
+
+def test_update_batches_keep_the_graph_valid(gen):
+    rng = np.random.default_rng(1)
+    g = gen.road_like(5_000, seed=2)
+    for size in (1, 10, 200):
+        batch = gen.deletion_batch(g, size, rng)
+        assert len(batch) <= size and len(set(batch)) == len(batch)  # may be empty: only bridges drawn
+        g = gen.remove_edges(g, batch)
+        _valid(g)
+        assert gen.is_connected(g)
+        ins = gen.insertion_batch(g, 5, rng)
+        for a, b in ins:
+            assert a != b and b not in g.indices[g.offsets[a]:g.offsets[a + 1]]
+        g = gen.add_edges(g, ins)
+        _valid(g)
