@@ -1,7 +1,10 @@
 // kc_host.cpp -- C ABI (include/kc.h): validation, graph preparation,
-// device workspace and launches.  Graph preparation (root, BFS tree tau0,
-// tau0 preorder) runs once per graph on the host; everything per sample runs
-// in the kernels of kc_device.hip.
+// device workspace and launches.  Graph preparation (root, tau0 by its rule,
+// tau0 preorder) runs once per graph version on the host; everything per
+// sample runs in the kernels of kc_device.hip.  The sample maintenance of
+// section 4 keeps its bookkeeping here (which trees to replace or transform,
+// the weights of Algorithm 3, the switch to the updated graph and its undo on
+// failure); the per-tree work runs on the device.
 
 #include <hip/hip_runtime.h>
 
