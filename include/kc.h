@@ -98,7 +98,8 @@ enum {
                               More finish one sample in fewer rounds; fewer let more samples
                               run at once.  Results do not depend on it. */
     KC_OPT_MAINTENANCE = 8 /* KC_MAINT_*: how kc_apply_updates maintains the resident set;
-                              set while no resident set exists (before kc_samples_init) */
+                              may change while the set's weights are all equal (always under
+                              basic maintenance), else KC_ERR_INVALID */
 };
 
 /* Sample maintenance of a resident set (section 4). */

@@ -765,7 +765,10 @@ kc_status kc_set_option(kc_graph *g, int option, int64_t value) {
             if (value != KC_MAINT_BASIC && value != KC_MAINT_IMPROVED)
                 return fail(KC_ERR_INVALID, "maintenance must be KC_MAINT_BASIC or KC_MAINT_IMPROVED");
             if (g->res_count > 0 && value != g->maint)
-                return fail(KC_ERR_INVALID, "choose the maintenance before kc_samples_init");
+                for (double w : g->res_w)
+                    if (w != g->res_w[0])  // weighted trees are not a uniform set for basic maintenance
+                        return fail(KC_ERR_INVALID, "the resident trees carry unequal weights; "
+                                                    "re-initialise the set to change the maintenance");
             g->maint = (int32_t)value;
             return KC_OK;
         case KC_OPT_START_ORDER: {
