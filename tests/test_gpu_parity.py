@@ -8,7 +8,6 @@ Bars (exact integer work, so exactness everywhere):
   - results independent of walkers per sample, samples in flight, batch
     split and traversal variant.
 """
-import os
 import sys
 
 import numpy as np
