@@ -719,16 +719,25 @@ kc_status kc_set_tau0(kc_graph *g, int kind, const int32_t *parent, void *hip_st
         const kc_status st = prepare_graph(g->h_off, g->h_adj, g->root, kind, &given, &probe);
         if (st != KC_OK) return st;
     }
+    const int32_t old_kind = g->tau0_kind;
+    std::vector<int32_t> old_tau0 = g->h_tau0;
     g->tau0_kind = kind;
     g->h_tau0.swap(given);
     kc_status st = rebuild_graph(g, g->root, stream);
-    if (st != KC_OK) return st;
-    if (g->res_count > 0) {
-        // resident trees are unchanged; their f is taken over the new tau0 (Theorem 3.4)
+    // resident trees are unchanged; their f is taken over the new tau0 (Theorem 3.4)
+    if (st == KC_OK && g->res_count > 0)
         st = kc_evaluate_trees(g, g->d_res_par, g->res_count, g->d_res_f, hip_stream);
-        if (st != KC_OK) return st;
-        HIP_TRY(hipStreamSynchronize(stream));
+    if (st != KC_OK) {
+        // put back the previous tau0 and the f values taken over it
+        const std::string err = g_last_error;
+        g->tau0_kind = old_kind;
+        g->h_tau0.swap(old_tau0);
+        if (rebuild_graph(g, g->root, stream) == KC_OK && g->res_count > 0)
+            (void)kc_evaluate_trees(g, g->d_res_par, g->res_count, g->d_res_f, hip_stream);
+        g_last_error = err;
+        return st;
     }
+    HIP_TRY(hipStreamSynchronize(stream));
     return KC_OK;
 }
 
