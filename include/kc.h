@@ -242,7 +242,8 @@ kc_status kc_progress(const kc_graph *g, int64_t *samples_done);
  *
  * kc_samples_init draws the trees of samples 0 .. count-1 (as
  * kc_sample_trees, with `seed`) and keeps their parent arrays and f values
- * on the device with the graph.  Replaces any earlier set.
+ * on the device with the graph.  Replaces any earlier set; on an error no
+ * set is resident afterwards.
  * Errors: as kc_sample_trees; KC_ERR_INVALID for count < 1.
  */
 kc_status kc_samples_init(kc_graph *g, uint64_t seed, int32_t count, void *hip_stream);
