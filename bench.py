@@ -244,7 +244,8 @@ def study_graphs(points: int):
     """The three synthetic shapes at a reduced size: the 32x32 grid (exact
     kappa known), road-like and social-like graphs of about `points` vertices."""
     import graphgen
-    return [("grid 32x32", graphgen.grid(32, 32), 3400.358743308690),
+    grid = graphgen.grid(32, 32)
+    return [("grid 32x32", grid, exact_kemeny(grid.offsets, grid.indices)),
             ("road-like %d points" % points, graphgen.road_like(points, seed=0), None),
             ("social-like %d vertices" % points, graphgen.chung_lu(points, 2.2, 10.0, 5000.0, seed=0), None)]
 
