@@ -59,7 +59,7 @@ def algorithmic_bytes(draws: int, n: int, depth0: int, samples: int) -> int:
     return SECTOR * (draws + samples * (n + per_tree_trav))
 
 
-def cpu_baseline(g, seed: int, first: int, threads: int, per_thread: int):
+def cpu_baseline(g, seed: int, first: int, threads: int, per_thread: int, what: str = "the same workload"):
     import oracle
     P = oracle.prepare_graph(g)
     count = threads * per_thread
@@ -67,8 +67,8 @@ def cpu_baseline(g, seed: int, first: int, threads: int, per_thread: int):
     oracle.estimate_f(P, seed=seed, s0=first, count=count, threads=threads)
     dt = time.perf_counter() - t0
     return {"value": count / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
-            "sample": "samples %d..%d of the same workload (%d per thread), %.1f s" %
-                      (first, first + count - 1, per_thread, dt)}
+            "sample": "samples %d..%d of %s (%d per thread), %.1f s" %
+                      (first, first + count - 1, what, per_thread, dt)}
 
 
 def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: float, duration: float,
@@ -545,6 +545,10 @@ def main():
             out["cpu_baseline"] = cpu_baseline(g, args.seed, 0, threads, args.cpu_per_thread)
             # the same oracle on one thread, samples 0..1
             out["cpu_baseline_1thread"] = cpu_baseline(g, args.seed, 0, 1, 2)
+            if not args.no_accuracy:
+                # the oracle on the 32x32 grid of the accuracy leg: all 2,000 samples
+                out["cpu_baseline_grid32"] = cpu_baseline(graphgen.grid(32, 32), args.seed, 0, threads,
+                                                          (2000 + threads - 1) // threads, "the 32x32 grid")
         except Exception as exc:  # the oracle is test infrastructure; report, never fall back
             out["cpu_baseline"] = {"error": str(exc)}
     G.close()
