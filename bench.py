@@ -540,17 +540,21 @@ def main():
                                                            args.serve_rate, args.serve_seconds, maintenance=1,
                                                            one_at_a_time=True)
     if not args.no_cpu:
+        # the oracle is test infrastructure: a failure is reported, never a fallback
         threads = min(16, os.cpu_count() or 1)
-        try:
-            out["cpu_baseline"] = cpu_baseline(g, args.seed, 0, threads, args.cpu_per_thread)
-            # the same oracle on one thread, samples 0..1
-            out["cpu_baseline_1thread"] = cpu_baseline(g, args.seed, 0, 1, 2)
-            if not args.no_accuracy:
-                # the oracle on the 32x32 grid of the accuracy leg: all 2,000 samples
-                out["cpu_baseline_grid32"] = cpu_baseline(graphgen.grid(32, 32), args.seed, 0, threads,
-                                                          (2000 + threads - 1) // threads, "the 32x32 grid")
-        except Exception as exc:  # the oracle is test infrastructure; report, never fall back
-            out["cpu_baseline"] = {"error": str(exc)}
+        legs = [("cpu_baseline", lambda: cpu_baseline(g, args.seed, 0, threads, args.cpu_per_thread)),
+                # the same oracle on one thread, samples 0..1
+                ("cpu_baseline_1thread", lambda: cpu_baseline(g, args.seed, 0, 1, 2))]
+        if not args.no_accuracy:
+            # the oracle on the 32x32 grid of the accuracy leg: all 2,000 samples
+            legs.append(("cpu_baseline_grid32",
+                         lambda: cpu_baseline(graphgen.grid(32, 32), args.seed, 0, threads,
+                                              (2000 + threads - 1) // threads, "the 32x32 grid")))
+        for key, leg in legs:
+            try:
+                out[key] = leg()
+            except Exception as exc:
+                out[key] = {"error": str(exc)}
     G.close()
     print(json.dumps(out), flush=True)
 
