@@ -1,16 +1,21 @@
 """Benchmark: spanning-tree samples/s of the full estimator path on one MI355X.
 
-One step = one kc_estimate call over a batch of tree samples of the
-road-like workload (thinned random geometric graph from 1,000,000 points,
-largest component, int32 CSR; 4,096 samples per batch), i.e. the whole hot
-path: Wilson sampling, subtree volumes and numbering, f(tau) per tree and
-the exact reduction.  Inputs (graph and workspace) are resident in HBM before
-the timed region; sample ids advance from step to step.
+One step = one persistent launch of the estimator over a batch of tree
+samples: Wilson sampling, subtree volumes and numbering, f(tau) per tree and
+the exact reduction (the whole hot path).  The default workload is the
+dense power-law graph: Chung-Lu, 3,000,000 vertices, expected degrees with
+exponent 2.0, mean 76, cap 30,000, largest component, int64 offsets on
+input; 4,096 samples per launch, so four launches make one 16,384-sample
+estimate.  Inputs (graph and workspace) are resident in HBM before the timed
+region; sample ids advance from step to step.
 
-Prints ONE JSON line (rank 0).  Besides the contract fields it carries
-`roofline` (algorithmic HBM bytes of the persistent kernel per launch over
-its average duration, against the 8 TB/s HBM peak) and `cpu_baseline` (the
-CPU oracle on the host cores, on a bounded prefix of the same samples).
+Prints ONE JSON line.  Besides the contract fields it carries `roofline`
+(algorithmic HBM bytes of the persistent kernel per launch over its average
+duration, against the 8 TB/s HBM peak) and `cpu_baseline` (the CPU oracle on
+the host cores, on a bounded sample of the same workload).  The accuracy leg
+(K-hat against exact K on the 32x32 grid), the plain one-sample-at-a-time
+form and a short serving leg follow the timed region while the run stays
+within its wall-clock budget (--budget).
 """
 from __future__ import annotations
 
@@ -30,15 +35,11 @@ SECTOR = 64
 KERNEL_SRC = os.path.join(ROOT, "paper_2511_16356_amd", "csrc", "kc_device.hip")
 
 # HBM bytes per launch of the persistent kernel, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs of this script with default arguments, each scaled by what the
-# counter reads for a plain 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0);
-# profiles/hbm_traffic_persistent_kernel_road_like_1M_b4096.md.  Keyed by the
-# SHA-256 of the kernel source the counters were taken on: another kernel
-# source, or another workload, reports traffic = null.
-MEASURED_TRAFFIC = {
-    "c08ab2f4451658012d25767730e4b86ef0c5c9526b56fdec913a58460c1ab965":
-        {"samples": 4096, "points": 1_000_000, "seed": 0, "bytes": 1.54381e+14},
-}
+# WRITE_SIZE runs of this script, each scaled by what the counter reads for a
+# plain copy of known size (profiles/).  Keyed by the SHA-256 of the kernel
+# source the counters were taken on: another kernel source, or another
+# workload, reports traffic = null.
+MEASURED_TRAFFIC = {}
 
 
 # Measured ceilings of the device (bench.py --calibrate-random 16, libkc_probe.so;
@@ -59,16 +60,37 @@ def algorithmic_bytes(draws: int, n: int, depth0: int, samples: int) -> int:
     return SECTOR * (draws + samples * (n + per_tree_trav))
 
 
+def host_cpu():
+    """(logical CPUs, model name) of the host this runs on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
 def cpu_baseline(g, seed: int, first: int, threads: int, per_thread: int, what: str = "the same workload"):
+    """The CPU oracle as it stands (sequential Wilson per sample, the per-edge
+    f of Theorem 3.4, exact sums) on `threads` host threads, samples split
+    across them, over a bounded sample of `threads * per_thread` ids of the
+    workload; graph preparation is outside the timed region."""
     import oracle
     P = oracle.prepare_graph(g)
     count = threads * per_thread
     t0 = time.perf_counter()
     oracle.estimate_f(P, seed=seed, s0=first, count=count, threads=threads)
     dt = time.perf_counter() - t0
+    nproc, model = host_cpu()
     return {"value": count / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
-            "sample": "samples %d..%d of %s (%d per thread), %.1f s" %
-                      (first, first + count - 1, what, per_thread, dt)}
+            "nproc": nproc, "cpu_model": model,
+            "sample": "samples %d..%d of %s (%d per thread on %d threads), %.1f s; the rate over this "
+                      "bounded sample stands for the workload's" %
+                      (first, first + count - 1, what, per_thread, threads, dt)}
 
 
 def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: float, duration: float,
@@ -361,23 +383,36 @@ def calibrate_random(gib: int):
           flush=True)
 
 
+WORKLOADS = {
+    "dense": ("dense power-law: Chung-Lu, 3,000,000 vertices, expected degrees with exponent 2.0, "
+              "mean 76, cap 30,000, largest component (n=%d, m=%d, depth0=%d), int64 offsets on input"),
+    "road": ("road-like: thinned random geometric graph, 1,000,000 uniform points, radius for mean "
+             "degree 12, edges kept w.p. 0.2055, largest component (n=%d, m=%d, depth0=%d), int32 CSR"),
+    "social": ("social-like: Chung-Lu, 1,000,000 vertices, expected degrees with exponent 2.2, mean 10, "
+               "cap 5,000, largest component (n=%d, m=%d, depth0=%d), int32 CSR"),
+}
+DEFAULT_SAMPLES = {"dense": 4096, "road": 4096, "social": 8192}
+
+
 def main():
+    T_START = time.perf_counter()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--samples", type=int, default=4096, help="tree samples per step")
-    ap.add_argument("--points", type=int, default=1_000_000)
-    ap.add_argument("--workload", choices=["road", "social"], default="road",
-                    help="road: the benchmark workload; social: the Chung-Lu power-law graph")
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="dense",
+                    help="dense: the headline workload (default); road / social: the other shapes")
+    ap.add_argument("--samples", type=int, default=0, help="tree samples per step (launch)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--budget", type=float, default=480.0,
+                    help="wall-clock seconds after which the optional legs are skipped")
     ap.add_argument("--cpu-per-thread", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-latency leg")
     ap.add_argument("--serve-graphs", type=int, default=8)
     ap.add_argument("--serve-rate", type=float, default=5.0, help="requests per second")
-    ap.add_argument("--serve-seconds", type=float, default=12.0)
-    ap.add_argument("--no-accuracy", action="store_true", help="skip the exact-K and plain-form legs")
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the exact-K leg on the 32x32 grid")
     ap.add_argument("--plain-samples", type=int, default=2,
                     help="sample ids run one launch each on the benchmark graph (plain form)")
     ap.add_argument("--study", choices=["tau0", "root"], default=None,
@@ -392,16 +427,16 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (samples would "
+              "shard by index range, with one 32-byte all-reduce of the sums at the end)", file=sys.stderr)
+        sys.exit(2)
     if args.calibrate_random:
         calibrate_random(args.calibrate_random)
         return
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
         return
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: the library has no multi-GPU path (samples would "
-              "shard by index range, with one 32-byte all-reduce of the sums at the end)", file=sys.stderr)
-        sys.exit(2)
     if args.serve_sweep:
         import torch
         torch.cuda.set_device(0)
@@ -420,69 +455,49 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    if args.workload == "road":
-        g = graphgen.road_like(args.points, seed=0)
-    else:
-        g = graphgen.chung_lu(1_000_000, 2.2, 10.0, 5000.0, seed=0)
-    log("graph: n=%d 2m=%d (%.1f s)" % (g.n, g.two_m, time.perf_counter() - t0))
+    g = graphgen.workload(args.workload)
+    log("graph %s: n=%d 2m=%d (%.1f s)" % (args.workload, g.n, g.two_m, time.perf_counter() - t0))
+    t0 = time.perf_counter()
     G = kc.Graph.from_graph(g)
     info = G.info
+    log("prepared on the device (%.1f s): %s" % (time.perf_counter() - t0, info))
     stream = torch.cuda.current_stream()
+    B = args.samples or DEFAULT_SAMPLES[args.workload]
     # set-up (not a step): allocate the workspace for the batch
-    G.reserve(args.samples)
+    G.reserve(B)
     torch.cuda.synchronize()
 
-    B = args.samples
     for w in range(args.warmup):
-        G.estimate(args.seed, (w + 1) * 10 ** 8, B)
+        G.estimate(args.seed, (10 ** 8) + w * B, B)
         log("warmup step %d done" % w)
     torch.cuda.synchronize()
 
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    draws = iters = 0
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ests = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    # progress of the long batch, read from the counters the kernel publishes
-    import threading
-    stop = threading.Event()
-
-    def watch():
-        t_w = time.perf_counter()
-        while not stop.wait(20.0):
-            log("  %.0f s: %d of %d samples of the step finished" % (time.perf_counter() - t_w, G.progress(), B))
-
-    watcher = threading.Thread(target=watch, daemon=True)
-    watcher.start()
-    ev0.record(stream)
     for k in range(args.steps):
+        starts[k].record(stream)
         est = G.estimate(args.seed, k * B, B)
+        ends[k].record(stream)
         ests.append(est)
-        draws += est.total_steps
-        iters += est.sampler_iterations
         log("step %d: kappa=%.1f +- %.1f draws/sample=%.0f" % (k, est.kappa, est.std_error, est.total_steps / B))
-    ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    stop.set()
-    gpu_ms = ev0.elapsed_time(ev1)
+    launch_ms = [starts[k].elapsed_time(ends[k]) for k in range(args.steps)]
 
     total = B * args.steps
-    value = total / wall
-    # pooled estimate over all timed steps
-    s1 = sum(e.sum_f for e in ests)
-    s2 = sum(e.sum_f2 for e in ests)
-    kappa = float(s1) / float(g.two_m * total)
-    mean = float(s1) / total
-    var = (float(s2) - total * mean * mean) / max(1, total - 1)
-    se = math.sqrt(max(var, 0.0) / total) / g.two_m
+    pooled = G.combine(ests)
+    draws = pooled.total_steps
     alg = algorithmic_bytes(draws, g.n, info["depth0"], total)
-    achieved = alg / (gpu_ms / 1e3) / 1e9  # GB/s: algorithmic bytes over the timed launches
+    avg_launch_s = sum(launch_ms) / len(launch_ms) / 1e3
+    achieved = alg / args.steps / avg_launch_s / 1e9  # GB/s: algorithmic bytes per launch over its duration
     meas = MEASURED_TRAFFIC.get(kernel_sha())
     traffic = None  # HBM bytes per launch, when counters exist for this kernel and workload
-    if meas and args.workload == "road" and (meas["samples"], meas["points"], meas["seed"]) == (B, args.points, args.seed):
+    if meas and (meas["workload"], meas["samples"], meas["seed"]) == (args.workload, B, args.seed):
         traffic = meas["bytes"]
+    value = total / wall
     out = {
         "metric": METRIC,
         "value": value,
@@ -497,24 +512,17 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {
-            "workload": ("road-like: thinned random geometric graph, %d uniform points, radius for "
-                         "mean degree 12, edges kept w.p. 0.2055, largest component (n=%d, m=%d, "
-                         "depth0=%d), int32 CSR; %d tree samples per step, Philox seed %d"
-                         % (args.points, g.n, g.two_m // 2, info["depth0"], B, args.seed))
-                        if args.workload == "road" else
-                        ("social-like: Chung-Lu, 1,000,000 vertices, power-law expected degrees "
-                         "(exponent 2.2, mean 10, cap 5,000), largest component (n=%d, m=%d, depth0=%d), "
-                         "int32 CSR; %d tree samples per step, Philox seed %d"
-                         % (g.n, g.two_m // 2, info["depth0"], B, args.seed)),
+            "workload": (WORKLOADS[args.workload] % (g.n, g.two_m // 2, info["depth0"])) +
+                        "; %d tree samples per step (one persistent launch), Philox seed %d" % (B, args.seed),
             "samples_per_step": B,
             "parallelism": "1 GPU, one wavefront per sample in flight",
         },
-        "kappa": kappa,
-        "kappa_std_error": se,
-        "kappa_rel_ci95": 1.959963984540054 * se / kappa if kappa else None,
+        "kappa": pooled.kappa,
+        "kappa_std_error": pooled.std_error,
+        "kappa_rel_ci95": 1.959963984540054 * pooled.std_error / pooled.kappa if pooled.kappa else None,
         "draws_per_sample": draws / total,
-        "draws_per_sampler_round": draws / max(1, iters),
-        "gpu_ms_per_step": gpu_ms / args.steps,
+        "draws_per_sampler_round": draws / max(1, pooled.sampler_iterations),
+        "launch_ms": launch_ms,
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
@@ -527,35 +535,32 @@ def main():
             "frac_of_random_64B_ceiling": achieved / MEASURED_CEILINGS["random_64B_read_GBps"],
         },
     }
-    if not args.no_accuracy:
-        out["plain_one_at_a_time"] = plain_leg(G, args.seed, args.plain_samples)
-        out["plain_one_at_a_time"]["batched_samples_per_s"] = value
-        out["accuracy"] = accuracy_leg(args.seed, 8192, 2000)
-    if not args.no_serve:
-        out["served"] = serving_leg(args.seed + 7, args.serve_graphs, 10_000, 30_000, 1024,
-                                    args.serve_rate, args.serve_seconds)
-        out["served_improved"] = serving_leg(args.seed + 7, args.serve_graphs, 10_000, 30_000, 1024,
-                                             args.serve_rate, args.serve_seconds, maintenance=1)
-        out["served_improved_one_at_a_time"] = serving_leg(args.seed + 7, args.serve_graphs, 10_000, 30_000, 1024,
-                                                           args.serve_rate, args.serve_seconds, maintenance=1,
-                                                           one_at_a_time=True)
+    log("timed: %.1f samples/s, %.1f ms per launch, %.0f GB/s algorithmic" % (value, avg_launch_s * 1e3, achieved))
+
+    def budget_left(need_s: float) -> bool:
+        return time.perf_counter() - T_START + need_s < args.budget
+
+    skipped = {"skipped": "wall-clock budget of %.0f s reached" % args.budget}
     if not args.no_cpu:
         # the oracle is test infrastructure: a failure is reported, never a fallback
         threads = min(16, os.cpu_count() or 1)
-        legs = [("cpu_baseline", lambda: cpu_baseline(g, args.seed, 0, threads, args.cpu_per_thread)),
-                # the same oracle on one thread, samples 0..1
-                ("cpu_baseline_1thread", lambda: cpu_baseline(g, args.seed, 0, 1, 2))]
-        if not args.no_accuracy:
-            # the oracle on the 32x32 grid of the accuracy leg: all 2,000 samples
-            legs.append(("cpu_baseline_grid32",
-                         lambda: cpu_baseline(graphgen.grid(32, 32), args.seed, 0, threads,
-                                              (2000 + threads - 1) // threads, "the 32x32 grid")))
-        for key, leg in legs:
-            try:
-                out[key] = leg()
-            except Exception as exc:
-                out[key] = {"error": str(exc)}
+        try:
+            out["cpu_baseline"] = cpu_baseline(g, args.seed, 0, threads, args.cpu_per_thread) \
+                if budget_left(60) else skipped
+        except Exception as exc:
+            out["cpu_baseline"] = {"error": str(exc)}
+    if args.plain_samples > 0:
+        out["plain_one_at_a_time"] = plain_leg(G, args.seed, args.plain_samples) if budget_left(30) else skipped
+        if "samples_per_s" in out["plain_one_at_a_time"]:
+            out["plain_one_at_a_time"]["batched_samples_per_s"] = value
     G.close()
+    del G
+    if not args.no_accuracy:
+        out["accuracy"] = accuracy_leg(args.seed, 8192, 2000) if budget_left(30) else skipped
+    if not args.no_serve:
+        out["served"] = serving_leg(args.seed + 7, args.serve_graphs, 10_000, 30_000, 1024, args.serve_rate,
+                                    args.serve_seconds, maintenance=1) if budget_left(60) else skipped
+    out["wall_s"] = time.perf_counter() - T_START
     print(json.dumps(out), flush=True)
 
 

@@ -47,6 +47,8 @@ def _load():
         lib.gg_rgg_edges.argtypes = [i64, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, p, p, i64]
         lib.gg_chung_lu_edges.restype = i64
         lib.gg_chung_lu_edges.argtypes = [i64, p, ctypes.c_uint64, p, p, i64]
+        lib.gg_lcc.restype = i64
+        lib.gg_lcc.argtypes = [i64, p, p, p, p]
         _lib = lib
     return _lib
 
@@ -152,35 +154,26 @@ def is_connected(g: Graph) -> bool:
 
 
 def largest_component(g: Graph) -> Graph:
-    """Keep the largest connected component, relabelled in original order."""
-    from scipy.sparse import csr_matrix
-    from scipy.sparse.csgraph import connected_components
-
+    """Keep the largest connected component, relabelled in original order
+    (ties between equally large components go to the one holding the smallest
+    vertex)."""
     n = g.n
     if n == 0:
         return g
-    mat = csr_matrix((np.ones(g.indices.shape[0], dtype=np.int8), g.indices, g.offsets), shape=(n, n))
-    ncomp, lab = connected_components(mat, directed=False)
-    if ncomp == 1:
-        g.meta.setdefault("n_before_lcc", n)
-        return g
-    big = np.bincount(lab).argmax()
-    keep = lab == big
-    newid = np.full(n, -1, dtype=np.int64)
-    newid[keep] = np.arange(int(keep.sum()))
-    deg = g.degrees
-    rows = np.repeat(np.arange(n), deg)
-    sel = keep[rows]
-    r2 = newid[rows[sel]]
-    c2 = newid[g.indices[sel]]
-    n2 = int(keep.sum())
-    off2 = np.zeros(n2 + 1, dtype=np.int64)
-    np.add.at(off2, r2 + 1, 1)
-    off2 = np.cumsum(off2)
-    # rows stay sorted because relabelling is monotone and rows were sorted
+    off = np.ascontiguousarray(g.offsets, dtype=np.int64)
+    idx = np.ascontiguousarray(g.indices, dtype=np.int32)
+    off2 = np.zeros(n + 1, dtype=np.int64)
+    idx2 = np.empty(max(1, idx.shape[0]), dtype=np.int32)
+    n2 = int(_load().gg_lcc(n, _ptr(off), _ptr(idx), _ptr(off2), _ptr(idx2)))
+    if n2 < 0:
+        raise MemoryError("gg_lcc failed")
     meta = dict(g.meta)
     meta["n_before_lcc"] = n
-    return Graph(g.name, off2, c2.astype(np.int32), meta)
+    if n2 == n:
+        g.meta.setdefault("n_before_lcc", n)
+        return g
+    off2 = off2[: n2 + 1].copy()
+    return Graph(g.name, off2, idx2[: int(off2[-1])].copy(), meta)
 
 
 # ----------------------------------------------------------------- small graphs

@@ -221,3 +221,50 @@ int64_t gg_chung_lu_edges(int64_t n, const double *w, uint64_t seed,
     }
     return cnt <= cap ? cnt : -cnt;
 }
+
+/*
+ * Largest connected component of a CSR graph, relabelled in original vertex
+ * order (the relabelling is monotone, so rows stay ascending).  Components
+ * are found by breadth-first search from each unlabelled vertex in
+ * ascending order; ties between equally large components go to the one
+ * holding the smallest vertex.  Writes the component's CSR into off_out
+ * (n_out+1 slots) and idx_out (at most offsets[n] entries) and returns its
+ * vertex count n_out (n when the graph is connected), or -1 on allocation
+ * failure.
+ */
+int64_t gg_lcc(int64_t n, const int64_t *off, const int32_t *idx, int64_t *off_out, int32_t *idx_out) {
+    int32_t *comp = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!comp || !queue) { free(comp); free(queue); return -1; }
+    for (int64_t v = 0; v < n; ++v) comp[v] = -1;
+    int32_t ncomp = 0, best = -1;
+    int64_t best_size = 0;
+    for (int64_t s = 0; s < n; ++s) {
+        if (comp[s] >= 0) continue;
+        int64_t qh = 0, qt = 0;
+        comp[s] = ncomp;
+        queue[qt++] = (int32_t)s;
+        while (qh < qt) {
+            int32_t x = queue[qh++];
+            for (int64_t e = off[x]; e < off[x + 1]; ++e) {
+                int32_t y = idx[e];
+                if (comp[y] < 0) { comp[y] = ncomp; queue[qt++] = y; }
+            }
+        }
+        if (qt > best_size) { best_size = qt; best = ncomp; }
+        ncomp++;
+    }
+    /* new id of each kept vertex, in original order */
+    int32_t *newid = queue;
+    int64_t k = 0;
+    for (int64_t v = 0; v < n; ++v) newid[v] = comp[v] == best ? (int32_t)k++ : -1;
+    int64_t w = 0;
+    off_out[0] = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        if (newid[v] < 0) continue;
+        for (int64_t e = off[v]; e < off[v + 1]; ++e) idx_out[w++] = newid[idx[e]];
+        off_out[newid[v] + 1] = w;
+    }
+    free(comp); free(queue);
+    return k;
+}

@@ -63,6 +63,8 @@ typedef struct {
     int32_t traversal;  /* KC_TRAV_WALK or KC_TRAV_SWEEP, as chosen for this graph */
     int64_t device_bytes; /* graph arrays resident on the device */
     int32_t tau0;       /* KC_TAU0_* rule tau0 is built with */
+    int64_t sample_bytes; /* device workspace one sample in flight needs in kc_estimate under the
+                             current traversal (sampler state, tree numbering, sweep Fenwick tree) */
 } kc_graph_info;
 
 /* How tau0, the fixed spanning tree whose root paths define the path mapping,
@@ -214,13 +216,27 @@ kc_status kc_estimate(kc_graph *g, uint64_t seed, int64_t first_sample, int32_t 
                       kc_result *result, int64_t *f_out, int64_t *steps_out, void *hip_stream);
 
 /*
+ * Pool results of the same graph over disjoint sample ranges (for example the
+ * successive batches of a long run) into one estimate of Theorem 3.3 over all
+ * their samples: the exact sums and counts add, and kappa and std_error are
+ * recomputed from the pooled sums exactly as kc_estimate computes them.
+ *   parts : HOST pointer, k results of kc_estimate (or of other calls that
+ *           fill kc_result) on this graph; out : HOST pointer
+ * Errors: KC_ERR_INVALID (NULL argument, k < 1, a part with count < 1).
+ */
+kc_status kc_combine_results(const kc_graph *g, const kc_result *parts, int32_t k, kc_result *out);
+
+/*
  * Evaluate f for caller-supplied rooted spanning trees (no sampling).
  *   parents : DEVICE pointer, count*n int32 parent arrays rooted at the
- *             graph's root (root -> -1); every edge (v, parent[v]) must be a
- *             graph edge and the array must describe a spanning tree
- *             (not checked on the device: a non-tree gives an undefined f,
- *             never an out-of-bounds access).
+ *             graph's root (root -> -1; the root's entry is not read).
+ *             Every edge (v, parent[v]) should be a graph edge.
  *   f_out   : DEVICE pointer, count int64
+ * The kernels check each array: a parent out of range or equal to its vertex,
+ * or parents that do not form one tree rooted at r (a cycle, a vertex that
+ * does not reach r), give KC_ERR_INVALID.  Whether each (v, parent[v]) is an
+ * edge of the graph is not checked; f of such an array is that of the tree
+ * it describes, on the graph's degrees.
  */
 kc_status kc_evaluate_trees(kc_graph *g, const int32_t *parents, int32_t count, int64_t *f_out,
                             void *hip_stream);
@@ -263,8 +279,10 @@ kc_status kc_samples_weights(const kc_graph *g, double *w_out);
 
 /* Copy the resident set out: parents_out DEVICE [count*n] int32, f_out
  * DEVICE [count] int64, ids_out HOST [count] int64 (the sample index each
- * tree was drawn with); any may be NULL.  count is the set's size. */
-kc_status kc_samples_get(const kc_graph *g, int32_t *parents_out, int64_t *f_out, int64_t *ids_out,
+ * tree was drawn with); any may be NULL.  count is the set's size.  If the
+ * last update could not recompute f on the device, f is recomputed first
+ * (kc_samples_query does the same), and its failure is returned. */
+kc_status kc_samples_get(kc_graph *g, int32_t *parents_out, int64_t *f_out, int64_t *ids_out,
                          void *hip_stream);
 
 /*
@@ -320,8 +338,14 @@ kc_status kc_samples_get(const kc_graph *g, int32_t *parents_out, int64_t *f_out
  * reach 2^31), and those of kc_sample_trees.  Updates before the failing one
  * stay applied; the failing one changes nothing, also when it fails on the
  * device after the graph was switched (the previous graph and trees are put
- * back).  A run of deletions counts as one update under KC_MAINT_BASIC and
- * as one update per edge under KC_MAINT_IMPROVED.
+ * back).  f of the resident trees is recomputed once at the end of the call;
+ * if that recomputation fails (for example KC_ERR_NOMEM when the graph grew
+ * past KC_OPT_MEM_BUDGET), the call returns its error with the updates in
+ * place, and f stays marked stale: kc_samples_query and kc_samples_get
+ * recompute it first and return the failure again while it persists, so no
+ * query ever reduces f values of an earlier graph.  A run of deletions
+ * counts as one update under KC_MAINT_BASIC and as one update per edge under
+ * KC_MAINT_IMPROVED.
  */
 kc_status kc_apply_updates(kc_graph *g, const int32_t *u, const int32_t *v, const uint8_t *is_insert,
                            int32_t count, int32_t *resampled, void *hip_stream);

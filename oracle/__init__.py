@@ -24,9 +24,11 @@ _SRC = os.path.join(_HERE, "kc_oracle.c")
 _LIB = os.path.join(_HERE, "libkc_oracle.so")
 _lib = None
 
-F_NAIVE, F_ALG1, F_PEREDGE, F_WALK, F_ALG1_PRINTED = 1, 2, 3, 4, 5
-FORMS = {"naive": F_NAIVE, "alg1": F_ALG1, "peredge": F_PEREDGE, "walk": F_WALK,
-         "alg1_printed": F_ALG1_PRINTED}
+F_NAIVE, F_PEREDGE, F_WALK = 1, 3, 4
+# f(tau) in three independent forms: the definition of Theorem 3.3 (naive), the
+# per-edge sums of Theorem 3.4 (peredge, the default) and the tau0-ancestor walk
+# of the complexity remark after Theorem 3.5 (walk)
+FORMS = {"naive": F_NAIVE, "peredge": F_PEREDGE, "walk": F_WALK}
 
 ERRORS = {1: "invalid graph", 2: "graph is disconnected", 3: "out of memory", 6: "step limit"}
 
@@ -65,6 +67,9 @@ def _load():
         lib.orc_estimate.restype = ctypes.c_int
         lib.orc_estimate.argtypes = [i64, p, p, i32, p, p, p, u64, i64, i64, ctypes.c_int,
                                      ctypes.c_int, i64, p, p]
+        lib.orc_estimate_ids.restype = ctypes.c_int
+        lib.orc_estimate_ids.argtypes = [i64, p, p, i32, p, p, p, u64, p, i64, ctypes.c_int,
+                                         ctypes.c_int, i64, p, p]
         _lib = lib
     return _lib
 
@@ -191,7 +196,7 @@ def wilson(P: Prepared, seed: int, s: int, order=None):
     return parent, cnt, int(steps.value)
 
 
-def f_of_tree(P: Prepared, parent, form: str = "alg1") -> int:
+def f_of_tree(P: Prepared, parent, form: str = "peredge") -> int:
     par = np.ascontiguousarray(parent, dtype=np.int32)
     f = ctypes.c_int64()
     _check(_load().orc_f(P.n, _ptr(P.offsets), P.root, _ptr(P.p0), _ptr(P.in0), _ptr(P.out0),
@@ -211,13 +216,26 @@ def sample(P: Prepared, seed: int, s0: int, count: int, threads: int = 1, max_st
 
 
 def estimate_f(P: Prepared, seed: int, s0: int, count: int, threads: int = 1,
-               form: str = "alg1", max_steps: int = 0):
+               form: str = "peredge", max_steps: int = 0):
     """Per-sample f (int64) and total draws for samples s0..s0+count-1."""
     f = np.zeros(count, np.int64)
     steps = np.zeros(count, np.int64)
     _check(_load().orc_estimate(P.n, _ptr(P.offsets), _ptr(P.indices), P.root, _ptr(P.p0),
                                 _ptr(P.in0), _ptr(P.out0), seed, s0, count, threads,
                                 FORMS[form], max_steps, _ptr(f), _ptr(steps)))
+    return f, steps
+
+
+def estimate_ids(P: Prepared, seed: int, ids, threads: int = 1, form: str = "peredge",
+                 max_steps: int = 0):
+    """Per-sample f (int64) and total draws for the listed sample ids."""
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    count = int(ids.shape[0])
+    f = np.zeros(count, np.int64)
+    steps = np.zeros(count, np.int64)
+    _check(_load().orc_estimate_ids(P.n, _ptr(P.offsets), _ptr(P.indices), P.root, _ptr(P.p0),
+                                    _ptr(P.in0), _ptr(P.out0), seed, _ptr(ids), count, threads,
+                                    FORMS[form], max_steps, _ptr(f), _ptr(steps)))
     return f, steps
 
 

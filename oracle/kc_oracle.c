@@ -18,12 +18,11 @@
  *     each (sample, vertex, visit-count) drawing its neighbour from a
  *     Philox4x32-10 stream, so the sampled tree equals the cycle-popping
  *     result and does not depend on the walk order;
- *   - the per-tree value f(tau) of Theorem 3.3 in four independent forms:
+ *   - the per-tree value f(tau) of Theorem 3.3 in three independent forms:
  *       F1 naive       : the definition in Theorem 3.3 (compare each vertex's
  *                        tree path with its fixed tau0 path);
- *       F2 Algorithm 1 : the DFS over tau with a Fenwick tree over tau0's
- *                        numbering (with the undo-sign reading, see below);
- *       F3 per edge    : the two sums of Theorem 3.4;
+ *       F3 per edge    : the two sums of Theorem 3.4, each intersection
+ *                        counted by brute force (the default form);
  *       F4 tau0 walk   : the O(n * depth) form mentioned in the proof of
  *                        Theorem 3.5 (walk each vertex's tau0 path and test
  *                        tree ancestry);
@@ -33,11 +32,10 @@
  * Readings of the paper (where it is silent or misprinted):
  *   - Ties for the root go to the smallest vertex index; the BFS parent of v
  *     is its smallest-index neighbour one level closer to the root.
- *   - Algorithm 1's line "kappa <- d(v) * Query" is read as accumulation.
- *   - Algorithm 1's undo for the reverse case is printed with the same sign
- *     as the apply; it must be the opposite sign (restore the structure).
- *     orc_f_alg1() takes a flag that reproduces the printed sign so a test
- *     can show that the printed form disagrees with Theorem 3.3.
+ *   - Algorithm 1 (a depth-first search over tau with a Fenwick tree over
+ *     tau0's numbering) is not reproduced here: it is one way to evaluate
+ *     the sums of Theorem 3.4, and the forms above evaluate the same sums
+ *     directly from their definitions.
  *   - The random arrow: Philox4x32-10 (Salmon et al., SC'11) with counter
  *     (k, v, s_lo, s_hi) and key (seed_lo, seed_hi); outputs o0, o1 form
  *     x = o0 | o1 << 32, and the neighbour slot is floor(x * deg / 2^64).
@@ -320,66 +318,6 @@ static int64_t f_naive(tree_ctx *t) {
     return f;
 }
 
-/* Fenwick tree over positions 1..n storing a difference array: range add,
- * point query. */
-static void bit_add(int64_t *b, int64_t n, int64_t i, int64_t val) {
-    for (; i <= n; i += i & (-i)) b[i] += val;
-}
-static int64_t bit_prefix(const int64_t *b, int64_t i) {
-    int64_t s = 0;
-    for (; i > 0; i -= i & (-i)) s += b[i];
-    return s;
-}
-static void range_add(int64_t *b, int64_t n, int64_t l, int64_t r, int64_t val) {
-    /* positions are 0-based preorder numbers; Fenwick is 1-based */
-    bit_add(b, n, l + 1, val);
-    bit_add(b, n, r + 2, -val);
-}
-static int64_t point_query(const int64_t *b, int64_t i) { return bit_prefix(b, i + 1); }
-
-/*
- * F2 -- Algorithm 1's DFS over tau with vol_sum kept in a Fenwick tree over
- * tau0's numbering.  On entering v: if (v, p(v)) is a tau0 edge oriented the
- * same way, add 2m - vol[v] on Sub(tau0, v); if it is oriented the other way,
- * add vol[v] - 2m on Sub(tau0, p(v)).  Then accumulate d(v) * vol_sum[v],
- * recurse, and undo on exit.  printed_sign != 0 reproduces the undo as
- * printed for the reverse case (same sign as the apply).
- */
-static int64_t f_alg1(tree_ctx *t, int printed_sign) {
-    int64_t n = t->n;
-    int64_t *bit = (int64_t *)calloc((size_t)n + 2, sizeof(int64_t));
-    int64_t f = 0;
-    int64_t sp = 0;
-    t->stack[sp++] = t->root;
-    t->spos[t->root] = -1; /* -1: not yet entered */
-    while (sp > 0) {
-        int32_t v = t->stack[sp - 1];
-        int32_t pv = t->parent[v];
-        int fwd = (v != t->root) && t->p0[v] == pv;
-        int rev = (v != t->root) && !fwd && t->p0[pv] == v;
-        if (t->spos[v] == -1) {
-            /* enter */
-            if (fwd) range_add(bit, n, t->in0[v], t->out0[v], t->two_m - t->vol[v]);
-            else if (rev) range_add(bit, n, t->in0[pv], t->out0[pv], t->vol[v] - t->two_m);
-            f += deg_of(t, v) * point_query(bit, t->in0[v]);
-            t->spos[v] = t->cstart[v];
-        }
-        if (t->spos[v] < t->cstart[v + 1]) {
-            int32_t c = t->clist[t->spos[v]++];
-            t->spos[c] = -1;
-            t->stack[sp++] = c;
-        } else {
-            /* exit: undo */
-            if (fwd) range_add(bit, n, t->in0[v], t->out0[v], t->vol[v] - t->two_m);
-            else if (rev) range_add(bit, n, t->in0[pv], t->out0[pv],
-                                    printed_sign ? (t->vol[v] - t->two_m) : (t->two_m - t->vol[v]));
-            sp--;
-        }
-    }
-    free(bit);
-    return f;
-}
-
 /*
  * F3 -- Theorem 3.4: f = sum over tree edges (v, p(v)) oriented like tau0 of
  * (2m - vol(Sub(tau,v))) * vol(Sub(tau,v) & Sub(tau0,v)), minus the sum over
@@ -431,7 +369,7 @@ static int64_t f_walk(tree_ctx *t) {
     return f;
 }
 
-enum { F_NAIVE = 1, F_ALG1 = 2, F_PEREDGE = 3, F_WALK = 4, F_ALG1_PRINTED = 5 };
+enum { F_NAIVE = 1, F_PEREDGE = 3, F_WALK = 4 };
 
 /*
  * f(tau) for a given rooted spanning tree.  p0/in0/out0 describe the fixed
@@ -453,8 +391,6 @@ int orc_f(int64_t n, const int64_t *off, int32_t root, const int32_t *p0, const 
     int64_t f = 0;
     switch (form) {
         case F_NAIVE: f = f_naive(&t); break;
-        case F_ALG1: f = f_alg1(&t, 0); break;
-        case F_ALG1_PRINTED: f = f_alg1(&t, 1); break;
         case F_PEREDGE: f = f_peredge(&t); break;
         case F_WALK: f = f_walk(&t); break;
         default: tree_free(&t); return ORC_INVALID;
@@ -472,20 +408,23 @@ typedef struct {
     uint64_t seed; int64_t s_begin, s_end, s0; int form; int64_t max_steps;
     int64_t *f_out; int64_t *steps_out;
     int32_t *parents_out; uint32_t *cnt_out; /* sample mode */
+    const int64_t *ids;                       /* optional list of sample ids */
     int status;
 } job_t;
 
 static void *run_job(void *arg) {
     job_t *j = (job_t *)arg;
     int64_t n = j->n;
+    /* sample ids: s_begin..s_end-1, or ids[s_begin..s_end-1] when a list is given */
     int32_t *parent = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     uint32_t *cnt = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
     uint8_t *intree = (uint8_t *)malloc((size_t)n);
     j->status = ORC_OK;
-    for (int64_t s = j->s_begin; s < j->s_end && j->status == ORC_OK; ++s) {
+    for (int64_t t = j->s_begin; t < j->s_end && j->status == ORC_OK; ++t) {
+        int64_t s = j->ids ? j->ids[t - j->s0] : t;
         int64_t steps = orc_wilson(n, j->off, j->adj, j->root, j->seed, (uint64_t)s, NULL,
                                    j->max_steps, parent, cnt, intree);
-        int64_t i = s - j->s0;
+        int64_t i = t - j->s0;
         if (steps < 0) { j->status = ORC_LIMIT; break; }
         if (j->steps_out) j->steps_out[i] = steps;
         if (j->parents_out) {
@@ -545,6 +484,19 @@ int orc_estimate(int64_t n, const int64_t *off, const int32_t *adj, int32_t root
     j.n = n; j.off = off; j.adj = adj; j.root = root; j.p0 = p0; j.in0 = in0; j.out0 = out0;
     j.seed = seed; j.form = form; j.max_steps = max_steps; j.f_out = f_out; j.steps_out = steps_out;
     return run_batch(&j, s0, count, nthreads);
+}
+
+/* Per-sample f (form F1, F3 or F4) and draw totals for the sample ids ids[0..count-1]. */
+int orc_estimate_ids(int64_t n, const int64_t *off, const int32_t *adj, int32_t root,
+                     const int32_t *p0, const int32_t *in0, const int32_t *out0, uint64_t seed,
+                     const int64_t *ids, int64_t count, int nthreads, int form, int64_t max_steps,
+                     int64_t *f_out, int64_t *steps_out) {
+    job_t j;
+    memset(&j, 0, sizeof(j));
+    j.n = n; j.off = off; j.adj = adj; j.root = root; j.p0 = p0; j.in0 = in0; j.out0 = out0;
+    j.seed = seed; j.form = form; j.max_steps = max_steps; j.f_out = f_out; j.steps_out = steps_out;
+    j.ids = ids;
+    return run_batch(&j, 0, count, nthreads);
 }
 
 /* Wilson with an explicit start order (for the order-independence pin). */

@@ -32,7 +32,7 @@ KC_MAINT_BASIC, KC_MAINT_IMPROVED = 0, 1
 EXPORTS = ("kc_graph_create", "kc_graph_destroy", "kc_graph_get_info", "kc_set_option", "kc_set_tau0",
            "kc_reserve", "kc_progress",
            "kc_samples_init", "kc_samples_query", "kc_samples_get", "kc_samples_weights", "kc_apply_updates",
-           "kc_sample_trees", "kc_estimate", "kc_evaluate_trees", "kc_status_string",
+           "kc_sample_trees", "kc_estimate", "kc_evaluate_trees", "kc_combine_results", "kc_status_string",
            "kc_last_error")
 
 
@@ -46,7 +46,8 @@ class KcError(RuntimeError):
 class _Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("two_m", ctypes.c_int64), ("root", ctypes.c_int32),
                 ("depth0", ctypes.c_int32), ("max_degree", ctypes.c_int32),
-                ("traversal", ctypes.c_int32), ("device_bytes", ctypes.c_int64), ("tau0", ctypes.c_int32)]
+                ("traversal", ctypes.c_int32), ("device_bytes", ctypes.c_int64), ("tau0", ctypes.c_int32),
+                ("sample_bytes", ctypes.c_int64)]
 
 
 class _Result(ctypes.Structure):
@@ -97,6 +98,8 @@ def library() -> ctypes.CDLL:
     lib.kc_sample_trees.argtypes = [p, u64, i64, i32, p, p, p, p]
     lib.kc_estimate.restype = ctypes.c_int
     lib.kc_estimate.argtypes = [p, u64, i64, i32, ctypes.POINTER(_Result), p, p, p]
+    lib.kc_combine_results.restype = ctypes.c_int
+    lib.kc_combine_results.argtypes = [p, ctypes.POINTER(_Result), i32, ctypes.POINTER(_Result)]
     lib.kc_evaluate_trees.restype = ctypes.c_int
     lib.kc_evaluate_trees.argtypes = [p, p, i32, p, p]
     lib.kc_status_string.restype = ctypes.c_char_p
@@ -134,6 +137,14 @@ class Estimate:
     count: int
     total_steps: int
     sampler_iterations: int
+
+
+def _result_of(est: Estimate) -> "_Result":
+    m64 = (1 << 64) - 1
+    s1 = est.sum_f & ((1 << 128) - 1)
+    hi = s1 >> 64
+    return _Result(est.kappa, est.std_error, s1 & m64, hi - (1 << 64) if hi >> 63 else hi,
+                   est.sum_f2 & m64, est.sum_f2 >> 64, est.count, est.total_steps, est.sampler_iterations)
 
 
 def _estimate_of(res: "_Result") -> Estimate:
@@ -273,6 +284,14 @@ class Graph:
         est = _estimate_of(res)
         return (est, f, stp) if per_sample else est
 
+    def combine(self, estimates) -> Estimate:
+        """One estimate over all samples of several estimates of this graph
+        (disjoint sample ranges), pooled by the library from the exact sums."""
+        parts = (_Result * len(estimates))(*[_result_of(e) for e in estimates])
+        out = _Result()
+        _check(library().kc_combine_results(self._h, parts, len(estimates), ctypes.byref(out)))
+        return _estimate_of(out)
+
     def evaluate_trees(self, parents, stream=None):
         """f for given rooted parent arrays (CUDA int32 tensor [count, n])."""
         import torch
@@ -299,8 +318,3 @@ class Graph:
 
     def __exit__(self, *exc):
         self.close()
-
-
-def kappa_interval(est: Estimate, z: float = 1.959963984540054):
-    """Normal-approximation confidence interval kappa +- z * std_error."""
-    return est.kappa - z * est.std_error, est.kappa + z * est.std_error

@@ -634,9 +634,18 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
 struct SlotPtrs {
     SamplerWS ws;
     uint64_t *word, *rec;  // rec: 2 words per vertex {vol<<32 | tin, parent}
-    int32_t *ordr, *grp, *leaves;
+    int4 *ord;             // finished vertices {v, parent, vol, 0} in completion order; the
+                           // leaves {v, parent, deg, 0} wait at the end of the same array
+    int32_t *grp;
     int64_t *fen;
 };
+
+// Vertices each lane keeps in flight in the tree numbering: the memory
+// operations of one step are issued together, so a wavefront has this many
+// times as many requests outstanding as it has lanes.  The streaming passes
+// take twice as many.
+constexpr int NB = 4;
+constexpr int NBS = 8;
 
 constexpr uint64_t PEND_ONE = 1ull << 44;
 constexpr uint64_t VOL_MASK = PEND_ONE - 1;
@@ -700,92 +709,232 @@ __device__ __forceinline__ int64_t items_at(const Items &it, uint32_t t) {
 }
 
 // Volumes and the volume-weighted preorder of the tree whose parents are in
-// rec[2v+1].  Returns false if the parents do not form a tree rooted at r.
+// rec[2v+1] (word[v] = deg(v) already).  Returns false if the parents do not
+// form a tree rooted at r.
+//
+// Bottom-up: each lane carries up to NB finished vertices; a carrier pushes
+// its vertex's volume into the parent's word with one atomic, and the last
+// child to arrive carries the parent on in the next round.  Every round's
+// finished vertices form a completion group.  Top-down: the groups in
+// reverse order (a parent always finishes in a later group than its
+// children); a vertex's interval starts after its parent's own degree and
+// the intervals of the siblings that reserved before it.
 __device__ bool tree_numbering(const GraphDev &g, const SlotPtrs &sp) {
     const int lane = threadIdx.x;
-    const int n = g.n, root = g.root;
-    // word[v] = deg(v) (volume so far) + PEND_ONE * (children not yet finished)
-    for (int v = lane; v < n; v += WAVE) astore(&sp.word[v], (uint64_t)degree(g, v));
-    fence_wg();
-    for (int v = lane; v < n; v += WAVE)
-        if (v != root) afetch_add(&sp.word[(int32_t)aload(&sp.rec[2 * (size_t)v + 1])], PEND_ONE);
-    fence_wg();
-    int nleaves = 0;
-    for (int base = 0; base < n; base += WAVE) {
-        const int v = base + lane;
-        const bool leaf = v < n && (aload(&sp.word[v]) >> 44) == 0;
-        const uint64_t m = __ballot(leaf);
-        if (leaf) astore(&sp.leaves[nleaves + rank_in(m)], v);
-        nleaves += __popcll(m);
+    const int n = g.n;
+    // one PEND_ONE per child in the parent's word
+    for (int b = 0; b < n; b += WAVE * NBS) {
+        int32_t p[NBS];
+#pragma unroll
+        for (int k = 0; k < NBS; ++k) {
+            const int v = b + k * WAVE + lane;
+            p[k] = v < n ? (int32_t)aload(&sp.rec[2 * (size_t)v + 1]) : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < NBS; ++k)
+            if (p[k] >= 0) afetch_add(&sp.word[p[k]], PEND_ONE);
     }
     fence_wg();
-    // bottom-up: a carrier finishes v (volume known) and pushes it into p(v);
-    // the last child to arrive finishes the parent in the next round.
-    int cv = -1;
-    uint64_t cval = 0;
+    // leaves {v, parent, deg}: leaf number j at ord[n - 1 - j]
+    int L = 0;
+    for (int b = 0; b < n; b += WAVE * NBS) {
+        uint64_t w[NBS];
+        int32_t p[NBS];
+#pragma unroll
+        for (int k = 0; k < NBS; ++k) {
+            const int v = b + k * WAVE + lane;
+            w[k] = v < n ? aload(&sp.word[v]) : PEND_ONE;  // past the end: not a leaf
+            p[k] = v < n ? (int32_t)aload(&sp.rec[2 * (size_t)v + 1]) : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < NBS; ++k) {
+            const bool leaf = (w[k] >> 44) == 0;
+            const uint64_t m = __ballot(leaf);
+            if (leaf)
+                sp.ord[n - 1 - (L + rank_in(m))] = make_int4(b + k * WAVE + lane, p[k], (int)(w[k] & VOL_MASK), 0);
+            L += __popcll(m);
+        }
+    }
+    fence_wg();
+    // bottom-up.  Leaves are taken from the low end of their block, ord[n-L ..]:
+    // the finished entries written at ord[0 .. nord) never reach an untaken leaf,
+    // since nord + (leaves not yet taken) <= n.
+    int cv[NB], cp[NB];
+    uint64_t cval[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) { cv[k] = -1; cp[k] = -1; cval[k] = 0; }
     int li = 0, nord = 0, ngrp = 0;
     while (true) {
-        const uint64_t freem = __ballot(cv < 0);
-        if (li < nleaves) {
-            if (cv < 0) {
-                const int k = li + rank_in(freem);
-                if (k < nleaves) {
-                    cv = aload(&sp.leaves[k]);
-                    cval = degree(g, cv);
+        if (li < L) {
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const uint64_t freem = __ballot(cv[k] < 0);
+                const int j = li + rank_in(freem);
+                if (cv[k] < 0 && j < L) {
+                    const int4 e = sp.ord[n - L + j];
+                    cv[k] = e.x;
+                    cp[k] = e.y;
+                    cval[k] = (uint64_t)(uint32_t)e.z;
                 }
+                li = min(L, li + (int)__popcll(freem));
             }
-            li = min(nleaves, li + (int)__popcll(freem));
         }
-        const uint64_t busy = __ballot(cv >= 0);
+        uint64_t busy = 0;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) busy |= __ballot(cv[k] >= 0);
         if (busy == 0ull) break;
         if (lane == 0) astore(&sp.grp[ngrp], nord);
         ngrp++;
-        if (cv >= 0) {
-            astore(&sp.ordr[nord + rank_in(busy)], cv);
-            astore(&sp.rec[2 * (size_t)cv], cval << 32);
+        uint64_t old[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const uint64_t bm = __ballot(cv[k] >= 0);
+            if (cv[k] >= 0) sp.ord[nord + rank_in(bm)] = make_int4(cv[k], cp[k], (int)cval[k], 0);
+            nord += __popcll(bm);
+            old[k] = 0;
+            if (cv[k] >= 0 && cp[k] >= 0) old[k] = afetch_add(&sp.word[cp[k]], cval[k] - PEND_ONE);
         }
-        nord += __popcll(busy);
-        if (cv >= 0) {
-            if (cv == root) {
-                cv = -1;
-            } else {
-                const int p = (int32_t)aload(&sp.rec[2 * (size_t)cv + 1]);
-                const uint64_t old = afetch_add(&sp.word[p], cval - PEND_ONE);
-                if ((old >> 44) == 1) { cv = p; cval = (old & VOL_MASK) + cval; }
-                else cv = -1;
-            }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const bool last = cv[k] >= 0 && cp[k] >= 0 && (old[k] >> 44) == 1;
+            cv[k] = last ? cp[k] : -1;
+            if (last) cval[k] = (old[k] & VOL_MASK) + cval[k];
         }
-        fence_wg();
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+            if (cv[k] >= 0) cp[k] = (int32_t)aload(&sp.rec[2 * (size_t)cv[k] + 1]);
+        if (nord > n) break;  // more entries than vertices: not a tree
     }
     if (lane == 0) astore(&sp.grp[ngrp], nord);
     fence_wg();
-    // top-down: groups in reverse completion order; a parent is always in a
-    // later group than its children.  Siblings take consecutive volume
-    // ranges after the parent's own degree, in the order they reserve them.
-    for (int gi = ngrp - 1; gi >= 0; --gi) {
-        const int a = aload(&sp.grp[gi]), b = aload(&sp.grp[gi + 1]);
-        if (lane < b - a) {
-            const int v = aload(&sp.ordr[a + lane]);
-            const uint64_t rv = aload(&sp.rec[2 * (size_t)v]);
-            const uint64_t vol = rv >> 32;
-            if (v == root) {
-                astore(&sp.rec[2 * (size_t)v], vol << 32);
-            } else {
-                const int p = (int32_t)aload(&sp.rec[2 * (size_t)v + 1]);
-                const uint64_t rp = aload(&sp.rec[2 * (size_t)p]);
-                const uint64_t volp = rp >> 32, tinp = rp & 0xFFFFFFFFull;
-                const uint64_t old = afetch_add(&sp.word[p], vol);
-                const uint64_t tin = tinp + degree(g, p) + (old - volp);
-                astore(&sp.rec[2 * (size_t)v], (vol << 32) | tin);
+    if (nord != n) return false;
+    // top-down; the group boundaries are read 64 at a time
+    for (int g0 = ngrp - 1; g0 >= 0; g0 -= WAVE) {
+        const int bnd = g0 - lane >= 0 ? aload(&sp.grp[g0 - lane]) : 0;
+        const int nb = min(WAVE, g0 + 1);
+        int hi = aload(&sp.grp[g0 + 1]);
+        for (int t = 0; t < nb; ++t) {
+            const int lo = __shfl(bnd, t);
+            for (int i0 = lo; i0 < hi; i0 += WAVE * NB) {
+                int4 e[NB];
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    const int i = i0 + k * WAVE + lane;
+                    e[k] = i < hi ? sp.ord[i] : make_int4(-1, -1, 0, 0);
+                }
+                uint64_t rp[NB], old[NB];
+                uint32_t dp[NB];
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    rp[k] = 0; old[k] = 0; dp[k] = 0;
+                    if (e[k].x >= 0 && e[k].y >= 0) {
+                        rp[k] = aload(&sp.rec[2 * (size_t)e[k].y]);
+                        old[k] = afetch_add(&sp.word[e[k].y], (uint64_t)(uint32_t)e[k].z);
+                        dp[k] = degree(g, e[k].y);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    if (e[k].x < 0) continue;
+                    const uint64_t vol = (uint32_t)e[k].z;
+                    uint64_t tin = 0;
+                    if (e[k].y >= 0) tin = (rp[k] & 0xFFFFFFFFull) + dp[k] + (old[k] - (rp[k] >> 32));
+                    astore(&sp.rec[2 * (size_t)e[k].x], (vol << 32) | tin);
+                }
             }
+            fence_wg();  // the next group reads the intervals of this one
+            hi = lo;
         }
-        fence_wg();
     }
-    return nord == n;
+    return true;
 }
 
-// f by walking each vertex's tau0 ancestors.
+// f by walking each vertex's tau0 ancestors (Theorem 3.4 as a sum over
+// vertices u of d(u) q(u): every tau0 edge x -> p0(x) on u's tau0 path adds
+// 2m - vol(x) when tau uses it in the same direction and x is a tau ancestor
+// of u, and subtracts 2m - vol(p0(x)) when tau uses it the other way and
+// p0(x) (not the root) is a tau ancestor of u).
+//
+// With the graph's ancestor table (shallow tau0: anc0[i n + u] is the
+// (i+1)-th tau0 ancestor of u, -1 past the root) every record a vertex needs
+// is loaded at once; otherwise the walk follows p0 step by step.
+
+template <int D>
+__device__ __forceinline__ int64_t q_of_table(const GraphDev &g, const SlotPtrs &sp, int u) {
+    const int root = g.root;
+    const int64_t two_m = g.two_m;
+    const size_t n = (size_t)g.n;
+    int z[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) z[i] = g.anc0[(size_t)i * n + (size_t)u];
+    uint64_t rz[D];
+    int32_t pz[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        rz[i] = 0;
+        pz[i] = -2;
+        if (z[i] >= 0 && z[i] != root) {
+            rz[i] = aload(&sp.rec[2 * (size_t)z[i]]);
+            pz[i] = (int32_t)aload(&sp.rec[2 * (size_t)z[i] + 1]);
+        }
+    }
+    const uint64_t ru = aload(&sp.rec[2 * (size_t)u]);
+    const uint32_t tu = (uint32_t)ru;
+    int x = u;
+    uint64_t rx = ru;
+    int32_t px = (int32_t)aload(&sp.rec[2 * (size_t)u + 1]);
+    int64_t q = 0;
+    bool go = u != root;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        if (go && z[i] >= 0) {
+            if (px == z[i]) {
+                const uint32_t t = (uint32_t)rx, vol = (uint32_t)(rx >> 32);
+                if (t <= tu && tu < t + vol) q += two_m - (int64_t)vol;
+            }
+            if (z[i] == root) {
+                go = false;
+            } else {
+                if (pz[i] == x) {
+                    const uint32_t t = (uint32_t)rz[i], vol = (uint32_t)(rz[i] >> 32);
+                    if (t <= tu && tu < t + vol) q -= two_m - (int64_t)vol;
+                }
+                x = z[i];
+                rx = rz[i];
+                px = pz[i];
+            }
+        }
+    }
+    return q;
+}
+
+// U vertices per lane and step (their loads in flight together); the deeper
+// table takes one, to keep the kernel's register count at its occupancy (a
+// table of more than 8 levels would not fit it, so deeper trees follow p0).
+template <int D, int U>
+__device__ int64_t f_walk_table(const GraphDev &g, const SlotPtrs &sp) {
+    const int lane = threadIdx.x;
+    const int n = g.n;
+    int64_t acc = 0;
+    for (int b = 0; b < n; b += U * WAVE) {
+        int64_t q[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int u = b + k * WAVE + lane;
+            q[k] = u < n ? q_of_table<D>(g, sp, u) : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int u = b + k * WAVE + lane;
+            if (u < n) acc += (int64_t)degree(g, u) * q[k];
+        }
+    }
+    return wave_sum(acc);
+}
+
 __device__ int64_t f_walk(const GraphDev &g, const SlotPtrs &sp) {
+    if (g.anc0 && g.anc_depth <= 4) return f_walk_table<4, 2>(g, sp);
+    if (g.anc0 && g.anc_depth <= 8) return f_walk_table<8, 1>(g, sp);
     const int lane = threadIdx.x;
     const int n = g.n, root = g.root;
     const int64_t two_m = g.two_m;
@@ -1047,11 +1196,11 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
     sp.ws.rq = sd.rq + (size_t)blockIdx.x * n;
     sp.ws.queue = sd.queue + (size_t)blockIdx.x * (size_t)sd.chains;
     sp.ws.start = sd.cstart + (size_t)blockIdx.x * (size_t)sd.chains;
-    sp.word = sd.word ? sd.word + (size_t)blockIdx.x * n : nullptr;
+    // the numbering's word array reuses the sampler's tag words (dead once the tree is drawn)
+    sp.word = sd.rec ? sp.ws.tagw : nullptr;
     sp.rec = sd.rec ? reinterpret_cast<uint64_t *>(sd.rec) + 2 * (size_t)blockIdx.x * n : nullptr;
-    sp.ordr = sd.ordr ? sd.ordr + (size_t)blockIdx.x * n : nullptr;
+    sp.ord = sd.ord ? sd.ord + (size_t)blockIdx.x * n : nullptr;
     sp.grp = sd.grp ? sd.grp + (size_t)blockIdx.x * (n + 1) : nullptr;
-    sp.leaves = sd.leaves ? sd.leaves + (size_t)blockIdx.x * n : nullptr;
     sp.fen = sd.fen ? sd.fen + (size_t)blockIdx.x * (size_t)sd.fen_len : nullptr;
     int64_t done = 0;
 
@@ -1077,19 +1226,27 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
                 if (co) co[v] = (uint32_t)(ar >> 32);
             }
         } else {
-            // parents into rec[2v+1]
+            // parents into rec[2v+1]; the numbering's volume words start at deg(v)
             const size_t row = rp.rows ? (size_t)rp.rows[idx] : (size_t)idx;
             bool bad = false;
-            for (int v = lane; v < g.n; v += WAVE) {
-                int32_t p;
-                if (v == g.root) {
-                    p = -1;
-                } else {
-                    p = (rp.mode != RUN_ESTIMATE) ? rp.parents_in[row * n + v]
-                                                  : (int32_t)(uint32_t)aload(&sp.ws.arrow[v]);
-                    if (p < 0 || p >= g.n || p == v) { bad = true; p = g.root; }
+            for (int b = 0; b < g.n; b += WAVE * NBS) {
+                int32_t p[NBS];
+#pragma unroll
+                for (int k = 0; k < NBS; ++k) {
+                    const int v = b + k * WAVE + lane;
+                    p[k] = -1;
+                    if (v < g.n && v != g.root)
+                        p[k] = (rp.mode != RUN_ESTIMATE) ? rp.parents_in[row * n + v]
+                                                         : (int32_t)(uint32_t)aload(&sp.ws.arrow[v]);
                 }
-                astore(&sp.rec[2 * (size_t)v + 1], (uint64_t)(uint32_t)p);
+#pragma unroll
+                for (int k = 0; k < NBS; ++k) {
+                    const int v = b + k * WAVE + lane;
+                    if (v >= g.n) continue;
+                    if (v != g.root && (p[k] < 0 || p[k] >= g.n || p[k] == v)) { bad = true; p[k] = g.root; }
+                    astore(&sp.rec[2 * (size_t)v + 1], (uint64_t)(uint32_t)p[k]);
+                    astore(&sp.word[v], (uint64_t)degree(g, v));
+                }
             }
             fence_wg();
             bool ok = tree_numbering(g, sp);

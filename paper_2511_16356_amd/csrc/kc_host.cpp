@@ -14,16 +14,16 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
-#include "../../include/kc.h"
-#include "kc_internal.h"
+#include "kc_host.h"
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-kc_status fail(kc_status st, const char *fmt, ...) {
+kc_status kc_host::fail(kc_status st, const char *fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -33,13 +33,9 @@ kc_status fail(kc_status st, const char *fmt, ...) {
     return st;
 }
 
-#define HIP_TRY(expr)                                                                          \
-    do {                                                                                       \
-        hipError_t e_ = (expr);                                                                \
-        if (e_ != hipSuccess)                                                                  \
-            return fail(e_ == hipErrorOutOfMemory ? KC_ERR_NOMEM : KC_ERR_DEVICE, "%s: %s", #expr, \
-                        hipGetErrorString(e_));                                                \
-    } while (0)
+using namespace kc_host;
+
+namespace {
 
 void dev_free(void *p) {
     if (p) (void)hipFree(p);
@@ -64,79 +60,39 @@ struct DevTmp {
     hipError_t alloc(size_t count) { return dev_alloc(&p, count); }
 };
 
+// Runs body(lo, hi) over [0, n) in contiguous chunks on up to 16 host threads
+// and returns the smallest index any chunk reported (body returns its first
+// failing index, or -1), so errors are reported as a serial scan would.
+template <typename F>
+int64_t parallel_first(int64_t n, F body) {
+    unsigned nt = std::thread::hardware_concurrency();
+    nt = std::max(1u, std::min(nt, 16u));
+    if (n < (1 << 16)) nt = 1;
+    std::vector<int64_t> first(nt, -1);
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t) {
+        const int64_t lo = n * t / nt, hi = n * (t + 1) / nt;
+        if (nt == 1) first[t] = body(lo, hi);
+        else th.emplace_back([&, t, lo, hi] { first[t] = body(lo, hi); });
+    }
+    for (auto &x : th) x.join();
+    for (int64_t f : first)
+        if (f >= 0) return f;
+    return -1;
+}
+
 }  // namespace
-
-struct PreparedGraph {
-    int32_t root = -1, depth0 = 0, nblk = 0;
-    std::vector<int32_t> order, p0, pre0, out0, eoff, elist, vrec;
-};
-
-struct kc_graph {
-    int64_t n = 0, two_m = 0;
-    int32_t root = -1, depth0 = 0, max_degree = 0;
-    int32_t traversal = KC_TRAV_WALK;
-    int32_t walkers = 64;
-    int32_t chains = 1024;
-    int32_t slots_opt = 0;
-    int32_t trav_opt = KC_TRAV_AUTO;
-    int64_t step_limit = 0;
-    int64_t mem_budget = 0;
-    int64_t graph_bytes = 0;
-    int32_t nblk = 0;
-    int32_t start_order = 2;
-    int32_t tau0_kind = KC_TAU0_BFS;  // rule that builds tau0 on every (re)build
-    std::vector<int32_t> h_tau0;     // the caller's tau0 when tau0_kind == KC_TAU0_GIVEN
-    std::vector<int32_t> bfs_order;  // host copy of the BFS order from the root
-    std::vector<int64_t> h_off;      // host copy of the current CSR
-    std::vector<int32_t> h_adj;
-    // resident sample set (kc_samples_init / kc_apply_updates)
-    int32_t res_count = 0;
-    uint64_t res_seed = 0;
-    int64_t res_next = 0;             // next unused sample index
-    int64_t res_serial = 0;           // basic: insertions applied so far; improved: single-edge
-                                      // updates applied so far (the counter of their draws)
-    int32_t maint = KC_MAINT_BASIC;   // sample maintenance of the resident set
-    std::vector<double> res_w;        // improved maintenance: weight of each tree (sum 1)
-    bool res_f_stale = false;         // the graph changed since d_res_f was computed
-    std::vector<int64_t> res_ids;     // sample index of each resident tree
-    int32_t *d_res_par = nullptr;     // [res_count * n] parents
-    int64_t *d_res_f = nullptr;       // [res_count] f of each tree on the current graph
-    // graph arrays on the device
-    int64_t *d_off = nullptr;
-    int32_t *d_adj = nullptr, *d_p0 = nullptr, *d_order = nullptr, *d_pre0 = nullptr;
-    int32_t *d_out0 = nullptr, *d_eoff = nullptr, *d_elist = nullptr;
-    int4 *d_vrec = nullptr;
-    // workspace
-    int ws_slots = 0;
-    bool ws_trav = false, ws_fen = false;
-    int64_t ws_fen_len = 0;  // per-slot Fenwick length the buffer was sized for (2m + 2)
-    uint64_t *d_tagw = nullptr, *d_arrow = nullptr;
-    int32_t *d_rq = nullptr;
-    int4 *d_queue = nullptr;
-    int32_t *d_cstart = nullptr;
-    uint64_t *d_word = nullptr;
-    int4 *d_rec = nullptr;
-    int32_t *d_ordr = nullptr, *d_grp = nullptr, *d_leaves = nullptr;
-    int64_t *d_fen = nullptr;
-    int64_t *d_f = nullptr, *d_steps = nullptr, *d_iters = nullptr;  // internal per-sample buffers
-    int64_t fbuf_len = 0;
-    int32_t *d_ctl = nullptr;
-    int64_t *h_progress = nullptr;  // pinned host array, one counter per slot
-    int64_t *d_progress = nullptr;  // its device view
-    int progress_len = 0;
-    kc::ReduceOut *d_red = nullptr;
-};
 
 namespace {
 
 void free_workspace(kc_graph *g) {
     dev_free(g->d_tagw); dev_free(g->d_arrow); dev_free(g->d_rq);
-    dev_free(g->d_queue); dev_free(g->d_cstart); dev_free(g->d_word); dev_free(g->d_rec); dev_free(g->d_ordr);
-    dev_free(g->d_grp); dev_free(g->d_leaves); dev_free(g->d_fen);
+    dev_free(g->d_queue); dev_free(g->d_cstart); dev_free(g->d_rec); dev_free(g->d_ord);
+    dev_free(g->d_grp); dev_free(g->d_fen);
     g->d_tagw = g->d_arrow = nullptr; g->d_rq = nullptr; g->d_queue = nullptr;
     g->d_cstart = nullptr;
-    g->d_word = nullptr; g->d_rec = nullptr;
-    g->d_ordr = g->d_grp = g->d_leaves = nullptr; g->d_fen = nullptr;
+    g->d_rec = nullptr; g->d_ord = nullptr;
+    g->d_grp = nullptr; g->d_fen = nullptr;
     g->ws_slots = 0; g->ws_trav = g->ws_fen = false;
 }
 
@@ -145,8 +101,8 @@ void free_graph_arrays(kc_graph *g);
 void free_all(kc_graph *g) {
     free_workspace(g);
     free_graph_arrays(g);
-    dev_free(g->d_res_par); dev_free(g->d_res_f);
-    g->d_res_par = nullptr; g->d_res_f = nullptr; g->res_count = 0;
+    dev_free(g->d_res_par); dev_free(g->d_res_f); dev_free(g->d_res_f_alt);
+    g->d_res_par = nullptr; g->d_res_f = nullptr; g->d_res_f_alt = nullptr; g->res_count = 0;
     dev_free(g->d_f); dev_free(g->d_steps); dev_free(g->d_iters); dev_free(g->d_ctl); dev_free(g->d_red);
     if (g->h_progress) (void)hipHostFree(g->h_progress);
     g->h_progress = nullptr;
@@ -175,12 +131,16 @@ std::vector<int32_t> start_order_of(const std::vector<int32_t> &bfs, int kind) {
     return ord;
 }
 
-int64_t slot_bytes(const kc_graph *g, bool trav, bool fen) {
+}  // namespace
+
+int64_t kc_host::slot_bytes(const kc_graph *g, bool trav, bool fen) {
     int64_t b = 20 * g->n + 20 * (int64_t)kc::sampler_chains();  // state records, restart ring, tasks
-    if (trav) b += 8 * g->n + 16 * g->n + 4 * g->n + 4 * (g->n + 1) + 4 * g->n;
+    if (trav) b += 16 * g->n + 16 * g->n + 4 * (g->n + 1);  // rec, ord, grp (word reuses tagw)
     if (fen) b += 8 * (g->two_m + 2);
     return b;
 }
+
+namespace {
 
 // Make sure at least `want` slots of workspace exist; returns the usable count.
 kc_status ensure_workspace(kc_graph *g, int want, bool trav, bool fen, hipStream_t stream, int *got) {
@@ -210,11 +170,9 @@ kc_status ensure_workspace(kc_graph *g, int want, bool trav, bool fen, hipStream
     HIP_TRY(dev_alloc(&g->d_queue, (size_t)slots * (size_t)kc::sampler_chains()));
     HIP_TRY(dev_alloc(&g->d_cstart, (size_t)slots * (size_t)kc::sampler_chains()));
     if (trav) {
-        HIP_TRY(dev_alloc(&g->d_word, (size_t)slots * n));
         HIP_TRY(dev_alloc(&g->d_rec, (size_t)slots * n));
-        HIP_TRY(dev_alloc(&g->d_ordr, (size_t)slots * n));
+        HIP_TRY(dev_alloc(&g->d_ord, (size_t)slots * n));
         HIP_TRY(dev_alloc(&g->d_grp, (size_t)slots * (n + 1)));
-        HIP_TRY(dev_alloc(&g->d_leaves, (size_t)slots * n));
     }
     if (fen) {
         const int64_t len = (int64_t)slots * (g->two_m + 2);
@@ -243,8 +201,10 @@ kc_status ensure_fbuf(kc_graph *g, int64_t count) {
     return KC_OK;
 }
 
+}  // namespace
+
 // One slot per resident single-wave workgroup of the persistent kernel.
-int default_slots(const kc_graph *g) {
+int kc_host::default_slots(const kc_graph *g) {
     (void)g;
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1024;
@@ -254,15 +214,12 @@ int default_slots(const kc_graph *g) {
     return cus * per_cu;
 }
 
-// Launch the persistent kernel over `count` samples and check its status.
-kc_status run_persistent(kc_graph *g, kc::RunParams rp, hipStream_t stream) {
-    const bool trav = rp.mode != kc::RUN_SAMPLE;
-    const bool fen = trav && g->traversal == KC_TRAV_SWEEP;
-    int want = g->slots_opt > 0 ? g->slots_opt : default_slots(g);
-    want = std::min(want, rp.count);
-    int slots = 0;
-    kc_status st = ensure_workspace(g, want, trav, fen, stream, &slots);
-    if (st != KC_OK) return st;
+namespace {
+
+}  // namespace
+
+// The graph's device arrays as the kernels see them.
+kc::GraphDev kc_host::graph_dev(const kc_graph *g) {
     kc::GraphDev gd;
     gd.n = (int32_t)g->n;
     gd.root = g->root;
@@ -276,39 +233,33 @@ kc_status run_persistent(kc_graph *g, kc::RunParams rp, hipStream_t stream) {
     gd.eoff = g->d_eoff;
     gd.elist = g->d_elist;
     gd.vrec = g->d_vrec;
-    kc::SlotDev sd;
-    sd.tagw = g->d_tagw;
-    sd.arrow = g->d_arrow;
-    sd.rq = g->d_rq;
-    sd.queue = g->d_queue;
-    sd.cstart = g->d_cstart;
-    sd.chains = kc::sampler_chains();
-    sd.word = g->d_word;
-    sd.rec = g->d_rec;
-    sd.ordr = g->d_ordr;
-    sd.grp = g->d_grp;
-    sd.leaves = g->d_leaves;
-    sd.fen = fen ? g->d_fen : nullptr;
-    sd.fen_len = fen ? g->two_m + 2 : 0;
+    gd.anc0 = g->d_anc0;
+    gd.anc_depth = g->anc_depth;
+    return gd;
+}
+
+namespace {
+
+}  // namespace
+
+// The options of g that every launch carries.
+void kc_host::fill_run_options(const kc_graph *g, kc::RunParams &rp) {
     rp.walkers = g->walkers;
     rp.traversal = g->traversal;
     rp.iter_cap = g->step_limit > 0 ? g->step_limit : 1024 * g->n + (1 << 22);
     rp.ctl = g->d_ctl;
-    if (g->progress_len < slots) {
-        if (g->h_progress) (void)hipHostFree(g->h_progress);
-        g->h_progress = nullptr;
-        g->d_progress = nullptr;
-        g->progress_len = 0;
-        HIP_TRY(hipHostMalloc((void **)&g->h_progress, sizeof(int64_t) * (size_t)slots,
-                              hipHostMallocMapped | hipHostMallocCoherent));
-        HIP_TRY(hipHostGetDevicePointer((void **)&g->d_progress, g->h_progress, 0));
-        g->progress_len = slots;
-    }
-    HIP_TRY(hipStreamSynchronize(stream));  // no earlier launch still writes the counters
-    for (int i = 0; i < g->progress_len; ++i) __atomic_store_n(&g->h_progress[i], (int64_t)0, __ATOMIC_RELAXED);
-    rp.progress = g->d_progress;
+}
+
+namespace {
+
+}  // namespace
+
+// Launch the persistent kernel on a prepared workspace and check the status
+// its workgroups report.
+kc_status kc_host::launch_checked(kc_graph *g, const kc::SlotDev &sd, const kc::RunParams &rp, int slots,
+                         hipStream_t stream) {
     HIP_TRY(kc::launch_reset_ctl(g->d_ctl, stream));
-    HIP_TRY(kc::launch_persistent(gd, sd, rp, g->chains, slots, stream));
+    HIP_TRY(kc::launch_persistent(graph_dev(g), sd, rp, g->chains, slots, stream));
     int32_t ctl[4] = {0, 0, 0, 0};
     HIP_TRY(hipMemcpyAsync(ctl, g->d_ctl, sizeof(ctl), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
@@ -323,6 +274,47 @@ kc_status run_persistent(kc_graph *g, kc::RunParams rp, hipStream_t stream) {
                     (long long)(rp.first + ctl[2]));
     }
     return KC_OK;
+}
+
+namespace {
+
+// Launch the persistent kernel over `count` samples on the graph's own
+// workspace (allocated or grown here) and check its status.
+kc_status run_persistent(kc_graph *g, kc::RunParams rp, hipStream_t stream) {
+    const bool trav = rp.mode != kc::RUN_SAMPLE;
+    const bool fen = trav && g->traversal == KC_TRAV_SWEEP;
+    int want = g->slots_opt > 0 ? g->slots_opt : default_slots(g);
+    want = std::min(want, rp.count);
+    int slots = 0;
+    kc_status st = ensure_workspace(g, want, trav, fen, stream, &slots);
+    if (st != KC_OK) return st;
+    kc::SlotDev sd;
+    sd.tagw = g->d_tagw;
+    sd.arrow = g->d_arrow;
+    sd.rq = g->d_rq;
+    sd.queue = g->d_queue;
+    sd.cstart = g->d_cstart;
+    sd.chains = kc::sampler_chains();
+    sd.rec = trav ? g->d_rec : nullptr;
+    sd.ord = trav ? g->d_ord : nullptr;
+    sd.grp = trav ? g->d_grp : nullptr;
+    sd.fen = fen ? g->d_fen : nullptr;
+    sd.fen_len = fen ? g->two_m + 2 : 0;
+    fill_run_options(g, rp);
+    if (g->progress_len < slots) {
+        if (g->h_progress) (void)hipHostFree(g->h_progress);
+        g->h_progress = nullptr;
+        g->d_progress = nullptr;
+        g->progress_len = 0;
+        HIP_TRY(hipHostMalloc((void **)&g->h_progress, sizeof(int64_t) * (size_t)slots,
+                              hipHostMallocMapped | hipHostMallocCoherent));
+        HIP_TRY(hipHostGetDevicePointer((void **)&g->d_progress, g->h_progress, 0));
+        g->progress_len = slots;
+    }
+    HIP_TRY(hipStreamSynchronize(stream));  // no earlier launch still writes the counters
+    for (int i = 0; i < g->progress_len; ++i) __atomic_store_n(&g->h_progress[i], (int64_t)0, __ATOMIC_RELAXED);
+    rp.progress = g->d_progress;
+    return launch_checked(g, sd, rp, slots, stream);
 }
 
 // Philox4x32-10 (Salmon et al., SC'11) on the host: ten rounds of two 32x32
@@ -537,6 +529,21 @@ kc_status prepare_graph(const std::vector<int64_t> &off, const std::vector<int32
             if (in0[(size_t)x] < be * 64) elist[(size_t)fill[(size_t)be]++] = (int32_t)x;
         }
     }
+    // shallow tau0 (depth <= 8): every vertex's tau0 ancestors, level-major and padded to 4 or
+    // 8 levels with -1 past the root, so the per-tree walk loads them without following p0
+    pg->anc_depth = depth0 <= 4 ? 4 : depth0 <= 8 ? 8 : 0;
+    pg->anc0.clear();
+    if (pg->anc_depth > 0) {
+        const int32_t D = pg->anc_depth;
+        pg->anc0.assign((size_t)D * (size_t)n, -1);
+        for (int64_t v = 0; v < n; ++v) {
+            int32_t x = (int32_t)v;
+            for (int32_t i = 0; i < D && x != root; ++i) {
+                x = p0[(size_t)x];
+                pg->anc0[(size_t)i * (size_t)n + (size_t)v] = x;
+            }
+        }
+    }
     // per-vertex graph record for the sampler: offset, degree, first six neighbours
     std::vector<int32_t> &vrec = pg->vrec;
     vrec.assign((size_t)n * 8, -1);
@@ -552,6 +559,9 @@ kc_status prepare_graph(const std::vector<int64_t> &off, const std::vector<int32
 
 void free_graph_arrays(kc_graph *g) {
     dev_free(g->d_vrec);
+    dev_free(g->d_anc0);
+    g->d_anc0 = nullptr;
+    g->anc_depth = 0;
     dev_free(g->d_off); dev_free(g->d_adj); dev_free(g->d_p0); dev_free(g->d_order);
     dev_free(g->d_pre0); dev_free(g->d_out0); dev_free(g->d_eoff); dev_free(g->d_elist);
     g->d_vrec = nullptr;
@@ -595,12 +605,16 @@ kc_status rebuild_graph(kc_graph *g, int32_t root, hipStream_t stream) {
     if (e == hipSuccess) e = up(&g->d_eoff, pg.eoff.data(), pg.eoff.size());
     if (e == hipSuccess) e = up(&g->d_elist, pg.elist.data(), pg.elist.size());
     if (e == hipSuccess) e = up(&g->d_vrec, reinterpret_cast<const int4 *>(pg.vrec.data()), (size_t)n * 2);
+    if (e == hipSuccess && pg.anc_depth > 0) e = up(&g->d_anc0, pg.anc0.data(), pg.anc0.size());
+    g->anc_depth = pg.anc_depth;
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess)
         return fail(e == hipErrorOutOfMemory ? KC_ERR_NOMEM : KC_ERR_DEVICE, "upload failed: %s",
                     hipGetErrorString(e));
     return KC_OK;
 }
+
+kc_status refresh_resident_f(kc_graph *g, hipStream_t stream);
 
 }  // namespace
 
@@ -644,9 +658,20 @@ kc_status kc_graph_create(int64_t n, const void *offsets, int offsets_are_i64, c
     const int64_t nnz = off[(size_t)n];
     if (nnz >= (1ll << 31)) return fail(KC_ERR_OVERFLOW, "2m=%lld does not fit 31-bit volumes", (long long)nnz);
     int32_t maxdeg = 0;
-    for (int64_t v = 0; v < n; ++v) {
-        const int64_t a = off[(size_t)v], b = off[(size_t)v + 1];
-        maxdeg = (int32_t)std::max<int64_t>(maxdeg, b - a);
+    for (int64_t v = 0; v < n; ++v) maxdeg = (int32_t)std::max<int64_t>(maxdeg, off[(size_t)v + 1] - off[(size_t)v]);
+    // rows: neighbours in range, no self-loop, strictly ascending (the first bad row is reported)
+    const int64_t bad_row = parallel_first(n, [&](int64_t lo, int64_t hi) -> int64_t {
+        for (int64_t v = lo; v < hi; ++v) {
+            const int64_t a = off[(size_t)v], b = off[(size_t)v + 1];
+            for (int64_t e = a; e < b; ++e) {
+                const int32_t u = indices[e];
+                if (u < 0 || u >= n || u == v || (e > a && indices[e - 1] >= u)) return v;
+            }
+        }
+        return -1;
+    });
+    if (bad_row >= 0) {
+        const int64_t v = bad_row, a = off[(size_t)v], b = off[(size_t)v + 1];
         for (int64_t e = a; e < b; ++e) {
             const int32_t u = indices[e];
             if (u < 0 || u >= n) return fail(KC_ERR_INVALID, "neighbour %d of %lld out of range", u, (long long)v);
@@ -656,11 +681,20 @@ kc_status kc_graph_create(int64_t n, const void *offsets, int offsets_are_i64, c
         }
     }
     if (maxdeg >= (1 << 20)) return fail(KC_ERR_UNSUPPORTED, "max degree %d >= 2^20", maxdeg);
-    for (int64_t v = 0; v < n; ++v) {
-        for (int64_t e = off[(size_t)v]; e < off[(size_t)v + 1]; ++e) {
+    // every entry has its reverse entry (undirected); rows are valid at this point
+    const int64_t no_rev = parallel_first(n, [&](int64_t lo, int64_t hi) -> int64_t {
+        for (int64_t v = lo; v < hi; ++v)
+            for (int64_t e = off[(size_t)v]; e < off[(size_t)v + 1]; ++e) {
+                const int32_t u = indices[e];
+                if (!std::binary_search(indices + off[(size_t)u], indices + off[(size_t)u + 1], (int32_t)v)) return v;
+            }
+        return -1;
+    });
+    if (no_rev >= 0) {
+        for (int64_t e = off[(size_t)no_rev]; e < off[(size_t)no_rev + 1]; ++e) {
             const int32_t u = indices[e];
-            if (!std::binary_search(indices + off[(size_t)u], indices + off[(size_t)u + 1], (int32_t)v))
-                return fail(KC_ERR_INVALID, "edge (%lld,%d) has no reverse entry", (long long)v, u);
+            if (!std::binary_search(indices + off[(size_t)u], indices + off[(size_t)u + 1], (int32_t)no_rev))
+                return fail(KC_ERR_INVALID, "edge (%lld,%d) has no reverse entry", (long long)no_rev, u);
         }
     }
     kc_graph *g = new (std::nothrow) kc_graph();
@@ -702,6 +736,7 @@ kc_status kc_graph_get_info(const kc_graph *g, kc_graph_info *info) {
     info->traversal = g->traversal;
     info->device_bytes = g->graph_bytes;
     info->tau0 = g->tau0_kind;
+    info->sample_bytes = slot_bytes(g, true, g->traversal == KC_TRAV_SWEEP);
     return KC_OK;
 }
 
@@ -725,15 +760,18 @@ kc_status kc_set_tau0(kc_graph *g, int kind, const int32_t *parent, void *hip_st
     g->h_tau0.swap(given);
     kc_status st = rebuild_graph(g, g->root, stream);
     // resident trees are unchanged; their f is taken over the new tau0 (Theorem 3.4)
-    if (st == KC_OK && g->res_count > 0)
-        st = kc_evaluate_trees(g, g->d_res_par, g->res_count, g->d_res_f, hip_stream);
+    const bool was_stale = g->res_f_stale;
+    if (st == KC_OK && g->res_count > 0) {
+        g->res_f_stale = true;
+        st = refresh_resident_f(g, stream);
+    }
     if (st != KC_OK) {
-        // put back the previous tau0 and the f values taken over it
+        // put back the previous tau0; the f values taken over it are untouched
         const std::string err = g_last_error;
         g->tau0_kind = old_kind;
         g->h_tau0.swap(old_tau0);
-        if (rebuild_graph(g, g->root, stream) == KC_OK && g->res_count > 0)
-            (void)kc_evaluate_trees(g, g->d_res_par, g->res_count, g->d_res_f, hip_stream);
+        (void)rebuild_graph(g, g->root, stream);
+        g->res_f_stale = was_stale;
         g_last_error = err;
         return st;
     }
@@ -833,14 +871,31 @@ kc_status kc_sample_trees(kc_graph *g, uint64_t seed, int64_t first_sample, int3
     return run_persistent(g, rp, (hipStream_t)hip_stream);
 }
 
-static kc_status finish_reduce(kc_graph *g, int32_t count, const int64_t *f, const int64_t *steps,
+// kappa and its standard error from the exact sums of a result (Theorem 3.3):
+// kappa = sum f / (2 m count), one correctly rounded conversion and one
+// division; std_error = the sample standard deviation of f / 2m over sqrt(count).
+static void finish_result(int64_t two_m, kc_result *res) {
+    const __int128 s1 = (__int128)(((unsigned __int128)(uint64_t)res->sum_f_hi << 64) | res->sum_f_lo);
+    const unsigned __int128 s2 = ((unsigned __int128)res->sum_f2_hi << 64) | res->sum_f2_lo;
+    const int64_t count = res->count;
+    res->kappa = (double)s1 / (double)(two_m * count);
+    if (count > 1) {
+        const double mean = (double)s1 / (double)count;
+        const double var = ((double)s2 - (double)count * mean * mean) / (double)(count - 1);
+        res->std_error = std::sqrt(std::max(var, 0.0) / (double)count) / (double)two_m;
+    } else {
+        res->std_error = std::nan("");
+    }
+}
+
+}  // extern "C"
+
+kc_status kc_host::finish_reduce(kc_graph *g, int32_t count, const int64_t *f, const int64_t *steps,
                                const int64_t *iters, kc_result *res, hipStream_t stream) {
     HIP_TRY(kc::launch_reduce(f, steps, iters, count, g->d_red, stream));
     kc::ReduceOut ro;
     HIP_TRY(hipMemcpyAsync(&ro, g->d_red, sizeof(ro), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    const __int128 s1 = (__int128)(((unsigned __int128)(uint64_t)ro.sum_hi << 64) | ro.sum_lo);
-    const unsigned __int128 s2 = ((unsigned __int128)ro.sq_hi << 64) | ro.sq_lo;
     res->sum_f_lo = ro.sum_lo;
     res->sum_f_hi = ro.sum_hi;
     res->sum_f2_lo = ro.sq_lo;
@@ -848,15 +903,33 @@ static kc_status finish_reduce(kc_graph *g, int32_t count, const int64_t *f, con
     res->count = count;
     res->total_steps = ro.steps;
     res->sampler_iterations = ro.iters;
-    // kappa = sum f / (2 m count): one correctly rounded conversion, one division
-    res->kappa = (double)s1 / (double)(g->two_m * (int64_t)count);
-    if (count > 1) {
-        const double mean = (double)s1 / (double)count;
-        const double var = ((double)s2 - (double)count * mean * mean) / (double)(count - 1);
-        res->std_error = std::sqrt(std::max(var, 0.0) / (double)count) / (double)g->two_m;
-    } else {
-        res->std_error = std::nan("");
+    finish_result(g->two_m, res);
+    return KC_OK;
+}
+
+extern "C" {
+
+kc_status kc_combine_results(const kc_graph *g, const kc_result *parts, int32_t k, kc_result *out) {
+    g_last_error.clear();
+    if (!g || !parts || !out) return fail(KC_ERR_INVALID, "NULL argument");
+    if (k < 1) return fail(KC_ERR_INVALID, "need at least one result");
+    unsigned __int128 s1 = 0, s2 = 0;
+    kc_result r{};
+    for (int32_t i = 0; i < k; ++i) {
+        const kc_result &p = parts[i];
+        if (p.count < 1) return fail(KC_ERR_INVALID, "result %d has no samples", i);
+        s1 += ((unsigned __int128)(uint64_t)p.sum_f_hi << 64) | p.sum_f_lo;
+        s2 += ((unsigned __int128)p.sum_f2_hi << 64) | p.sum_f2_lo;
+        r.count += p.count;
+        r.total_steps += p.total_steps;
+        r.sampler_iterations += p.sampler_iterations;
     }
+    r.sum_f_lo = (uint64_t)s1;
+    r.sum_f_hi = (int64_t)(uint64_t)(s1 >> 64);
+    r.sum_f2_lo = (uint64_t)s2;
+    r.sum_f2_hi = (uint64_t)(s2 >> 64);
+    finish_result(g->two_m, &r);
+    *out = r;
     return KC_OK;
 }
 
@@ -911,8 +984,12 @@ kc_status kc_samples_init(kc_graph *g, uint64_t seed, int32_t count, void *hip_s
     g->d_res_f = nullptr;
     g->res_count = 0;
     g->res_ids.clear();
+    dev_free(g->d_res_f_alt);
+    g->d_res_f_alt = nullptr;
+    g->res_f_stale = false;
     HIP_TRY(dev_alloc(&g->d_res_par, (size_t)count * (size_t)g->n));
     HIP_TRY(dev_alloc(&g->d_res_f, (size_t)count));
+    HIP_TRY(dev_alloc(&g->d_res_f_alt, (size_t)count));
     kc_status st = kc_sample_trees(g, seed, 0, count, g->d_res_par, nullptr, nullptr, hip_stream);
     if (st != KC_OK) return st;
     st = kc_evaluate_trees(g, g->d_res_par, count, g->d_res_f, hip_stream);
@@ -933,7 +1010,10 @@ kc_status kc_samples_query(kc_graph *g, kc_result *result, void *hip_stream) {
     if (!g || !result) return fail(KC_ERR_INVALID, "NULL graph or result");
     if (g->res_count < 1) return fail(KC_ERR_INVALID, "no resident samples (call kc_samples_init)");
     hipStream_t stream = (hipStream_t)hip_stream;
-    const kc_status st = finish_reduce(g, g->res_count, g->d_res_f, nullptr, nullptr, result, stream);
+    // f from before the last update is never reduced: a failed recomputation is retried here
+    kc_status st = refresh_resident_f(g, stream);
+    if (st != KC_OK) return st;
+    st = finish_reduce(g, g->res_count, g->d_res_f, nullptr, nullptr, result, stream);
     if (st != KC_OK || g->maint != KC_MAINT_IMPROVED) return st;
     // Algorithm 3: kappa = sum_t w_t f_t / 2m, weights summing to one, in slot order
     std::vector<int64_t> f((size_t)g->res_count);
@@ -961,11 +1041,15 @@ kc_status kc_samples_weights(const kc_graph *g, double *w_out) {
     return KC_OK;
 }
 
-kc_status kc_samples_get(const kc_graph *g, int32_t *parents_out, int64_t *f_out, int64_t *ids_out,
+kc_status kc_samples_get(kc_graph *g, int32_t *parents_out, int64_t *f_out, int64_t *ids_out,
                          void *hip_stream) {
     g_last_error.clear();
     if (!g) return fail(KC_ERR_INVALID, "NULL graph");
     hipStream_t stream = (hipStream_t)hip_stream;
+    if (f_out) {
+        const kc_status st = refresh_resident_f(g, stream);
+        if (st != KC_OK) return st;
+    }
     const size_t c = (size_t)g->res_count;
     if (parents_out && c)
         HIP_TRY(hipMemcpyAsync(parents_out, g->d_res_par, c * (size_t)g->n * sizeof(int32_t),
@@ -1496,12 +1580,11 @@ kc_status kc_apply_updates(kc_graph *g, const int32_t *u, const int32_t *v, cons
     // so it is computed once per call), also when a later update failed
     if (g->res_f_stale && g->res_count > 0) {
         const std::string err = g_last_error;
-        const kc_status st2 = kc_evaluate_trees(g, g->d_res_par, g->res_count, g->d_res_f, hip_stream);
+        const kc_status st2 = refresh_resident_f(g, stream);
         if (st2 == KC_OK) {
-            g->res_f_stale = false;
             if (st != KC_OK) g_last_error = err;
         } else if (st == KC_OK) {
-            st = st2;
+            st = st2;  // f stays marked stale: a query recomputes it or reports the failure
         }
     }
     HIP_TRY(hipStreamSynchronize(stream));
@@ -1509,3 +1592,19 @@ kc_status kc_apply_updates(kc_graph *g, const int32_t *u, const int32_t *v, cons
 }
 
 }  // extern "C"
+
+namespace {
+
+// f of every resident tree on the current graph, evaluated into the spare
+// buffer and swapped in only when the whole evaluation succeeded, so that a
+// failure leaves the previous values and the stale mark in place.
+kc_status refresh_resident_f(kc_graph *g, hipStream_t stream) {
+    if (!g->res_f_stale || g->res_count < 1) return KC_OK;
+    const kc_status st = kc_evaluate_trees(g, g->d_res_par, g->res_count, g->d_res_f_alt, (void *)stream);
+    if (st != KC_OK) return st;
+    std::swap(g->d_res_f, g->d_res_f_alt);
+    g->res_f_stale = false;
+    return KC_OK;
+}
+
+}  // namespace

@@ -22,6 +22,9 @@ struct GraphDev {
     const int32_t *elist; //          subtree started before the block and ends in it
     const int4 *vrec;     // [2n]  32-byte record per vertex: {offset, degree, first six
                           //       neighbours (-1 past the degree)}
+    const int32_t *anc0;  // [anc_depth * n] level-major tau0 ancestors: anc0[i n + v] is the
+                          //       (i+1)-th ancestor of v, -1 past the root; null if tau0 is deep
+    int32_t anc_depth;    //       levels in anc0 (4 or 8), 0 without the table
 };
 
 // Per-slot workspace: one slot = one sample in flight = one wavefront.
@@ -32,11 +35,10 @@ struct SlotDev {
     int4 *queue;     // [slots*chains] sampler: ready tasks
     int32_t *cstart; // [slots*chains] sampler: chain start vertices
     int64_t chains;  // per-slot stride of queue and cstart
-    uint64_t *word;  // [slots*n] pending-children | volume accumulator
-    int4 *rec;       // [slots*n] {tin_w, vol, parent, unused}
-    int32_t *ordr;   // [slots*n] bottom-up completion order
+    int4 *rec;       // [slots*n] {tin, vol, parent, unused}; null without the traversal
+                     // (the numbering's pending-children | volume words reuse tagw)
+    int4 *ord;       // [slots*n] finished vertices {v, parent, vol} and leaves {v, parent, deg}
     int32_t *grp;    // [slots*(n+1)] completion group boundaries
-    int32_t *leaves; // [slots*n] leaves of the tree
     int64_t *fen;    // [slots*fen_len] Fenwick tree (sweep traversal only)
     int64_t fen_len; // 2m + 2 (0 if not allocated)
 };

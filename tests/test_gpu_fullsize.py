@@ -49,6 +49,44 @@ def _check_prefix(kc, oracle_lib, g, count, tree_id):
     assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ref_cnt)
 
 
+def _check_random_ids(kc, oracle_lib, g, batch, first, nids, seed_ids):
+    """The benchmark's launch shape (default options, `batch` samples from
+    `first`), compared with the oracle on a seeded random subset of `nids`
+    sample ids of the batch, each computed by the oracle on its own."""
+    P = oracle_lib.prepare_graph(g)
+    rng = np.random.default_rng(seed_ids)
+    pos = np.sort(rng.choice(batch, size=nids, replace=False))
+    ids = first + pos
+    _say("oracle", g.name, g.n, "ids", nids, "of", batch)
+    ref_f, ref_steps = oracle_lib.estimate_ids(P, 0, ids, threads=16)
+    with kc.Graph.from_graph(g) as G:
+        assert G.root == P.root
+        _say("gpu batch", batch, "from", first)
+        G.reserve(batch)
+        est, f, st = G.estimate(0, first, batch, per_sample=True)
+        f = f.cpu().numpy()
+        st = st.cpu().numpy()
+    assert np.array_equal(f[pos], ref_f)
+    assert np.array_equal(st[pos], ref_steps)
+    assert est.count == batch and est.sum_f == int(f.astype(object).sum())
+
+
+def test_dense_power_law_random_ids(kc, oracle_lib):
+    """The headline workload (Chung-Lu 3x10^6 vertices, mean degree 76): one
+    4,096-sample launch of the third benchmark step (ids 8,192..12,287), as
+    bench.py times it, with slots reused across waves; 64 seeded random ids
+    checked against the oracle."""
+    import graphgen
+    _check_random_ids(kc, oracle_lib, graphgen.workload("dense"), 4096, 2 * 4096, 64, 5)
+
+
+def test_road_like_random_ids(kc, oracle_lib):
+    """Road-like 10^6 points: a 256-sample launch in the benchmark's launch
+    options, 64 seeded random ids against the oracle."""
+    import graphgen
+    _check_random_ids(kc, oracle_lib, graphgen.workload("road"), 256, 4096, 64, 6)
+
+
 def test_road_like_full_size(kc, oracle_lib):
     """Road-like: 10^6 points, thinned RGG, LCC n = 792,324 (the bench workload)."""
     import graphgen

@@ -110,7 +110,7 @@ def test_chain_table_size_invariance(kc, oracle_lib, graphs, chains):
         _say("chains", chains, name)
         P = oracle_lib.prepare_graph(g)
         ref_par, ref_cnt, ref_steps = oracle_lib.sample(P, seed=31, s0=200, count=20, threads=8)
-        ref_f = np.array([oracle_lib.f_of_tree(P, t, "alg1") for t in ref_par], np.int64)
+        ref_f = np.array([oracle_lib.f_of_tree(P, t) for t in ref_par], np.int64)
         with kc.Graph.from_graph(g) as G:
             G.set_option(kc.KC_OPT_CHAINS, chains)
             par, cnt, stp = G.sample_trees(31, 200, 20)
@@ -145,7 +145,7 @@ def test_tree_values_exact(kc, oracle_lib, graphs, name, trav):
     _say("f parity", name, trav)
     P = oracle_lib.prepare_graph(g)
     par, _, _ = oracle_lib.sample(P, seed=21, s0=0, count=24, threads=8)
-    ref = np.array([oracle_lib.f_of_tree(P, t, "alg1") for t in par], np.int64)
+    ref = np.array([oracle_lib.f_of_tree(P, t) for t in par], np.int64)
     with kc.Graph.from_graph(g) as G:
         G.set_option(kc.KC_OPT_TRAVERSAL, trav)
         f = G.evaluate_trees(torch.from_numpy(par).cuda())
@@ -171,6 +171,68 @@ def test_estimate_exact(kc, oracle_lib, graphs, name, trav):
         assert est.kappa == K  # bit-identical
         assert est.std_error == se
         assert est.total_steps == int(ref_steps.sum())
+
+
+@pytest.mark.parametrize("trav", [1, 2])
+@pytest.mark.parametrize("name", ["petersen", "grid32", "road3k", "social3k"])
+def test_more_samples_than_slots(kc, oracle_lib, graphs, name, trav):
+    """Five slots serve forty samples, so every slot is reused about eight
+    times within one launch: its sampler state, numbering arrays and (sweep)
+    Fenwick tree must return to their start state between trees.  Estimate,
+    evaluation of given trees and a resident set, each against the oracle."""
+    import torch
+    g = graphs[name]
+    _say("slots < count", name, trav)
+    P = oracle_lib.prepare_graph(g)
+    ref_f, ref_steps = oracle_lib.estimate_f(P, seed=41, s0=300, count=40, threads=8)
+    ref_par, _, _ = oracle_lib.sample(P, seed=41, s0=300, count=40, threads=8)
+    K, se, s1, s2 = oracle_lib.reduce_estimate(ref_f, g.two_m)
+    with kc.Graph.from_graph(g) as G:
+        G.set_option(kc.KC_OPT_SLOTS, 5)
+        G.set_option(kc.KC_OPT_TRAVERSAL, trav)
+        est, f, stp = G.estimate(41, 300, 40, per_sample=True)
+        assert np.array_equal(f.cpu().numpy(), ref_f)
+        assert np.array_equal(stp.cpu().numpy(), ref_steps)
+        assert est.kappa == K and est.std_error == se and est.sum_f == s1
+        fe = G.evaluate_trees(torch.from_numpy(ref_par).cuda())
+        assert np.array_equal(fe.cpu().numpy(), ref_f)
+        G.samples_init(41, 40)
+        S = oracle_lib.samples_init(g.offsets, g.indices, seed=41, count=40)
+        par, fr, ids = G.samples_get()
+        assert np.array_equal(par.cpu().numpy(), S.parents)
+        assert np.array_equal(fr.cpu().numpy(), S.f)
+
+
+def test_grid32_eps_at_95(kc, oracle_lib, gen):
+    """The 32x32 grid with 8,192 samples from seed 0 (the first 8,192 sample
+    ids): every f equals the oracle's, and K-hat lies within eps = 0.01 of the
+    exact Kemeny constant (Eq. 1, dense eigensolve), with the 95% interval
+    (reading A10: 1.96 standard errors) also narrower than eps."""
+    from oracle import exact as E
+    g = gen.grid(32, 32)
+    P = oracle_lib.prepare_graph(g)
+    ref_f, _ = oracle_lib.estimate_f(P, seed=0, s0=0, count=8192, threads=8)
+    K, se, _, _ = oracle_lib.reduce_estimate(ref_f, g.two_m)
+    Kx = E.kemeny_exact(g.offsets, g.indices)
+    with kc.Graph.from_graph(g) as G:
+        est, f, _ = G.estimate(0, 0, 8192, per_sample=True)
+        assert np.array_equal(f.cpu().numpy(), ref_f)
+        assert est.kappa == K and est.std_error == se
+    assert abs(est.kappa / Kx - 1.0) <= 0.01
+    assert 1.959963984540054 * est.std_error / Kx <= 0.01
+
+
+def test_combine_results_pools_exact_sums(kc, oracle_lib, graphs):
+    """Estimates of consecutive sample ranges, pooled by the library, equal one
+    estimate over the whole range bit for bit."""
+    g = graphs["road3k"]
+    with kc.Graph.from_graph(g) as G:
+        whole = G.estimate(6, 0, 30)
+        parts = [G.estimate(6, 0, 7), G.estimate(6, 7, 1), G.estimate(6, 8, 22)]
+        pooled = G.combine(parts)
+        assert pooled.sum_f == whole.sum_f and pooled.sum_f2 == whole.sum_f2
+        assert pooled.kappa == whole.kappa and pooled.std_error == whole.std_error
+        assert pooled.count == 30 and pooled.total_steps == whole.total_steps
 
 
 def test_grid32_full_config(kc, oracle_lib, gen):

@@ -207,3 +207,37 @@ def test_one_call_runs_in_order(kc, oracle_lib, gen):
         assert k1 == k2
         assert np.array_equal(f1.cpu().numpy(), f2.cpu().numpy())
         assert np.array_equal(p1.cpu().numpy(), p2.cpu().numpy()) and np.array_equal(i1, i2)
+
+
+def test_failed_refresh_is_never_queried(kc, oracle_lib, gen):
+    """f is recomputed once at the end of an update call.  When that fails
+    (forced from the host: a memory budget of exactly one sample's workspace
+    before the insertion, so the sweep's larger Fenwick tree no longer fits),
+    the call reports it, and queries report it too instead of reducing the f
+    of the previous graph; once the budget is lifted the query recomputes f
+    and equals the oracle's result for the updated set (Theorem 4.1)."""
+    from test_gpu_parity import small_graphs
+    g = small_graphs(gen)["grid32"]
+    count = 16
+    S = oracle_lib.samples_init(g.offsets, g.indices, seed=23, count=count)
+    a, b = 5, 900
+    g2 = gen.add_edges(g, [(a, b)])
+    S2, _, _ = oracle_lib.bsm_insert(S, g2.offsets, g2.indices, a, b, 0)
+    with kc.Graph.from_graph(g) as G:
+        G.set_option(kc.KC_OPT_SLOTS, 1)
+        G.set_option(kc.KC_OPT_TRAVERSAL, kc.KC_TRAV_SWEEP)
+        G.samples_init(23, count)
+        G.set_option(kc.KC_OPT_MEM_BUDGET, G.info["sample_bytes"])
+        with pytest.raises(kc.KcError) as ei:
+            G.apply_updates([a], [b], is_insert=[1])
+        assert ei.value.status == 3
+        assert G.two_m == g2.two_m  # the insertion itself is in place
+        with pytest.raises(kc.KcError) as ei:
+            G.samples_query()
+        assert ei.value.status == 3
+        G.set_option(kc.KC_OPT_MEM_BUDGET, 0)
+        est = G.samples_query()
+        K, se, s1, _ = oracle_lib.reduce_estimate(S2.f, g2.two_m)
+        assert est.sum_f == s1 and est.kappa == K
+        _compare(G, S2, g2.two_m)
+

@@ -118,7 +118,7 @@ def test_enumeration_mean_equals_exact_kemeny(gen, oracle_lib):
         P = oracle_lib.prepare_graph(g)
         trees = E.spanning_trees(g.offsets, g.indices, P.root)
         assert len(trees) == E.tree_count(g.offsets, g.indices)
-        for form in ("naive", "alg1", "peredge", "walk"):
+        for form in ("naive", "peredge", "walk"):
             fs = [oracle_lib.f_of_tree(P, t, form) for t in trees]
             mean = Fraction(sum(fs), len(fs) * g.two_m)
             assert float(mean) == pytest.approx(E.kemeny_exact(g.offsets, g.indices), rel=1e-12), (g.name, form)
@@ -134,7 +134,7 @@ def test_enumeration_with_non_bfs_tau0(gen, oracle_lib):
         dfs = oracle_lib.dfs_tree(g.offsets, g.indices, P.root)
         for t0 in (trees[0], trees[len(trees) // 2], trees[-1], dfs):
             Q = oracle_lib.with_tau0(P, t0)
-            for form in ("naive", "alg1", "peredge", "walk"):
+            for form in ("naive", "peredge", "walk"):
                 fs = [oracle_lib.f_of_tree(Q, t, form) for t in trees]
                 assert sum(fs) / (len(fs) * g.two_m) == pytest.approx(K, rel=1e-12)
 
@@ -146,7 +146,7 @@ def test_worked_triangle_example(gen, oracle_lib):
     assert P.root == ex["root"]
     for key, fval in ex["bfs_tau0"]["f"].items():
         parent = np.array([int(x) for x in key.split(",")], np.int32)
-        for form in ("naive", "alg1", "peredge", "walk"):
+        for form in ("naive", "peredge", "walk"):
             assert oracle_lib.f_of_tree(P, parent, form) == fval
     num, den = ex["bfs_tau0"]["kappa"]
     assert Fraction(sum(ex["bfs_tau0"]["f"].values()), 3 * g.two_m) == Fraction(num, den)
@@ -154,7 +154,7 @@ def test_worked_triangle_example(gen, oracle_lib):
     tot = 0
     for key, fval in ex["path_tau0"]["f"].items():
         parent = np.array([int(x) for x in key.split(",")], np.int32)
-        for form in ("naive", "alg1", "peredge", "walk"):
+        for form in ("naive", "peredge", "walk"):
             assert oracle_lib.f_of_tree(Q, parent, form) == fval
         tot += fval
     assert tot == ex["path_tau0"]["sum_f_equals_2m_trees_kappa"]
@@ -172,20 +172,63 @@ def test_forms_agree_on_sampled_trees(gen, oracle_lib, name):
     P = oracle_lib.prepare_graph(g)
     parents, _, _ = oracle_lib.sample(P, seed=11, s0=0, count=40)
     for t in parents:
-        vals = {form: oracle_lib.f_of_tree(P, t, form) for form in ("naive", "alg1", "peredge", "walk")}
+        vals = {form: oracle_lib.f_of_tree(P, t, form) for form in ("naive", "peredge", "walk")}
         assert len(set(vals.values())) == 1, vals
         assert vals["naive"] > 0
 
 
-def test_printed_undo_sign_disagrees(gen, oracle_lib):
-    """Algorithm 1's undo for the reverse case, taken with the printed sign,
-    breaks Theorem 3.3 on larger graphs; the corrected sign matches F1."""
-    g = gen.grid(8, 8)
+def _exact_spread(oracle_lib, P, trees, two_m):
+    """Exact mean, variance and fourth central moment of X = f(tau)/2m over
+    uniform spanning trees, from the list of all of them (rationals)."""
+    xs = [Fraction(oracle_lib.f_of_tree(P, t), two_m) for t in trees]
+    N = len(xs)
+    mu = sum(xs) / N
+    var = sum((x - mu) ** 2 for x in xs) / N
+    m4 = sum((x - mu) ** 4 for x in xs) / N
+    return mu, var, m4
+
+
+@pytest.mark.parametrize("name", ["grid3", "petersen"])
+def test_standard_error_matches_exact_spread(gen, oracle_lib, name):
+    """Theorem 3.3's estimate is the mean of omega i.i.d. values f(tau)/2m, so
+    its standard error is their standard deviation over sqrt(omega).  The
+    oracle's se times sqrt(omega) is checked against the exact standard
+    deviation over ALL spanning trees (enumeration: 192 trees of the 3x3 grid,
+    2,000 of the Petersen graph).  The tolerance is 4.5 sampling standard
+    deviations of a sample variance, sqrt((mu4 - var^2) / omega), from the
+    exact fourth moment."""
+    from oracle import exact as E
+    g = gen.grid(3, 3) if name == "grid3" else gen.petersen()
     P = oracle_lib.prepare_graph(g)
-    parents, _, _ = oracle_lib.sample(P, seed=3, s0=0, count=60)
-    bad = sum(oracle_lib.f_of_tree(P, t, "alg1_printed") != oracle_lib.f_of_tree(P, t, "naive")
-              for t in parents)
-    assert bad > 0
+    trees = E.spanning_trees(g.offsets, g.indices, P.root)
+    mu, var, m4 = _exact_spread(oracle_lib, P, trees, g.two_m)
+    assert float(mu) == pytest.approx(E.kemeny_exact(g.offsets, g.indices), rel=1e-12)
+    omega = 24000
+    f, _ = oracle_lib.estimate_f(P, seed=17, s0=0, count=omega, threads=8)
+    K, se, _, _ = oracle_lib.reduce_estimate(f, g.two_m)
+    s2 = (se * math.sqrt(omega)) ** 2
+    tol = 4.5 * math.sqrt(float(m4 - var * var) / omega)
+    assert abs(s2 - float(var)) < tol, (s2, float(var), tol)
+    # and the mean within 4.5 exact standard errors
+    assert abs(K - float(mu)) < 4.5 * math.sqrt(float(var) / omega)
+
+
+def test_interval_coverage_on_grid(gen, oracle_lib):
+    """The interval K-hat +- 1.96 se (reading A10: a normal approximation in
+    place of the Hoeffding bound of Theorem 3.6) covers the exact kappa of the
+    3x3 grid (9.5) in about 95% of 800 independent estimates of 200 trees
+    each; the tolerance is 4.5 binomial standard deviations.  An se off by a
+    factor of two would cover about 67% or 99.99% of the time."""
+    g = gen.grid(3, 3)
+    P = oracle_lib.prepare_graph(g)
+    reps, omega = 800, 200
+    f, _ = oracle_lib.estimate_f(P, seed=29, s0=0, count=reps * omega, threads=8)
+    cover = 0
+    for r in range(reps):
+        K, se, _, _ = oracle_lib.reduce_estimate(f[r * omega:(r + 1) * omega], g.two_m)
+        cover += abs(K - 9.5) <= 1.959963984540054 * se
+    p = cover / reps
+    assert abs(p - 0.95) < 4.5 * math.sqrt(0.95 * 0.05 / reps), p
 
 
 # --------------------------------------------------------- sampler pins
@@ -561,16 +604,26 @@ def test_ism_estimate_tracks_exact_kemeny(gen, oracle_lib):
     g2 = gen.remove_edges(g1, [(5, 6)])
     k1 = E.kemeny_exact(g1.offsets, g1.indices)
     k2 = E.kemeny_exact(g2.offsets, g2.indices)
-    e1, e2 = [], []
+    e1, e2, b1, b2 = [], [], [], []
     for seed in range(120):
         W = oracle_lib.ism_init(g0.offsets, g0.indices, seed=seed, count=24, threads=1)
         W, _ = oracle_lib.ism_insert(W, g1.offsets, g1.indices, 0, 15)
         assert abs(sum(W.w) - 1.0) < 1e-12
-        e1.append(oracle_lib.weighted_estimate(W)[0])
+        k_, b_ = oracle_lib.weighted_estimate(W)
+        e1.append(k_)
+        b1.append(b_)
         W, _ = oracle_lib.ism_delete(W, g2.offsets, g2.indices, 5, 6)
         assert abs(sum(W.w) - 1.0) < 1e-12
-        e2.append(oracle_lib.weighted_estimate(W)[0])
-    for est, k in ((e1, k1), (e2, k2)):
+        k_, b_ = oracle_lib.weighted_estimate(W)
+        e2.append(k_)
+        b2.append(b_)
+    for est, bars, k in ((e1, b1, k1), (e2, b2, k2)):
         est = np.array(est)
         se = est.std(ddof=1) / math.sqrt(len(est))
         assert abs(est.mean() - k) < 4 * se + 1e-3 * k, (est.mean(), k, se)
+        # the error bar of each weighted estimate (reading A30) against the
+        # spread of the 120 independent estimates: the mean squared bar and the
+        # empirical variance agree within 4.5 standard deviations of a sample
+        # variance of 120 values (relative sd sqrt(2/119) for a normal spread)
+        ratio = float(np.mean(np.square(bars))) / float(est.var(ddof=1))
+        assert abs(ratio - 1.0) < 4.5 * math.sqrt(2.0 / 119.0), ratio
