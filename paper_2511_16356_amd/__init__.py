@@ -32,7 +32,8 @@ KC_MAINT_BASIC, KC_MAINT_IMPROVED = 0, 1
 EXPORTS = ("kc_graph_create", "kc_graph_destroy", "kc_graph_get_info", "kc_set_option", "kc_set_tau0",
            "kc_reserve", "kc_progress",
            "kc_samples_init", "kc_samples_query", "kc_samples_get", "kc_samples_weights", "kc_apply_updates",
-           "kc_sample_trees", "kc_estimate", "kc_evaluate_trees", "kc_combine_results", "kc_status_string",
+           "kc_sample_trees", "kc_estimate", "kc_evaluate_trees", "kc_combine_results",
+           "kc_status_string",
            "kc_last_error")
 
 
@@ -247,11 +248,14 @@ class Graph:
         v = np.ascontiguousarray(v, dtype=np.int32)
         ins = None if is_insert is None else np.ascontiguousarray(is_insert, dtype=np.uint8)
         out = ctypes.c_int32(0)
-        _check(library().kc_apply_updates(self._h, u.ctypes.data_as(ctypes.c_void_p),
-                                          v.ctypes.data_as(ctypes.c_void_p),
-                                          None if ins is None else ins.ctypes.data_as(ctypes.c_void_p),
-                                          int(u.shape[0]), ctypes.byref(out), _stream(stream)))
-        self.info = self._info()
+        st = library().kc_apply_updates(self._h, u.ctypes.data_as(ctypes.c_void_p),
+                                        v.ctypes.data_as(ctypes.c_void_p),
+                                        None if ins is None else ins.ctypes.data_as(ctypes.c_void_p),
+                                        int(u.shape[0]), ctypes.byref(out), _stream(stream))
+        detail = library().kc_last_error().decode(errors="replace") if st != KC_OK else ""
+        self.info = self._info()  # updates before a failing one stay applied
+        if st != KC_OK:
+            raise KcError(st, detail)
         return out.value
 
     def reserve(self, count: int, stream=None):

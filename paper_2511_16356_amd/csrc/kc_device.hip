@@ -97,8 +97,10 @@ __device__ void report_error(int32_t *ctl, int code, int idx) {
 // (k, v, s_lo, s_hi), key (seed_lo, seed_hi).  The neighbour slot is the
 // high word of x * deg with x = out0 | out1 << 32, i.e. floor(x deg / 2^64),
 // computed from two 32x32 products.
-__device__ __forceinline__ uint32_t arrow_slot(uint64_t seed, uint64_t s, uint32_t v, uint32_t k,
-                                               uint32_t deg) {
+struct Bits {
+    uint32_t lo, hi;
+};
+__device__ __forceinline__ Bits philox_bits(uint64_t seed, uint64_t s, uint32_t v, uint32_t k) {
     uint32_t x0 = k, x1 = v, x2 = (uint32_t)s, x3 = (uint32_t)(s >> 32);
     uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
 #pragma unroll
@@ -112,9 +114,16 @@ __device__ __forceinline__ uint32_t arrow_slot(uint64_t seed, uint64_t s, uint32
         key0 += 0x9E3779B9u;
         key1 += 0xBB67AE85u;
     }
-    const uint64_t lowprod = (uint64_t)x0 * deg;
-    const uint64_t highprod = (uint64_t)x1 * deg + (lowprod >> 32);
+    return Bits{x0, x1};
+}
+__device__ __forceinline__ uint32_t slot_of(Bits x, uint32_t deg) {
+    const uint64_t lowprod = (uint64_t)x.lo * deg;
+    const uint64_t highprod = (uint64_t)x.hi * deg + (lowprod >> 32);
     return (uint32_t)(highprod >> 32);
+}
+__device__ __forceinline__ uint32_t arrow_slot(uint64_t seed, uint64_t s, uint32_t v, uint32_t k,
+                                               uint32_t deg) {
+    return slot_of(philox_bits(seed, s, v, k), deg);
 }
 
 // ------------------------------------------------------------ sampler state
@@ -219,7 +228,7 @@ template <int CH>
 __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerShared<CH> &sh,
                                uint64_t seed, uint64_t s, int walkers, int64_t iter_cap,
                                int32_t *ctl, int idx, int64_t *iters_used, int32_t root_u,
-                               int32_t root_v) {
+                               int32_t root_v, bool speculate) {
     const int lane = threadIdx.x;
     const int n = g.n, root = g.root;
     const bool two_roots = root_u >= 0;  // start from {u, v} instead of {root}
@@ -354,6 +363,12 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
         const bool do_arrow = m0 == M_LOOK || m0 == M_ERASE0 || do_xchg;
         const bool do_rec = m0 == M_LOOK || m0 == M_ERASE0;
         if (m0 == M_LOOK && pend) astore(&arw[cur], arrow_of(tgt, dcur));
+        // the graph record first: the speculative draw below waits for it alone
+        int4 r0 = make_int4(0, 0, 0, 0), r1 = make_int4(0, 0, 0, 0);
+        if (do_rec) {
+            r0 = g.vrec[2 * (size_t)tgt];
+            r1 = g.vrec[2 * (size_t)tgt + 1];
+        }
         // (each operation returns into a register of its own: a shared one would make
         // every later issue wait for the earlier operations' results)
         uint64_t o_cas = 0, o_xchg = 0, o_tag = 0;
@@ -370,10 +385,18 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
         if (m0 == M_ERASE0) o_tag = aload(&tagw[tgt]);
         uint64_t ar = 0;
         if (do_arrow) ar = aload(&arw[tgt]);
-        int4 r0 = make_int4(0, 0, 0, 0), r1 = make_int4(0, 0, 0, 0);
-        if (do_rec) {
-            r0 = g.vrec[2 * (size_t)tgt];
-            r1 = g.vrec[2 * (size_t)tgt + 1];
+        // speculative first draw of the looked-at vertex: if the claim finds it with
+        // no draws yet, its draw uses counter k = 0, so the Philox bits are computed
+        // while the claim is in flight, and a slot beyond the inline neighbours has
+        // its row entry requested in this same round
+        uint32_t sj = 0;
+        int32_t sy = -1;
+        const bool spec = speculate && m0 == M_LOOK;
+        if (spec) {
+            const Bits x0 = philox_bits(seed, s, (uint32_t)tgt, 0u);
+            sj = slot_of(x0, (uint32_t)r0.y);
+            if (sj >= (uint32_t)VREC_INLINE && sj < (uint32_t)r0.y && (unsigned)(r0.x + (int)sj) < (unsigned)g.two_m)
+                sy = g.adj[r0.x + (int)sj];
         }
         auto take_record = [&]() __attribute__((always_inline)) {
             hoff = r0.x; hdeg = r0.y; hn0 = r0.z; hn1 = r0.w;
@@ -401,7 +424,26 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
                 cur = tgt;
                 dcur = dt;
                 take_record();
-                drawing = true;
+                if (spec && dt == 0u && (sj < (uint32_t)VREC_INLINE || sy >= 0)) {
+                    // the speculative draw was this draw
+                    mysteps++;
+                    dcur = 1;
+                    haspath = true;
+                    if (sj < (uint32_t)VREC_INLINE) {
+                        const bool odd = (sj & 1u) != 0u;
+                        int p01 = odd ? hn1 : hn0;
+                        int p23 = odd ? hn3 : hn2;
+                        int p45 = odd ? hn5 : hn4;
+                        asm volatile("" : "+v"(p01), "+v"(p23), "+v"(p45));
+                        tgt = sj < 2u ? p01 : (sj < 4u ? p23 : p45);
+                    } else {
+                        tgt = sy;
+                    }
+                    pend = true;
+                    mode = M_LOOK;
+                } else {
+                    drawing = true;
+                }
             } else if (tg == T_TREE) {
                 if (haspath) {
                     stopv = tgt;
@@ -1183,92 +1225,154 @@ union KernelShared {
     SweepShared sweep;
 };
 
+// The per-slot arrays of workgroup blockIdx.x, each `stride` vertices long.
+__device__ __forceinline__ SlotPtrs slot_ptrs(const SlotDev &sd, size_t stride) {
+    SlotPtrs sp;
+    const size_t b = (size_t)blockIdx.x;
+    sp.ws.tagw = sd.tagw + b * stride;
+    sp.ws.arrow = sd.arrow + b * stride;
+    sp.ws.rq = sd.rq + b * stride;
+    sp.ws.queue = sd.queue + b * (size_t)sd.chains;
+    sp.ws.start = sd.cstart + b * (size_t)sd.chains;
+    // the numbering's word array reuses the sampler's tag words (dead once the tree is drawn)
+    sp.word = sd.rec ? sp.ws.tagw : nullptr;
+    sp.rec = sd.rec ? reinterpret_cast<uint64_t *>(sd.rec) + 2 * b * stride : nullptr;
+    sp.ord = sd.ord ? sd.ord + b * stride : nullptr;
+    sp.grp = sd.grp ? sd.grp + b * (stride + 1) : nullptr;
+    sp.fen = sd.fen ? sd.fen + b * (size_t)sd.fen_len : nullptr;
+    return sp;
+}
+
+// One sample s (work item idx) of graph g through the whole path in the
+// calling workgroup: the tree, then (except in RUN_SAMPLE) its numbering and
+// f.  Returns false when the workgroup must stop (an error was recorded).
 // CROSS: the instantiation for RUN_CROSS only (no sampler, no f), kept apart
 // so that its code does not weigh on the sampler's register allocation.
+template <int CH, bool CROSS>
+__device__ bool process_one(const GraphDev &g, const SlotPtrs &sp, KernelShared<CH> &lds, const RunParams &rp,
+                            int64_t fen_len, int idx, uint64_t s) {
+    const int lane = threadIdx.x;
+    const size_t n = (size_t)g.n;
+    int64_t steps = 0, iters = 0;
+    if (!CROSS && (rp.mode == RUN_SAMPLE || rp.mode == RUN_ESTIMATE)) {
+        steps = sample_tree<CH>(g, sp.ws, lds.samp, rp.seed, s, rp.walkers, rp.iter_cap, rp.ctl, idx, &iters,
+                                rp.root_u, rp.root_v, rp.speculate != 0);
+        if (steps < 0) return false;
+    }
+    if (!CROSS && rp.mode == RUN_SAMPLE) {
+        int32_t *po = rp.parents_out + (size_t)idx * n;
+        uint32_t *co = rp.cnt_out ? rp.cnt_out + (size_t)idx * n : nullptr;
+        for (int v = lane; v < g.n; v += WAVE) {
+            const uint64_t ar = aload(&sp.ws.arrow[v]);
+            po[v] = (int32_t)(uint32_t)ar;  // -1 at vertices that started in the tree
+            if (co) co[v] = (uint32_t)(ar >> 32);
+        }
+    } else {
+        // parents into rec[2v+1]; the numbering's volume words start at deg(v)
+        const size_t row = rp.rows ? (size_t)rp.rows[idx] : (size_t)idx;
+        bool bad = false;
+        for (int b = 0; b < g.n; b += WAVE * NBS) {
+            int32_t p[NBS];
+#pragma unroll
+            for (int k = 0; k < NBS; ++k) {
+                const int v = b + k * WAVE + lane;
+                p[k] = -1;
+                if (v < g.n && v != g.root)
+                    p[k] = (rp.mode != RUN_ESTIMATE) ? rp.parents_in[row * n + v]
+                                                     : (int32_t)(uint32_t)aload(&sp.ws.arrow[v]);
+            }
+#pragma unroll
+            for (int k = 0; k < NBS; ++k) {
+                const int v = b + k * WAVE + lane;
+                if (v >= g.n) continue;
+                if (v != g.root && (p[k] < 0 || p[k] >= g.n || p[k] == v)) { bad = true; p[k] = g.root; }
+                astore(&sp.rec[2 * (size_t)v + 1], (uint64_t)(uint32_t)p[k]);
+                astore(&sp.word[v], (uint64_t)degree(g, v));
+            }
+        }
+        fence_wg();
+        bool ok = tree_numbering(g, sp);
+        if (__ballot(bad) != 0ull) ok = false;
+        int64_t f = 0;
+        if constexpr (CROSS) {
+            f = ok ? crossing_edges(g, sp, rp, (int32_t)row, idx) : 0;
+        } else {
+            if (rp.mode == RUN_CURRENT) f = path_current(sp, rp.path, rp.path_len);
+            else if (rp.traversal == 2) f = f_sweep(g, sp, fen_len, lds.sweep);
+            else f = f_walk(g, sp);
+        }
+        if (!ok) report_error(rp.ctl, DEV_BADTREE, idx);
+        if (lane == 0) rp.f_out[idx] = f;
+    }
+    if (rp.steps_out && lane == 0) rp.steps_out[idx] = steps;
+    if (rp.iters_out && lane == 0) rp.iters_out[idx] = iters;
+    return true;
+}
+
+// The next work item for the calling workgroup (one atomic per workgroup).
+__device__ __forceinline__ int next_item(int32_t *ctl) {
+    int idx = 0;
+    if (threadIdx.x == 0) idx = __hip_atomic_fetch_add(&ctl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __shfl(idx, 0);
+}
+__device__ __forceinline__ bool stopped(const int32_t *ctl) {
+    return __hip_atomic_load(const_cast<int32_t *>(&ctl[1]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
 template <int CH, bool CROSS = false>
 __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd, RunParams rp) {
     __shared__ KernelShared<CH> lds;
-    const int lane = threadIdx.x;
-    const size_t n = (size_t)g.n;
-    SlotPtrs sp;
-    sp.ws.tagw = sd.tagw + (size_t)blockIdx.x * n;
-    sp.ws.arrow = sd.arrow + (size_t)blockIdx.x * n;
-    sp.ws.rq = sd.rq + (size_t)blockIdx.x * n;
-    sp.ws.queue = sd.queue + (size_t)blockIdx.x * (size_t)sd.chains;
-    sp.ws.start = sd.cstart + (size_t)blockIdx.x * (size_t)sd.chains;
-    // the numbering's word array reuses the sampler's tag words (dead once the tree is drawn)
-    sp.word = sd.rec ? sp.ws.tagw : nullptr;
-    sp.rec = sd.rec ? reinterpret_cast<uint64_t *>(sd.rec) + 2 * (size_t)blockIdx.x * n : nullptr;
-    sp.ord = sd.ord ? sd.ord + (size_t)blockIdx.x * n : nullptr;
-    sp.grp = sd.grp ? sd.grp + (size_t)blockIdx.x * (n + 1) : nullptr;
-    sp.fen = sd.fen ? sd.fen + (size_t)blockIdx.x * (size_t)sd.fen_len : nullptr;
+    const SlotPtrs sp = slot_ptrs(sd, (size_t)g.n);
     int64_t done = 0;
-
     while (true) {
-        int idx = 0;
-        if (lane == 0) idx = __hip_atomic_fetch_add(&rp.ctl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        idx = __shfl(idx, 0);
-        if (idx >= rp.count) break;
-        if (__hip_atomic_load(&rp.ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-        const uint64_t s = (uint64_t)(rp.first + idx);
-        int64_t steps = 0, iters = 0;
-        if (!CROSS && (rp.mode == RUN_SAMPLE || rp.mode == RUN_ESTIMATE)) {
-            steps = sample_tree<CH>(g, sp.ws, lds.samp, rp.seed, s, rp.walkers, rp.iter_cap, rp.ctl, idx, &iters,
-                                    rp.root_u, rp.root_v);
-            if (steps < 0) break;
-        }
-        if (!CROSS && rp.mode == RUN_SAMPLE) {
-            int32_t *po = rp.parents_out + (size_t)idx * n;
-            uint32_t *co = rp.cnt_out ? rp.cnt_out + (size_t)idx * n : nullptr;
-            for (int v = lane; v < g.n; v += WAVE) {
-                const uint64_t ar = aload(&sp.ws.arrow[v]);
-                po[v] = (int32_t)(uint32_t)ar;  // -1 at vertices that started in the tree
-                if (co) co[v] = (uint32_t)(ar >> 32);
-            }
-        } else {
-            // parents into rec[2v+1]; the numbering's volume words start at deg(v)
-            const size_t row = rp.rows ? (size_t)rp.rows[idx] : (size_t)idx;
-            bool bad = false;
-            for (int b = 0; b < g.n; b += WAVE * NBS) {
-                int32_t p[NBS];
-#pragma unroll
-                for (int k = 0; k < NBS; ++k) {
-                    const int v = b + k * WAVE + lane;
-                    p[k] = -1;
-                    if (v < g.n && v != g.root)
-                        p[k] = (rp.mode != RUN_ESTIMATE) ? rp.parents_in[row * n + v]
-                                                         : (int32_t)(uint32_t)aload(&sp.ws.arrow[v]);
-                }
-#pragma unroll
-                for (int k = 0; k < NBS; ++k) {
-                    const int v = b + k * WAVE + lane;
-                    if (v >= g.n) continue;
-                    if (v != g.root && (p[k] < 0 || p[k] >= g.n || p[k] == v)) { bad = true; p[k] = g.root; }
-                    astore(&sp.rec[2 * (size_t)v + 1], (uint64_t)(uint32_t)p[k]);
-                    astore(&sp.word[v], (uint64_t)degree(g, v));
-                }
-            }
-            fence_wg();
-            bool ok = tree_numbering(g, sp);
-            if (__ballot(bad) != 0ull) ok = false;
-            int64_t f = 0;
-            if constexpr (CROSS) {
-                f = ok ? crossing_edges(g, sp, rp, (int32_t)row, idx) : 0;
-            } else {
-                if (rp.mode == RUN_CURRENT) f = path_current(sp, rp.path, rp.path_len);
-                else if (rp.traversal == 2) f = f_sweep(g, sp, sd.fen_len, lds.sweep);
-                else f = f_walk(g, sp);
-            }
-            if (!ok) report_error(rp.ctl, DEV_BADTREE, idx);
-            if (lane == 0) rp.f_out[idx] = f;
-        }
-        if (rp.steps_out && lane == 0) rp.steps_out[idx] = steps;
-        if (rp.iters_out && lane == 0) rp.iters_out[idx] = iters;
+        const int idx = next_item(rp.ctl);
+        if (idx >= rp.count || stopped(rp.ctl)) break;
+        if (!process_one<CH, CROSS>(g, sp, lds, rp, sd.fen_len, idx, (uint64_t)(rp.first + idx))) break;
         // samples finished by this workgroup, for a host that watches a long batch
         ++done;
-        if (rp.progress && lane == 0)
+        if (rp.progress && threadIdx.x == 0)
             __hip_atomic_store(&rp.progress[blockIdx.x], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
+}
+
+// One persistent launch over the samples of several graphs (a batch): work
+// item idx belongs to the job j with base[j] <= idx < base[j + 1], and is
+// sample first[j] + launch * count[j] + (idx - base[j]) of that job's graph,
+// where `launch` counts the launches of the batch so far (read from device
+// memory, advanced by advance_kernel after each launch).  Every item's f,
+// draws and rounds go to position idx of the batch arrays.
+template <int CH>
+__global__ void __launch_bounds__(WAVE) batch_kernel(BatchArgs a, SlotDev sd, int32_t *ctl,
+                                                     const int64_t *launch) {
+    __shared__ KernelShared<CH> lds;
+    const SlotPtrs sp = slot_ptrs(sd, (size_t)sd.stride);
+    const int64_t L = *launch;
+    while (true) {
+        const int idx = next_item(ctl);
+        if (idx >= a.base[a.k] || stopped(ctl)) break;
+        int j = 0;
+        while (j + 1 < a.k && idx >= a.base[j + 1]) ++j;
+        const BatchJob &job = a.job[j];
+        RunParams rp{};
+        rp.seed = job.seed;
+        rp.mode = RUN_ESTIMATE;
+        rp.walkers = job.walkers;
+        rp.traversal = job.traversal;
+        rp.iter_cap = job.iter_cap;
+        rp.speculate = job.speculate;
+        rp.ctl = ctl;
+        rp.f_out = a.f;
+        rp.steps_out = a.steps;
+        rp.iters_out = a.iters;
+        const uint64_t s = (uint64_t)(job.first + L * (int64_t)(a.base[j + 1] - a.base[j]) + (idx - a.base[j]));
+        if (!process_one<CH, false>(job.g, sp, lds, rp, job.g.two_m + 2, idx, s)) break;
+    }
+}
+
+// Launch counter of a batch: one more launch done; the status word is cleared
+// by the next launch's reset.
+__global__ void advance_kernel(int64_t *launch) {
+    if (threadIdx.x == 0) *launch += 1;
 }
 
 // Resident trees that contain one of the deleted edges {u, v} (as u -> v or
@@ -1368,10 +1472,20 @@ __global__ void zero_i64_kernel(int64_t *p, int64_t len) {
         p[i] = 0;
 }
 
-// Exact sums of f and f^2 (128-bit) and of the draw counts; one block.
+// Exact sums of f and f^2 (128-bit) and of the draw counts of items
+// base[b] .. base[b+1]-1 into out[b], one block b per range (a single range:
+// base = {0, count}).
+struct Ranges {
+    int32_t base[BATCH_MAX + 1];
+};
+
 __global__ void __launch_bounds__(256) reduce_kernel(const int64_t *f, const int64_t *steps,
-                                                     const int64_t *iters, int32_t count,
-                                                     ReduceOut *out) {
+                                                     const int64_t *iters, Ranges r, ReduceOut *outs) {
+    const int32_t lo = r.base[blockIdx.x], count = r.base[blockIdx.x + 1] - lo;
+    f += lo;
+    if (steps) steps += lo;
+    if (iters) iters += lo;
+    ReduceOut *out = outs + blockIdx.x;
     __shared__ unsigned __int128 sh_s[256];
     __shared__ unsigned __int128 sh_q[256];
     __shared__ int64_t sh_t[256];
@@ -1457,7 +1571,34 @@ int persistent_blocks_per_cu(int chains) {
 
 hipError_t launch_reduce(const int64_t *f, const int64_t *steps, const int64_t *iters, int32_t count,
                          ReduceOut *out, hipStream_t stream) {
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, stream, f, steps, iters, count, out);
+    Ranges r{};
+    r.base[0] = 0;
+    r.base[1] = count;
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, stream, f, steps, iters, r, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs &a, const SlotDev &s, int32_t *ctl, int64_t *launch, ReduceOut *out,
+                        int chains, int slots, hipStream_t stream) {
+    if (a.k < 1 || a.k > BATCH_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reset_ctl_kernel, dim3(1), dim3(64), 0, stream, ctl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+#define KC_CASE(C)                                                                                \
+    if (chains == C) {                                                                           \
+        hipLaunchKernelGGL(batch_kernel<C>, dim3(slots), dim3(WAVE), 0, stream, a, s, ctl, launch); \
+        e = hipGetLastError();                                                                   \
+    }
+    e = hipErrorInvalidValue;
+    KC_CHAIN_VARIANTS(KC_CASE)
+#undef KC_CASE
+    if (e != hipSuccess) return e;
+    Ranges r{};
+    for (int j = 0; j <= a.k; ++j) r.base[j] = a.base[j];
+    hipLaunchKernelGGL(reduce_kernel, dim3(a.k), dim3(256), 0, stream, a.f, a.steps, a.iters, r, out);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, stream, launch);
     return hipGetLastError();
 }
 

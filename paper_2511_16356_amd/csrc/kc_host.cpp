@@ -214,9 +214,16 @@ int kc_host::default_slots(const kc_graph *g) {
     return cus * per_cu;
 }
 
-namespace {
 
-}  // namespace
+// Samples in flight for a launch of `count` samples on up to `slots` slots:
+// as many as give every wave of samples the same size (ceil(count / waves)
+// for the fewest waves), so that a launch does not end with a wave of a few
+// samples running nearly alone.
+int kc_host::balanced_slots(int slots, int64_t count) {
+    if (slots < 1 || count <= slots) return slots;
+    const int64_t waves = (count + slots - 1) / slots;
+    return (int)((count + waves - 1) / waves);
+}
 
 // The graph's device arrays as the kernels see them.
 kc::GraphDev kc_host::graph_dev(const kc_graph *g) {
@@ -238,21 +245,18 @@ kc::GraphDev kc_host::graph_dev(const kc_graph *g) {
     return gd;
 }
 
-namespace {
-
-}  // namespace
 
 // The options of g that every launch carries.
 void kc_host::fill_run_options(const kc_graph *g, kc::RunParams &rp) {
     rp.walkers = g->walkers;
     rp.traversal = g->traversal;
+    // the speculative first draw pays off when most draws land past the six inline
+    // neighbours of a vertex record: by default when the mean degree exceeds 12
+    rp.speculate = g->speculate_opt == 1 || (g->speculate_opt == 2 && g->two_m > 12 * g->n);
     rp.iter_cap = g->step_limit > 0 ? g->step_limit : 1024 * g->n + (1 << 22);
     rp.ctl = g->d_ctl;
 }
 
-namespace {
-
-}  // namespace
 
 // Launch the persistent kernel on a prepared workspace and check the status
 // its workgroups report.
@@ -288,6 +292,7 @@ kc_status run_persistent(kc_graph *g, kc::RunParams rp, hipStream_t stream) {
     int slots = 0;
     kc_status st = ensure_workspace(g, want, trav, fen, stream, &slots);
     if (st != KC_OK) return st;
+    slots = balanced_slots(slots, rp.count);
     kc::SlotDev sd;
     sd.tagw = g->d_tagw;
     sd.arrow = g->d_arrow;
@@ -818,6 +823,10 @@ kc_status kc_set_option(kc_graph *g, int option, int64_t value) {
                                                     "re-initialise the set to change the maintenance");
             g->maint = (int32_t)value;
             return KC_OK;
+        case 9: /* KC_OPT_SPECULATE */
+            if (value < 0 || value > 2) return fail(KC_ERR_INVALID, "speculate must be 0, 1 or 2");
+            g->speculate_opt = (int32_t)value;
+            return KC_OK;
         case KC_OPT_START_ORDER: {
             if (value < 0 || value > 2) return fail(KC_ERR_INVALID, "start order must be 0, 1 or 2");
             const std::vector<int32_t> ord = start_order_of(g->bfs_order, (int)value);
@@ -871,10 +880,12 @@ kc_status kc_sample_trees(kc_graph *g, uint64_t seed, int64_t first_sample, int3
     return run_persistent(g, rp, (hipStream_t)hip_stream);
 }
 
+}  // extern "C"
+
 // kappa and its standard error from the exact sums of a result (Theorem 3.3):
 // kappa = sum f / (2 m count), one correctly rounded conversion and one
 // division; std_error = the sample standard deviation of f / 2m over sqrt(count).
-static void finish_result(int64_t two_m, kc_result *res) {
+void kc_host::finish_result(int64_t two_m, kc_result *res) {
     const __int128 s1 = (__int128)(((unsigned __int128)(uint64_t)res->sum_f_hi << 64) | res->sum_f_lo);
     const unsigned __int128 s2 = ((unsigned __int128)res->sum_f2_hi << 64) | res->sum_f2_lo;
     const int64_t count = res->count;
@@ -887,8 +898,6 @@ static void finish_result(int64_t two_m, kc_result *res) {
         res->std_error = std::nan("");
     }
 }
-
-}  // extern "C"
 
 kc_status kc_host::finish_reduce(kc_graph *g, int32_t count, const int64_t *f, const int64_t *steps,
                                const int64_t *iters, kc_result *res, hipStream_t stream) {

@@ -24,6 +24,7 @@ struct kc_graph {
     int32_t chains = 1024;
     int32_t slots_opt = 0;
     int32_t trav_opt = KC_TRAV_AUTO;
+    int32_t speculate_opt = 2;        // speculative first draw: 0 off, 1 on, 2 by mean degree
     int64_t step_limit = 0;
     int64_t mem_budget = 0;
     int64_t graph_bytes = 0;
@@ -93,6 +94,8 @@ kc_status fail(kc_status st, const char *fmt, ...);
 int64_t slot_bytes(const kc_graph *g, bool trav, bool fen);
 // Samples in flight when the graph's slots option is 0: resident workgroups of the kernel.
 int default_slots(const kc_graph *g);
+// Slots that split `count` samples into equal waves (at most `slots`).
+int balanced_slots(int slots, int64_t count);
 // The graph's device arrays as the kernels see them.
 kc::GraphDev graph_dev(const kc_graph *g);
 // The options of g that every launch carries (walkers, traversal, step cap, status word).
@@ -100,6 +103,8 @@ void fill_run_options(const kc_graph *g, kc::RunParams &rp);
 // Launch the persistent kernel on a prepared workspace and check the status it reports.
 kc_status launch_checked(kc_graph *g, const kc::SlotDev &sd, const kc::RunParams &rp, int slots,
                          hipStream_t stream);
+// kappa and its standard error from the exact sums and count already in *res (Theorem 3.3).
+void finish_result(int64_t two_m, kc_result *res);
 // Exact sums of f (and draws, sampler rounds) over count samples into *res, with kappa
 // and its standard error (Theorem 3.3).
 kc_status finish_reduce(kc_graph *g, int32_t count, const int64_t *f, const int64_t *steps,

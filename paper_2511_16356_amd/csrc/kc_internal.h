@@ -40,7 +40,28 @@ struct SlotDev {
     int4 *ord;       // [slots*n] finished vertices {v, parent, vol} and leaves {v, parent, deg}
     int32_t *grp;    // [slots*(n+1)] completion group boundaries
     int64_t *fen;    // [slots*fen_len] Fenwick tree (sweep traversal only)
-    int64_t fen_len; // 2m + 2 (0 if not allocated)
+    int64_t fen_len; // per-slot length of fen: 2m + 2 (0 if not allocated)
+    int64_t stride;  // vertices per slot in the n-sized arrays (a batch: its largest graph's n)
+};
+
+// One graph's share of a batch launch (batch_kernel).
+struct BatchJob {
+    GraphDev g;
+    uint64_t seed;
+    int64_t first;      // sample index of the job's first item at launch 0
+    int64_t iter_cap;   // sampler rounds per sample
+    int32_t walkers, traversal, speculate;
+};
+
+constexpr int BATCH_MAX = 8;  // graphs in one batch launch
+
+// Kernel arguments of a batch launch: k jobs; job j owns work items
+// base[j] .. base[j+1]-1, whose f, draws and rounds go to f/steps/iters[idx].
+struct BatchArgs {
+    int32_t k;
+    int32_t base[BATCH_MAX + 1];
+    BatchJob job[BATCH_MAX];
+    int64_t *f, *steps, *iters;
 };
 
 enum RunMode { RUN_SAMPLE = 0, RUN_ESTIMATE = 1, RUN_EVALUATE = 2, RUN_CURRENT = 3, RUN_CROSS = 4 };
@@ -58,6 +79,8 @@ struct RunParams {
     int32_t mode;       // RunMode
     int32_t traversal;  // 1 walk, 2 sweep
     int64_t iter_cap;   // sampler iterations per sample
+    int32_t speculate;  // 1: a claim also computes the vertex's first draw (k = 0) and fetches
+                        //    its row entry in the same round; results do not depend on it
     const int32_t *parents_in; // RUN_EVALUATE input [count*n]
     int32_t *parents_out;      // RUN_SAMPLE  [count*n]
     uint32_t *cnt_out;         // RUN_SAMPLE  [count*n] (optional)
@@ -97,6 +120,10 @@ hipError_t launch_persistent(const GraphDev &g, const SlotDev &s, const RunParam
                              int slots, hipStream_t stream);
 hipError_t launch_reduce(const int64_t *f, const int64_t *steps, const int64_t *iters, int32_t count,
                          ReduceOut *out, hipStream_t stream);
+// A batch: reset of the status word, the persistent launch over every job, the
+// exact sums of each job into out[j], and one more on the launch counter.
+hipError_t launch_batch(const BatchArgs &a, const SlotDev &s, int32_t *ctl, int64_t *launch, ReduceOut *out,
+                        int chains, int slots, hipStream_t stream);
 hipError_t launch_zero_i64(int64_t *p, int64_t len, hipStream_t stream);
 hipError_t launch_reroot(int32_t *par, int32_t count, int64_t n, int32_t u, int32_t v, int32_t r,
                          hipStream_t stream);

@@ -10,12 +10,22 @@ Scheduling (continuous batching): every graph has its own HIP stream and one
 worker thread that takes that graph's requests in arrival order, so requests
 on different graphs run on the device at the same time and a request is
 started as soon as its graph is free and the HBM it may need is available.
-Admission is by HBM footprint: an update may allocate at most its share of
-the device budget (``KC_OPT_MEM_BUDGET``), and it starts only when that
-share is free; queries need no workspace.  Requests on one graph run in
-arrival order, so every graph's results are the same alone and in any mix.
-For comparison, ``one_at_a_time`` serves every request in one worker, one
-after another (the plain form).
+Requests on one graph run in arrival order, so every graph's results are the
+same alone and in any mix.  For comparison, ``one_at_a_time`` serves every
+request in one worker, one after another (the plain form).
+
+Admission is by HBM footprint, against one device budget:
+  - a resident graph holds, for as long as it is resident, its graph arrays
+    (``kc_graph_info.device_bytes``), its trees (4 n bytes each) and their f
+    values (16 bytes each), and the workspace the library may keep for it
+    (its ``KC_OPT_MEM_BUDGET``: at most ``workspace_share``, and no more than
+    its trees' worth of samples in flight, ``sample_bytes`` each);
+  - an update additionally holds, while it runs, the temporary buffers the
+    library allocates for it (at most two parent arrays per resident tree);
+  - a query allocates nothing.
+A graph whose footprint can never fit is refused with KC_ERR_NOMEM; one that
+does not fit now waits until removed graphs free memory (or is refused after
+``timeout``).
 
 This module only orchestrates calls into the HIP library; every step of the
 estimator and of the maintenance runs in the library's kernels.
@@ -46,20 +56,27 @@ class Request:
 
 
 class _Budget:
-    """Device bytes shared by the requests in flight."""
+    """Device bytes held by resident graphs and by the requests in flight."""
 
     def __init__(self, total: int):
         self.total = total
         self.free = total
         self.cv = threading.Condition()
 
-    def acquire(self, nbytes: int):
-        nbytes = min(nbytes, self.total)
+    def acquire(self, nbytes: int, timeout: float = None) -> bool:
+        """Take nbytes once they are free (False after `timeout` seconds, or at
+        once if nbytes exceeds the whole budget)."""
+        if nbytes > self.total:
+            return False
+        end = None if timeout is None else time.perf_counter() + timeout
         with self.cv:
             while self.free < nbytes:
-                self.cv.wait()
+                left = None if end is None else end - time.perf_counter()
+                if left is not None and left <= 0:
+                    return False
+                self.cv.wait(left)
             self.free -= nbytes
-        return nbytes
+        return True
 
     def release(self, nbytes: int):
         with self.cv:
@@ -67,18 +84,35 @@ class _Budget:
             self.cv.notify_all()
 
 
+def resident_bytes(info: dict, samples: int, workspace: int) -> int:
+    """Device bytes a resident graph holds: graph arrays, `samples` parent
+    arrays of 4 n bytes, their f (8 bytes, and 8 more for its recomputation
+    buffer) and the workspace cap."""
+    return int(info["device_bytes"]) + samples * (4 * int(info["n"]) + 16) + workspace
+
+
+def update_bytes(info: dict, samples: int) -> int:
+    """Temporary device bytes an update may allocate: replacement trees and the
+    saved rows of transformed trees, each at most one parent array per tree."""
+    return 2 * samples * 4 * int(info["n"])
+
+
 class Server:
     """Resident graphs and their request workers."""
 
-    def __init__(self, budget_bytes: int, update_share: int, maintenance: int = KC_MAINT_BASIC,
+    def __init__(self, budget_bytes: int, workspace_share: int, maintenance: int = KC_MAINT_BASIC,
                  one_at_a_time: bool = False):
-        """one_at_a_time: the plain form for comparison, one worker for all
-        graphs, so requests run strictly one after another in arrival order."""
+        """budget_bytes: device bytes the server may hold in all; workspace_share:
+        the most workspace one graph's estimates and updates may keep
+        (KC_OPT_MEM_BUDGET); one_at_a_time: the plain form for comparison, one
+        worker for all graphs, so requests run strictly one after another."""
         self.one_at_a_time = one_at_a_time
         self.budget = _Budget(budget_bytes)
-        self.update_share = update_share   # device bytes one update may use
+        self.workspace_share = workspace_share
         self.maintenance = maintenance     # KC_MAINT_BASIC (Algorithm 2) or KC_MAINT_IMPROVED (Algorithm 3)
         self.graphs = {}
+        self.held = {}       # gid -> resident bytes charged
+        self.tmp = {}        # gid -> bytes an update of it charges
         self.queues = {}
         self.threads = {}
         self.streams = {}
@@ -86,14 +120,30 @@ class Server:
         self.done_cv = threading.Condition()
         self.submitted = 0
 
-    def add_graph(self, gid: int, g, seed: int, samples: int):
+    def add_graph(self, gid: int, g, seed: int, samples: int, timeout: float = None):
+        """Make g resident with `samples` trees once its footprint fits the
+        budget (KcError KC_ERR_NOMEM if it never can, or not within `timeout`)."""
         import torch
         stream = torch.cuda.Stream()
         G = Graph.from_graph(g, stream=stream)
-        G.set_option(KC_OPT_MEM_BUDGET, self.update_share)
-        G.set_option(KC_OPT_MAINTENANCE, self.maintenance)
-        G.samples_init(seed, samples, stream=stream)
+        info = G.info
+        workspace = min(self.workspace_share, samples * int(info["sample_bytes"]))
+        need = resident_bytes(info, samples, workspace)
+        if not self.budget.acquire(need, timeout):
+            G.close()
+            raise KcError(3, "graph %s needs %d device bytes resident; %d of %d are free" %
+                          (gid, need, self.budget.free, self.budget.total))
+        try:
+            G.set_option(KC_OPT_MEM_BUDGET, workspace)
+            G.set_option(KC_OPT_MAINTENANCE, self.maintenance)
+            G.samples_init(seed, samples, stream=stream)
+        except Exception:
+            G.close()
+            self.budget.release(need)
+            raise
         self.graphs[gid] = G
+        self.held[gid] = need
+        self.tmp[gid] = update_bytes(info, samples)
         self.streams[gid] = stream
         if self.one_at_a_time and self.threads:
             self.queues[gid] = next(iter(self.queues.values()))
@@ -103,6 +153,15 @@ class Server:
         t = threading.Thread(target=self._worker, args=(q,), daemon=True)
         self.threads[gid] = t
         t.start()
+
+    def remove_graph(self, gid: int):
+        """Free a resident graph once its queued requests are done; its bytes
+        return to the budget."""
+        self.drain()
+        G = self.graphs.pop(gid)
+        G.close()
+        self.budget.release(self.held.pop(gid))
+        self.tmp.pop(gid, None)
 
     def submit(self, req: Request):
         with self.done_cv:
@@ -120,7 +179,11 @@ class Server:
             held = 0
             try:
                 if req.kind == "update":
-                    held = self.budget.acquire(self.update_share)
+                    held = self.tmp[req.gid]
+                    if not self.budget.acquire(held):
+                        held = 0
+                        raise KcError(3, "an update of graph %s needs %d temporary device bytes, more than "
+                                      "the whole budget" % (req.gid, self.tmp[req.gid]))
                 req.t_start = time.perf_counter()
                 if req.kind == "query":
                     req.result = G.samples_query(stream=stream)
@@ -154,9 +217,11 @@ class Server:
             q.put(None)
         for t in self.threads.values():
             t.join()
-        for G in self.graphs.values():
+        for gid, G in self.graphs.items():
             G.close()
+            self.budget.release(self.held.get(gid, 0))
         self.graphs.clear()
+        self.held.clear()
 
 
 def latency_stats(reqs, kind: str):

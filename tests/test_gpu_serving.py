@@ -43,7 +43,7 @@ def _ops(gen, g, seed, rounds):
 
 def _serve(kc, graphs, ops, order, maintenance=0, one_at_a_time=False):
     from paper_2511_16356_amd.serve import Server, Request
-    srv = Server(budget_bytes=8 << 30, update_share=2 << 30, maintenance=maintenance, one_at_a_time=one_at_a_time)
+    srv = Server(budget_bytes=8 << 30, workspace_share=2 << 30, maintenance=maintenance, one_at_a_time=one_at_a_time)
     try:
         for gid in graphs:
             srv.add_graph(gid, graphs[gid], seed=100 + gid, samples=128)
