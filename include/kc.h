@@ -227,6 +227,27 @@ kc_status kc_estimate(kc_graph *g, uint64_t seed, int64_t first_sample, int32_t 
 kc_status kc_combine_results(const kc_graph *g, const kc_result *parts, int32_t k, kc_result *out);
 
 /*
+ * kc_estimate for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and results as kc_estimate (bit for bit); it allocates
+ * nothing (no hipMalloc, hipFree or allocating library call).  Its workspace
+ * is one static device array of 256 MiB per device, held until the process
+ * ends: the per-sample results first (24 bytes per sample, 16 when f_out is
+ * given), then as many samples in flight as fit (kc_graph_info.sample_bytes
+ * each, at most the slots option or the kernel's resident workgroups).
+ * Every call on a device shares that array and leaves the last call's
+ * contents in it, so calls that overlap on one device race: callers
+ * serialise them.  The graph must have been created (kc_graph_create
+ * allocates its arrays); this call then allocates nothing.
+ *   result : HOST pointer (required); f_out : DEVICE pointer or NULL
+ * Errors: KC_ERR_INVALID (count < 1, NULL graph or result), KC_ERR_NOMEM (the
+ * per-sample results, or one sample in flight, do not fit the static
+ * workspace), KC_ERR_LIMIT, KC_ERR_DEVICE.
+ */
+kc_status kc_estimate_static(kc_graph *g, uint64_t seed, int64_t first_sample, int32_t count,
+                             kc_result *result, int64_t *f_out, void *hip_stream);
+
+/*
  * Evaluate f for caller-supplied rooted spanning trees (no sampling).
  *   parents : DEVICE pointer, count*n int32 parent arrays rooted at the
  *             graph's root (root -> -1; the root's entry is not read).

@@ -32,7 +32,7 @@ KC_MAINT_BASIC, KC_MAINT_IMPROVED = 0, 1
 EXPORTS = ("kc_graph_create", "kc_graph_destroy", "kc_graph_get_info", "kc_set_option", "kc_set_tau0",
            "kc_reserve", "kc_progress",
            "kc_samples_init", "kc_samples_query", "kc_samples_get", "kc_samples_weights", "kc_apply_updates",
-           "kc_sample_trees", "kc_estimate", "kc_evaluate_trees", "kc_combine_results",
+           "kc_sample_trees", "kc_estimate", "kc_estimate_static", "kc_evaluate_trees", "kc_combine_results",
            "kc_status_string",
            "kc_last_error")
 
@@ -101,6 +101,8 @@ def library() -> ctypes.CDLL:
     lib.kc_estimate.argtypes = [p, u64, i64, i32, ctypes.POINTER(_Result), p, p, p]
     lib.kc_combine_results.restype = ctypes.c_int
     lib.kc_combine_results.argtypes = [p, ctypes.POINTER(_Result), i32, ctypes.POINTER(_Result)]
+    lib.kc_estimate_static.restype = ctypes.c_int
+    lib.kc_estimate_static.argtypes = [p, u64, i64, i32, ctypes.POINTER(_Result), p, p]
     lib.kc_evaluate_trees.restype = ctypes.c_int
     lib.kc_evaluate_trees.argtypes = [p, p, i32, p, p]
     lib.kc_status_string.restype = ctypes.c_char_p
@@ -287,6 +289,17 @@ class Graph:
                                      _dptr(stp), _stream(stream)))
         est = _estimate_of(res)
         return (est, f, stp) if per_sample else est
+
+    def estimate_static(self, seed: int, first: int, count: int, per_sample: bool = False, stream=None):
+        """kc_estimate_static: the same estimate with no device allocation (the
+        library's static workspace); with per_sample, also the f [count] CUDA tensor."""
+        import torch
+        f = torch.empty((count,), dtype=torch.int64, device="cuda") if per_sample else None
+        res = _Result()
+        _check(library().kc_estimate_static(self._h, seed, first, count, ctypes.byref(res), _dptr(f),
+                                            _stream(stream)))
+        est = _estimate_of(res)
+        return (est, f) if per_sample else est
 
     def combine(self, estimates) -> Estimate:
         """One estimate over all samples of several estimates of this graph
