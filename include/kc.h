@@ -99,9 +99,14 @@ enum {
     KC_OPT_CHAINS = 7,     /* walks one sample may hold open at once: 1024 (default) or 2048.
                               More finish one sample in fewer rounds; fewer let more samples
                               run at once.  Results do not depend on it. */
-    KC_OPT_MAINTENANCE = 8 /* KC_MAINT_*: how kc_apply_updates maintains the resident set;
+    KC_OPT_MAINTENANCE = 8, /* KC_MAINT_*: how kc_apply_updates maintains the resident set;
                               may change while the set's weights are all equal (always under
                               basic maintenance), else KC_ERR_INVALID */
+    KC_OPT_SPECULATE = 9   /* speculative first draw: a walker that claims a vertex also computes
+                              that vertex's first draw (Philox counter k = 0) and requests its row
+                              entry in the same round, used when the claim finds no earlier draw
+                              there.  0 = off, 1 = on, 2 = when the mean degree exceeds 12
+                              (default).  Results do not depend on it. */
 };
 
 /* Sample maintenance of a resident set (section 4). */
@@ -246,6 +251,77 @@ kc_status kc_combine_results(const kc_graph *g, const kc_result *parts, int32_t 
  */
 kc_status kc_estimate_static(kc_graph *g, uint64_t seed, int64_t first_sample, int32_t count,
                              kc_result *result, int64_t *f_out, void *hip_stream);
+
+/*
+ * Batches (section 5, Exp-VI parallelises across samples; here the samples of
+ * several graphs of any sizes share one persistent launch).  A batch holds up
+ * to 8 graphs, one job each: launch number L (from 0) of the batch estimates
+ * samples firsts[j] + L*counts[j] .. firsts[j] + (L+1)*counts[j] - 1 of graph
+ * j, each tree bit-identical to kc_estimate's for the same (seed, s).  The
+ * launch sequence (status reset, the persistent kernel over every job, the
+ * exact sums of each job, the launch counter) is captured once as a HIP graph
+ * at creation and replayed by kc_batch_launch with no host round trip: the
+ * status and sums stay on the device until kc_batch_results reads them.
+ * Launch options (step limit, walkers, traversal, speculative draw) are each
+ * graph's; the chain-table size, samples in flight and memory budget are the
+ * first graph's.  The batch owns its workspace (slots sized for the largest
+ * graph) and copies of the graphs' device array pointers: the graphs must
+ * outlive the batch and must not be updated (kc_apply_updates, kc_set_tau0)
+ * while it exists.
+ */
+typedef struct kc_batch kc_batch;
+
+/*
+ *   graphs : HOST array of k graph handles (1 <= k <= 8)
+ *   seeds, firsts, counts : HOST arrays of k entries (counts >= 1, firsts >= 0,
+ *            sum of counts < 2^31)
+ *   out    : receives the batch
+ * Errors: KC_ERR_INVALID, KC_ERR_NOMEM (one sample of the largest graph does not
+ * fit the budget), KC_ERR_DEVICE (capture failed).
+ */
+kc_status kc_batch_create(kc_graph *const *graphs, int32_t k, const uint64_t *seeds, const int64_t *firsts,
+                          const int32_t *counts, void *hip_stream, kc_batch **out);
+
+/* Enqueue the next launch of the batch on hip_stream (a graph replay); returns
+ * at once.  Launches on one batch must be ordered (one stream). */
+kc_status kc_batch_launch(kc_batch *b, void *hip_stream);
+
+/* Wait for hip_stream, then read the last launch's status and results:
+ * results HOST [k] (as kc_estimate's for each job), launches HOST or NULL
+ * (launches completed so far).  Errors: the last launch's KC_ERR_LIMIT or
+ * KC_ERR_DEVICE (results then unspecified). */
+kc_status kc_batch_results(kc_batch *b, kc_result *results, int64_t *launches, void *hip_stream);
+
+/* Copy job j's per-sample f of the last launch (counts[j] int64) to the DEVICE
+ * pointer f_out. */
+kc_status kc_batch_f(const kc_batch *b, int32_t j, int64_t *f_out, void *hip_stream);
+
+/* Free the batch (its captured graph and workspace).  NULL is accepted. */
+kc_status kc_batch_destroy(kc_batch *b);
+
+/* Launch options chosen by kc_autotune. */
+typedef struct {
+    int32_t chains, slots, walkers, traversal, speculate; /* as KC_OPT_* values */
+    int32_t from_cache;   /* 1 if read from the cache file, 0 if measured now */
+    int32_t trials;       /* trial estimates run */
+    double samples_per_s; /* rate of the chosen options in their trial (0 from the cache) */
+} kc_tune_result;
+
+/*
+ * Choose g's launch options for estimates of `count` samples by timing short
+ * trial estimates (between one and two launches' worth of samples, on sample
+ * ids from 2^40 upward): starting from the current options, one option at a
+ * time (speculative draw, traversal for tau0 depth <= 64, chain-table size,
+ * 3/4 and 1/2 of the samples in flight, walkers 32/64), a change kept only for
+ * a gain above 2%.  The choice is applied to g (kc_set_option) and appended to
+ * cache_path (HOST string or NULL: no cache) as one JSON line keyed by device
+ * architecture, n, 2m, max degree, tau0 depth and count; a later call with the
+ * same key applies the cached choice without trials.  No option changes any
+ * result (trees, f and estimates are bit-identical).
+ *   out : HOST pointer
+ * Errors: those of kc_estimate (the options are then put back).
+ */
+kc_status kc_autotune(kc_graph *g, int32_t count, const char *cache_path, kc_tune_result *out, void *hip_stream);
 
 /*
  * Evaluate f for caller-supplied rooted spanning trees (no sampling).

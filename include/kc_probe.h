@@ -30,6 +30,23 @@ int kc_probe_stream_read(const void *buf, size_t bytes, int64_t *sink, double *g
  * lines read per second. */
 int kc_probe_random_read(const void *buf, size_t bytes, int64_t reads, int64_t *sink, double *sectors_per_s);
 
+/* Streaming read with `inflight` (1, 2, 4 or 8) 16-byte loads in flight per
+ * thread and `blocks_per_cu` (1..64) 256-thread blocks per compute unit;
+ * *gbps receives bytes / time in GB/s. */
+int kc_probe_stream_sweep(const void *buf, size_t bytes, int inflight, int blocks_per_cu, int64_t *sink,
+                          double *gbps);
+
+/* Random line reads in the estimator's shapes, for a sweep of the settings:
+ *   shape    : 0 = each lane reads 8 bytes of its own random 64-byte line,
+ *              1 = 16 bytes of its own line, 2 = four lanes read one line's
+ *              four 16-byte quarters
+ *   inflight : reads each thread keeps in flight (1, 2, 4, 8, 16 or 32)
+ *   blocks_per_cu : 256-thread blocks per compute unit (1..64)
+ * About 2^28 line reads per launch; *lines_per_s receives distinct 64-byte
+ * lines read per second. */
+int kc_probe_random_sweep(const void *buf, size_t bytes, int shape, int inflight, int blocks_per_cu,
+                          int64_t *sink, double *lines_per_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,13 +27,15 @@ KC_OPT_CHAINS = 7
 KC_TAU0_BFS, KC_TAU0_DFS, KC_TAU0_GIVEN = 0, 1, 2
 KC_OPT_MAINTENANCE = 8
 KC_MAINT_BASIC, KC_MAINT_IMPROVED = 0, 1
+KC_OPT_SPECULATE = 9
 
 # every symbol include/kc.h declares
 EXPORTS = ("kc_graph_create", "kc_graph_destroy", "kc_graph_get_info", "kc_set_option", "kc_set_tau0",
            "kc_reserve", "kc_progress",
            "kc_samples_init", "kc_samples_query", "kc_samples_get", "kc_samples_weights", "kc_apply_updates",
            "kc_sample_trees", "kc_estimate", "kc_estimate_static", "kc_evaluate_trees", "kc_combine_results",
-           "kc_status_string",
+           "kc_batch_create", "kc_batch_launch", "kc_batch_results", "kc_batch_f", "kc_batch_destroy",
+           "kc_autotune", "kc_status_string",
            "kc_last_error")
 
 
@@ -49,6 +51,12 @@ class _Info(ctypes.Structure):
                 ("depth0", ctypes.c_int32), ("max_degree", ctypes.c_int32),
                 ("traversal", ctypes.c_int32), ("device_bytes", ctypes.c_int64), ("tau0", ctypes.c_int32),
                 ("sample_bytes", ctypes.c_int64)]
+
+
+class _Tune(ctypes.Structure):
+    _fields_ = [("chains", ctypes.c_int32), ("slots", ctypes.c_int32), ("walkers", ctypes.c_int32),
+                ("traversal", ctypes.c_int32), ("speculate", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("trials", ctypes.c_int32), ("samples_per_s", ctypes.c_double)]
 
 
 class _Result(ctypes.Structure):
@@ -103,6 +111,18 @@ def library() -> ctypes.CDLL:
     lib.kc_combine_results.argtypes = [p, ctypes.POINTER(_Result), i32, ctypes.POINTER(_Result)]
     lib.kc_estimate_static.restype = ctypes.c_int
     lib.kc_estimate_static.argtypes = [p, u64, i64, i32, ctypes.POINTER(_Result), p, p]
+    lib.kc_batch_create.restype = ctypes.c_int
+    lib.kc_batch_create.argtypes = [p, i32, p, p, p, p, ctypes.POINTER(p)]
+    lib.kc_batch_launch.restype = ctypes.c_int
+    lib.kc_batch_launch.argtypes = [p, p]
+    lib.kc_batch_results.restype = ctypes.c_int
+    lib.kc_batch_results.argtypes = [p, ctypes.POINTER(_Result), ctypes.POINTER(i64), p]
+    lib.kc_batch_f.restype = ctypes.c_int
+    lib.kc_batch_f.argtypes = [p, i32, p, p]
+    lib.kc_batch_destroy.restype = ctypes.c_int
+    lib.kc_batch_destroy.argtypes = [p]
+    lib.kc_autotune.restype = ctypes.c_int
+    lib.kc_autotune.argtypes = [p, i32, ctypes.c_char_p, ctypes.POINTER(_Tune), p]
     lib.kc_evaluate_trees.restype = ctypes.c_int
     lib.kc_evaluate_trees.argtypes = [p, p, i32, p, p]
     lib.kc_status_string.restype = ctypes.c_char_p
@@ -309,6 +329,15 @@ class Graph:
         _check(library().kc_combine_results(self._h, parts, len(estimates), ctypes.byref(out)))
         return _estimate_of(out)
 
+    def autotune(self, count: int, cache_path=None, stream=None) -> dict:
+        """kc_autotune: choose and apply this graph's launch options for estimates
+        of `count` samples (cached in the JSON-lines file cache_path)."""
+        out = _Tune()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(library().kc_autotune(self._h, count, path, ctypes.byref(out), _stream(stream)))
+        self.info = self._info()
+        return {k: getattr(out, k) for k, _ in _Tune._fields_}
+
     def evaluate_trees(self, parents, stream=None):
         """f for given rooted parent arrays (CUDA int32 tensor [count, n])."""
         import torch
@@ -322,6 +351,59 @@ class Graph:
     def close(self):
         if getattr(self, "_h", None):
             library().kc_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """kc_batch: one captured persistent launch over the samples of several
+    graphs; launch L estimates samples firsts[j] + L*counts[j] .. of graph j."""
+
+    def __init__(self, graphs, seeds, firsts, counts, stream=None):
+        lib = library()
+        k = len(graphs)
+        hs = (ctypes.c_void_p * k)(*[g._h.value for g in graphs])
+        sd = np.ascontiguousarray(seeds, dtype=np.uint64)
+        fi = np.ascontiguousarray(firsts, dtype=np.int64)
+        co = np.ascontiguousarray(counts, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(lib.kc_batch_create(hs, k, sd.ctypes.data_as(ctypes.c_void_p), fi.ctypes.data_as(ctypes.c_void_p),
+                                   co.ctypes.data_as(ctypes.c_void_p), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.k = k
+        self.counts = [int(c) for c in co]
+        self.graphs = list(graphs)  # the graphs must outlive the batch
+
+    def launch(self, stream=None):
+        _check(library().kc_batch_launch(self._h, _stream(stream)))
+
+    def results(self, stream=None):
+        """(per-graph Estimates of the last launch, launches done so far)."""
+        res = (_Result * self.k)()
+        nl = ctypes.c_int64(0)
+        _check(library().kc_batch_results(self._h, res, ctypes.byref(nl), _stream(stream)))
+        return [_estimate_of(r) for r in res], nl.value
+
+    def f(self, j: int, stream=None):
+        import torch
+        out = torch.empty((self.counts[j],), dtype=torch.int64, device="cuda")
+        _check(library().kc_batch_f(self._h, j, _dptr(out), _stream(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().kc_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

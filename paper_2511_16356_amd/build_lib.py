@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkc_mi355x.so")
-SOURCES = ["kc_device.hip", "kc_host.cpp", "kc_static.hip"]
+SOURCES = ["kc_device.hip", "kc_host.cpp", "kc_static.hip", "kc_batch.cpp", "kc_tune.cpp"]
 # memory-ceiling probes used by the benchmark's roofline calibration
 PROBE_LIB = os.path.join(HERE, "libkc_probe.so")
 PROBE_SOURCES = ["kc_probe.hip"]

@@ -93,7 +93,7 @@ void free_workspace(kc_graph *g) {
     g->d_cstart = nullptr;
     g->d_rec = nullptr; g->d_ord = nullptr;
     g->d_grp = nullptr; g->d_fen = nullptr;
-    g->ws_slots = 0; g->ws_trav = g->ws_fen = false;
+    g->ws_slots = 0; g->ws_asked = 0; g->ws_trav = g->ws_fen = false;
 }
 
 void free_graph_arrays(kc_graph *g);
@@ -147,8 +147,10 @@ kc_status ensure_workspace(kc_graph *g, int want, bool trav, bool fen, hipStream
     if (want < 1) want = 1;
     // the sweep's per-slot stride is 2m + 2: a graph that gained edges needs a new buffer
     const bool fen_small = fen && g->ws_fen && g->ws_fen_len < g->two_m + 2;
-    if (g->ws_slots >= want && (!trav || g->ws_trav) && (!fen || g->ws_fen) && !fen_small) {
-        *got = want;
+    // a workspace asked for at least `want` slots is kept, also when the budget held fewer
+    if ((g->ws_slots >= want || g->ws_asked >= want) && (!trav || g->ws_trav) && (!fen || g->ws_fen) &&
+        !fen_small) {
+        *got = std::min(want, g->ws_slots);
         return KC_OK;
     }
     trav = trav || g->ws_trav;
@@ -180,6 +182,7 @@ kc_status ensure_workspace(kc_graph *g, int want, bool trav, bool fen, hipStream
         HIP_TRY(kc::launch_zero_i64(g->d_fen, len, stream));
     }
     g->ws_slots = slots;
+    g->ws_asked = want;
     g->ws_trav = trav;
     g->ws_fen = fen;
     g->ws_fen_len = fen ? g->two_m + 2 : 0;
@@ -812,6 +815,7 @@ kc_status kc_set_option(kc_graph *g, int option, int64_t value) {
         case KC_OPT_MEM_BUDGET:
             if (value < 0) return fail(KC_ERR_INVALID, "memory budget must be >= 0");
             g->mem_budget = value;
+            g->ws_asked = std::min(g->ws_asked, g->ws_slots);  // the next launch re-fits to the new budget
             return KC_OK;
         case KC_OPT_MAINTENANCE:
             if (value != KC_MAINT_BASIC && value != KC_MAINT_IMPROVED)

@@ -57,6 +57,7 @@ struct kc_graph {
     int32_t anc_depth = 0;
     // workspace
     int ws_slots = 0;
+    int ws_asked = 0;         // slots the allocation was asked for (the budget may have held fewer)
     bool ws_trav = false, ws_fen = false;
     int64_t ws_fen_len = 0;  // per-slot Fenwick length the buffer was sized for (2m + 2)
     uint64_t *d_tagw = nullptr, *d_arrow = nullptr;

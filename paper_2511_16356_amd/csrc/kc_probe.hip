@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "../../include/kc_probe.h"
 
 namespace {
@@ -37,6 +39,67 @@ __global__ void __launch_bounds__(BLOCK) random_read_kernel(const int4 *buf, siz
         const int4 *p = buf + line * 4;
         const int4 a = p[0], b = p[1], c = p[2], d = p[3];
         acc += (a.x ^ b.y) + (c.z ^ d.w);
+    }
+    if (acc == 0x7fffffffffffll) sink[0] = acc;
+}
+
+// Streaming read with K 16-byte loads in flight per thread and round.
+template <int K>
+__global__ void __launch_bounds__(BLOCK) stream_sweep_kernel(const int4 *buf, size_t n16, int64_t *sink) {
+    int64_t acc = 0;
+    const size_t stride = (size_t)gridDim.x * BLOCK;
+    for (size_t base = (size_t)blockIdx.x * BLOCK + threadIdx.x; base < n16; base += stride * K) {
+        int4 v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const size_t i = base + (size_t)k * stride;
+            v[k] = i < n16 ? buf[i] : make_int4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc += v[k].x ^ v[k].y ^ v[k].z ^ v[k].w;
+    }
+    if (acc == 0x7fffffffffffll) sink[0] = acc;
+}
+
+// Random reads in the shapes the estimator issues: every lane reads W bytes
+// (8 or 16) from its own pseudo-random 64-byte line, or (Q = 4) four lanes read
+// the four 16-byte quarters of one line; each thread keeps K reads in flight
+// (all K addresses are formed and issued before any result is used).
+__device__ __forceinline__ uint64_t mix(uint64_t t, uint64_t k) {
+    uint64_t h = (t * 0x9E3779B97F4A7C15ull) ^ (k * 0xC2B2AE3D27D4EB4Full);
+    h ^= h >> 31;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 29;
+    return h;
+}
+
+template <int W, int Q, int K>
+__global__ void __launch_bounds__(BLOCK) random_sweep_kernel(const unsigned char *buf, size_t lines, int rounds,
+                                                             int64_t *sink) {
+    const uint64_t t = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const uint64_t line_owner = t / Q;  // Q lanes share one line
+    const int quarter = (int)(t % Q);
+    int64_t acc = 0;
+    for (int r = 0; r < rounds; ++r) {
+        size_t off[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const size_t line = (size_t)(mix(line_owner, (uint64_t)(r * K + k)) % lines);
+            off[k] = line * 64 + (size_t)quarter * 16;
+        }
+        if (W == 8) {
+            int64_t v[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] = *reinterpret_cast<const int64_t *>(buf + off[k]);
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc += v[k];
+        } else {
+            int4 v[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] = *reinterpret_cast<const int4 *>(buf + off[k]);
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc += v[k].x ^ v[k].w;
+        }
     }
     if (acc == 0x7fffffffffffll) sink[0] = acc;
 }
@@ -77,9 +140,81 @@ int device_cus() {
     return cus;
 }
 
+struct SweepArgs { const unsigned char *buf; size_t lines; int rounds; int64_t *sink; int blocks; int shape; int inflight; };
+
+template <int W, int Q, int K>
+void launch_sweep_k(const SweepArgs *a) {
+    hipLaunchKernelGGL((random_sweep_kernel<W, Q, K>), dim3(a->blocks), dim3(BLOCK), 0, nullptr, a->buf, a->lines,
+                       a->rounds, a->sink);
+}
+
+template <int W, int Q>
+void launch_sweep_shape(const SweepArgs *a) {
+    switch (a->inflight) {
+        case 1: launch_sweep_k<W, Q, 1>(a); break;
+        case 2: launch_sweep_k<W, Q, 2>(a); break;
+        case 4: launch_sweep_k<W, Q, 4>(a); break;
+        case 8: launch_sweep_k<W, Q, 8>(a); break;
+        case 16: launch_sweep_k<W, Q, 16>(a); break;
+        default: launch_sweep_k<W, Q, 32>(a); break;
+    }
+}
+
+struct StreamSweepArgs { const int4 *buf; size_t n16; int64_t *sink; int blocks; int inflight; };
+
+void launch_stream_sweep(void *p) {
+    const StreamSweepArgs *a = static_cast<const StreamSweepArgs *>(p);
+    switch (a->inflight) {
+        case 1: hipLaunchKernelGGL(stream_sweep_kernel<1>, dim3(a->blocks), dim3(BLOCK), 0, nullptr, a->buf, a->n16, a->sink); break;
+        case 2: hipLaunchKernelGGL(stream_sweep_kernel<2>, dim3(a->blocks), dim3(BLOCK), 0, nullptr, a->buf, a->n16, a->sink); break;
+        case 4: hipLaunchKernelGGL(stream_sweep_kernel<4>, dim3(a->blocks), dim3(BLOCK), 0, nullptr, a->buf, a->n16, a->sink); break;
+        default: hipLaunchKernelGGL(stream_sweep_kernel<8>, dim3(a->blocks), dim3(BLOCK), 0, nullptr, a->buf, a->n16, a->sink); break;
+    }
+}
+
+void launch_sweep(void *p) {
+    const SweepArgs *a = static_cast<const SweepArgs *>(p);
+    if (a->shape == 0) launch_sweep_shape<8, 1>(a);
+    else if (a->shape == 1) launch_sweep_shape<16, 1>(a);
+    else launch_sweep_shape<16, 4>(a);
+}
+
 }  // namespace
 
 extern "C" {
+
+int kc_probe_stream_sweep(const void *buf, size_t bytes, int inflight, int blocks_per_cu, int64_t *sink,
+                          double *gbps) {
+    if (!buf || !sink || !gbps || bytes < 16 || blocks_per_cu < 1 || blocks_per_cu > 64) return -4;
+    if (inflight != 1 && inflight != 2 && inflight != 4 && inflight != 8) return -4;
+    StreamSweepArgs a{static_cast<const int4 *>(buf), bytes / 16, sink, device_cus() * blocks_per_cu, inflight};
+    double ms = 0.0;
+    const int rc = time_launch(launch_stream_sweep, &a, &ms);
+    if (rc != 0) return rc;
+    *gbps = (double)(a.n16 * 16) / (ms * 1e-3) / 1e9;
+    return 0;
+}
+
+int kc_probe_random_sweep(const void *buf, size_t bytes, int shape, int inflight, int blocks_per_cu,
+                          int64_t *sink, double *lines_per_s) {
+    if (!buf || !sink || !lines_per_s || bytes < 64 || shape < 0 || shape > 2 || blocks_per_cu < 1 ||
+        blocks_per_cu > 64)
+        return -4;
+    if (inflight != 1 && inflight != 2 && inflight != 4 && inflight != 8 && inflight != 16 && inflight != 32)
+        return -4;
+    const int blocks = device_cus() * blocks_per_cu;
+    const int q = shape == 2 ? 4 : 1;
+    // about 2^28 line reads per launch
+    const int64_t threads = (int64_t)blocks * BLOCK;
+    int rounds = (int)std::max<int64_t>(1, ((int64_t)1 << 28) * q / (threads * inflight));
+    SweepArgs a{static_cast<const unsigned char *>(buf), bytes / 64, rounds, sink, blocks, shape, inflight};
+    double ms = 0.0;
+    const int rc = time_launch(launch_sweep, &a, &ms);
+    if (rc != 0) return rc;
+    *lines_per_s = (double)threads / q * rounds * inflight / (ms * 1e-3);
+    return 0;
+}
+
 
 int kc_probe_stream_read(const void *buf, size_t bytes, int64_t *sink, double *gbps) {
     if (!buf || !sink || !gbps || bytes < 16) return -4;

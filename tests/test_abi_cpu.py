@@ -87,7 +87,7 @@ def test_probe_library_exports_its_header():
     text = open(os.path.join(ROOT, "include", "kc_probe.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     decl = set(re.findall(r"\b(kc_[a-z0-9_]+)\s*\(", text))
-    assert decl == {"kc_probe_stream_read", "kc_probe_random_read"}
+    assert decl == {"kc_probe_stream_read", "kc_probe_random_read", "kc_probe_stream_sweep", "kc_probe_random_sweep"}
     lib = ctypes.CDLL(build_lib.PROBE_LIB)
     for name in decl:
         assert hasattr(lib, name), name
