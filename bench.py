@@ -132,7 +132,7 @@ def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: fl
         else:
             plan.append((float(t), gid, "query", [], False))
     log("serving: %d graphs, %d requests planned (%.1f s)" % (graphs, n_req, time.perf_counter() - t_gen))
-    srv = Server(budget_bytes=32 << 30, update_share=4 << 30, maintenance=maintenance,
+    srv = Server(budget_bytes=32 << 30, workspace_share=4 << 30, maintenance=maintenance,
                  one_at_a_time=one_at_a_time)
     try:
         t_init = time.perf_counter()
@@ -356,31 +356,47 @@ def calibrate_copy(mib: int):
 
 
 def calibrate_random(gib: int):
-    """Measured ceilings for the roofline discussion (libkc_probe.so): a
-    streaming read of a `gib` GiB buffer, and independent random reads of whole
-    64-byte lines from it.  Prints one JSON line."""
+    """Measured ceilings for the roofline (libkc_probe.so), swept over the
+    launch settings, best kept: a streaming read of a `gib` GiB buffer (loads
+    in flight per thread x blocks per CU), and random reads of 64-byte lines
+    from it in the estimator's shapes (8 or 16 bytes per lane from its own
+    line, or four lanes on one line) x reads in flight per thread x blocks
+    per CU.  Prints one JSON line with every point and the best of each."""
     import ctypes
     import torch
     from paper_2511_16356_amd import build_lib
     lib = ctypes.CDLL(build_lib.PROBE_LIB)
-    lib.kc_probe_stream_read.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
-                                         ctypes.POINTER(ctypes.c_double)]
-    lib.kc_probe_random_read.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_void_p,
-                                         ctypes.POINTER(ctypes.c_double)]
+    lib.kc_probe_stream_sweep.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    lib.kc_probe_random_sweep.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
     nbytes = gib << 30
     buf = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
     sink = torch.zeros(1, dtype=torch.int64, device="cuda")
     torch.cuda.synchronize()
-    gbps, sps = ctypes.c_double(0.0), ctypes.c_double(0.0)
-    rc1 = lib.kc_probe_stream_read(ctypes.c_void_p(buf.data_ptr()), nbytes, ctypes.c_void_p(sink.data_ptr()),
-                                   ctypes.byref(gbps))
-    rc2 = lib.kc_probe_random_read(ctypes.c_void_p(buf.data_ptr()), nbytes, 1 << 28, ctypes.c_void_p(sink.data_ptr()),
-                                   ctypes.byref(sps))
-    if rc1 != 0 or rc2 != 0:
-        raise RuntimeError("probe failed (%d, %d)" % (rc1, rc2))
-    print(json.dumps({"buffer_GiB": gib, "stream_read_GBps": gbps.value,
-                      "random_64B_lines_per_s": sps.value, "random_64B_read_GBps": sps.value * 64 / 1e9}),
-          flush=True)
+    out = {"buffer_GiB": gib, "stream": [], "random": []}
+    val = ctypes.c_double(0.0)
+    for inflight in (1, 2, 4, 8):
+        for bpc in (4, 8, 16, 32):
+            rc = lib.kc_probe_stream_sweep(ctypes.c_void_p(buf.data_ptr()), nbytes, inflight, bpc,
+                                           ctypes.c_void_p(sink.data_ptr()), ctypes.byref(val))
+            if rc != 0:
+                raise RuntimeError("stream probe failed (%d)" % rc)
+            out["stream"].append({"inflight": inflight, "blocks_per_cu": bpc, "GBps": val.value})
+    shapes = {0: "8 B per lane, own line", 1: "16 B per lane, own line", 2: "4 lanes x 16 B on one line"}
+    for shape in (0, 1, 2):
+        for inflight in (1, 4, 8, 16, 32):
+            for bpc in (4, 8, 16):
+                rc = lib.kc_probe_random_sweep(ctypes.c_void_p(buf.data_ptr()), nbytes, shape, inflight, bpc,
+                                               ctypes.c_void_p(sink.data_ptr()), ctypes.byref(val))
+                if rc != 0:
+                    raise RuntimeError("random probe failed (%d)" % rc)
+                out["random"].append({"shape": shapes[shape], "inflight": inflight, "blocks_per_cu": bpc,
+                                      "lines_per_s": val.value, "GBps_64B": val.value * 64 / 1e9})
+        log("random shape %d done" % shape)
+    out["best_stream"] = max(out["stream"], key=lambda r: r["GBps"])
+    out["best_random"] = max(out["random"], key=lambda r: r["lines_per_s"])
+    print(json.dumps(out), flush=True)
 
 
 WORKLOADS = {
@@ -403,10 +419,16 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="dense",
                     help="dense: the headline workload (default); road / social: the other shapes")
     ap.add_argument("--samples", type=int, default=0, help="tree samples per step (launch)")
+    ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
+                    help="choose the launch options with kc_autotune before timing (auto: for the "
+                         "social-like workload, whose configuration asks for it)")
+    ap.add_argument("--tune-cache", default="", help="kc_autotune cache file (default: in the temp directory)")
+    ap.add_argument("--direct", action="store_true",
+                    help="time kc_estimate calls instead of replays of the captured launch")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--budget", type=float, default=480.0,
                     help="wall-clock seconds after which the optional legs are skipped")
-    ap.add_argument("--cpu-per-thread", type=int, default=2)
+    ap.add_argument("--cpu-per-thread", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-latency leg")
     ap.add_argument("--serve-graphs", type=int, default=8)
@@ -463,12 +485,38 @@ def main():
     log("prepared on the device (%.1f s): %s" % (time.perf_counter() - t0, info))
     stream = torch.cuda.current_stream()
     B = args.samples or DEFAULT_SAMPLES[args.workload]
-    # set-up (not a step): allocate the workspace for the batch
-    G.reserve(B)
+    # set-up (not a step): the launch over B samples, captured once as a HIP graph
+    # (kc_batch) with its workspace; launch L estimates samples L*B .. (L+1)*B - 1,
+    # so the warm-up launches take the first ids and the timed ones the next
+    tuned = None
+    if args.autotune == "on" or (args.autotune == "auto" and args.workload == "social"):
+        # set-up: choose the launch options for batches of B samples (trial estimates
+        # on sample ids from 2^40, far from the ones timed), then free the trials' workspace
+        import tempfile
+        t0 = time.perf_counter()
+        cache = args.tune_cache or os.path.join(tempfile.gettempdir(), "kc_autotune.jsonl")
+        tuned = G.autotune(B, cache_path=cache, stream=stream)
+        tuned["seconds"] = time.perf_counter() - t0
+        tuned["cache"] = cache
+        G.trim(stream)
+        log("autotune (%.1f s): %s" % (tuned["seconds"], tuned))
+    batch = None
+    if not args.direct:
+        batch = kc.Batch([G], [args.seed], [0], [B], stream=stream)
+    else:
+        G.reserve(B)
     torch.cuda.synchronize()
 
+    def step(k):
+        if batch is None:
+            return G.estimate(args.seed, k * B, B)
+        batch.launch(stream)
+        (est,), launches = batch.results(stream)
+        assert launches == k + 1
+        return est
+
     for w in range(args.warmup):
-        G.estimate(args.seed, (10 ** 8) + w * B, B)
+        step(w)
         log("warmup step %d done" % w)
     torch.cuda.synchronize()
 
@@ -479,13 +527,15 @@ def main():
     t_start = time.perf_counter()
     for k in range(args.steps):
         starts[k].record(stream)
-        est = G.estimate(args.seed, k * B, B)
+        est = step(args.warmup + k)
         ends[k].record(stream)
         ests.append(est)
         log("step %d: kappa=%.1f +- %.1f draws/sample=%.0f" % (k, est.kappa, est.std_error, est.total_steps / B))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     launch_ms = [starts[k].elapsed_time(ends[k]) for k in range(args.steps)]
+    if batch is not None:
+        batch.close()
 
     total = B * args.steps
     pooled = G.combine(ests)
@@ -513,7 +563,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (WORKLOADS[args.workload] % (g.n, g.two_m // 2, info["depth0"])) +
-                        "; %d tree samples per step (one persistent launch), Philox seed %d" % (B, args.seed),
+                        "; %d tree samples per step (one persistent launch%s), Philox seed %d" %
+                        (B, "" if args.direct else ", replayed from a captured HIP graph", args.seed),
             "samples_per_step": B,
             "parallelism": "1 GPU, one wavefront per sample in flight",
         },
@@ -523,6 +574,7 @@ def main():
         "draws_per_sample": draws / total,
         "draws_per_sampler_round": draws / max(1, pooled.sampler_iterations),
         "launch_ms": launch_ms,
+        "autotune": tuned,
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,

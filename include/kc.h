@@ -173,6 +173,16 @@ kc_status kc_set_tau0(kc_graph *g, int kind, const int32_t *parent, void *hip_st
 kc_status kc_reserve(kc_graph *g, int32_t count, void *hip_stream);
 
 /*
+ * Free g's device workspace (the per-sample sampler and numbering state of
+ * the samples in flight) and its internal per-sample result buffers now; the
+ * next call that needs them allocates them again.  The graph arrays and the
+ * resident sample set stay.  For callers that hand the memory to other work
+ * between estimates (a serving loop after an update, a captured batch).
+ * Errors: KC_ERR_INVALID (NULL graph), KC_ERR_DEVICE.
+ */
+kc_status kc_trim(kc_graph *g, void *hip_stream);
+
+/*
  * Draw the uniform spanning trees of samples first_sample ..
  * first_sample+count-1 with Wilson's algorithm (section 2.2), each
  * (sample s, vertex v, k-th draw at v) taking neighbour slot
@@ -305,12 +315,13 @@ typedef struct {
     int32_t from_cache;   /* 1 if read from the cache file, 0 if measured now */
     int32_t trials;       /* trial estimates run */
     double samples_per_s; /* rate of the chosen options in their trial (0 from the cache) */
+    double start_samples_per_s; /* rate of the options the graph had before (0 from the cache) */
 } kc_tune_result;
 
 /*
  * Choose g's launch options for estimates of `count` samples by timing short
- * trial estimates (between one and two launches' worth of samples, on sample
- * ids from 2^40 upward): starting from the current options, one option at a
+ * trial estimates (one wave of samples in flight, at least 64, on sample ids
+ * from 2^40 upward): starting from the current options, one option at a
  * time (speculative draw, traversal for tau0 depth <= 64, chain-table size,
  * 3/4 and 1/2 of the samples in flight, walkers 32/64), a change kept only for
  * a gain above 2%.  The choice is applied to g (kc_set_option) and appended to

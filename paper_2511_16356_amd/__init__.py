@@ -31,7 +31,7 @@ KC_OPT_SPECULATE = 9
 
 # every symbol include/kc.h declares
 EXPORTS = ("kc_graph_create", "kc_graph_destroy", "kc_graph_get_info", "kc_set_option", "kc_set_tau0",
-           "kc_reserve", "kc_progress",
+           "kc_reserve", "kc_trim", "kc_progress",
            "kc_samples_init", "kc_samples_query", "kc_samples_get", "kc_samples_weights", "kc_apply_updates",
            "kc_sample_trees", "kc_estimate", "kc_estimate_static", "kc_evaluate_trees", "kc_combine_results",
            "kc_batch_create", "kc_batch_launch", "kc_batch_results", "kc_batch_f", "kc_batch_destroy",
@@ -56,7 +56,8 @@ class _Info(ctypes.Structure):
 class _Tune(ctypes.Structure):
     _fields_ = [("chains", ctypes.c_int32), ("slots", ctypes.c_int32), ("walkers", ctypes.c_int32),
                 ("traversal", ctypes.c_int32), ("speculate", ctypes.c_int32), ("from_cache", ctypes.c_int32),
-                ("trials", ctypes.c_int32), ("samples_per_s", ctypes.c_double)]
+                ("trials", ctypes.c_int32), ("samples_per_s", ctypes.c_double),
+                ("start_samples_per_s", ctypes.c_double)]
 
 
 class _Result(ctypes.Structure):
@@ -101,6 +102,8 @@ def library() -> ctypes.CDLL:
     lib.kc_apply_updates.argtypes = [p, p, p, p, i32, ctypes.POINTER(i32), p]
     lib.kc_progress.restype = ctypes.c_int
     lib.kc_progress.argtypes = [p, ctypes.POINTER(i64)]
+    lib.kc_trim.restype = ctypes.c_int
+    lib.kc_trim.argtypes = [p, p]
     lib.kc_reserve.restype = ctypes.c_int
     lib.kc_reserve.argtypes = [p, i32, p]
     lib.kc_sample_trees.restype = ctypes.c_int
@@ -283,6 +286,10 @@ class Graph:
     def reserve(self, count: int, stream=None):
         """Allocate the workspace for estimates of up to `count` samples now."""
         _check(library().kc_reserve(self._h, count, _stream(stream)))
+
+    def trim(self, stream=None):
+        """Free the graph's workspace now (allocated again on next use)."""
+        _check(library().kc_trim(self._h, _stream(stream)))
 
     def sample_trees(self, seed: int, first: int, count: int, popcounts: bool = True,
                      steps: bool = True, stream=None):

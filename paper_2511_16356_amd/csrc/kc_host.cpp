@@ -850,6 +850,19 @@ kc_status kc_progress(const kc_graph *g, int64_t *samples_done) {
     return KC_OK;
 }
 
+kc_status kc_trim(kc_graph *g, void *hip_stream) {
+    g_last_error.clear();
+    if (!g) return fail(KC_ERR_INVALID, "NULL graph");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)hip_stream));  // no launch still uses the workspace
+    free_workspace(g);
+    dev_free(g->d_f);
+    dev_free(g->d_steps);
+    dev_free(g->d_iters);
+    g->d_f = g->d_steps = g->d_iters = nullptr;
+    g->fbuf_len = 0;
+    return KC_OK;
+}
+
 kc_status kc_reserve(kc_graph *g, int32_t count, void *hip_stream) {
     g_last_error.clear();
     if (!g) return fail(KC_ERR_INVALID, "NULL graph");

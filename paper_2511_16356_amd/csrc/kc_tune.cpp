@@ -107,17 +107,24 @@ extern "C" kc_status kc_autotune(kc_graph *g, int32_t count, const char *cache_p
         return KC_OK;
     }
     const Choice start{g->chains, g->slots_opt, g->walkers, g->trav_opt, g->speculate_opt};
-    // samples in flight by default: the kernel's resident workgroups, within the budget
-    const int full = std::max(1, std::min(default_slots(g), count));
-    // trial estimates: between one and two launches' worth of samples, on sample ids
-    // far from any the caller uses (2^40 upward)
+    // samples in flight by default: the kernel's resident workgroups, as many as fit the
+    // memory budget (measured with the graph's own workspace freed first)
+    kc_status st = kc_trim(g, hip_stream);
+    if (st != KC_OK) return st;
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    const int64_t budget = g->mem_budget > 0 ? g->mem_budget : (int64_t)(0.6 * (double)free_b);
+    const int64_t fit = budget / std::max<int64_t>(1, slot_bytes(g, true, g->traversal == KC_TRAV_SWEEP));
+    const int full = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(default_slots(g), count), fit));
+    // trial estimates: one wave of samples in flight (at least 64), on sample ids far
+    // from any the caller uses (2^40 upward)
     kc_result res{};
     int64_t next_first = 1ll << 40;
     auto trial = [&](const Choice &c, double *rate) -> kc_status {
         kc_status st = apply(g, c);
         if (st != KC_OK) return st;
         const int slots = c.slots > 0 ? c.slots : full;
-        const int32_t t = (int32_t)std::min<int64_t>(count, std::max<int64_t>(64, 2ll * slots));
+        const int32_t t = (int32_t)std::min<int64_t>(count, std::max<int64_t>(64, slots));
         st = kc_reserve(g, t, hip_stream);
         if (st != KC_OK) return st;
         const auto t0 = std::chrono::steady_clock::now();
@@ -131,11 +138,12 @@ extern "C" kc_status kc_autotune(kc_graph *g, int32_t count, const char *cache_p
     };
     best = start;
     double best_rate = 0.0;
-    kc_status st = trial(best, &best_rate);
+    st = trial(best, &best_rate);
     if (st != KC_OK) {
         (void)apply(g, start);
         return st;
     }
+    out->start_samples_per_s = best_rate;
     // one dimension at a time, each candidate a change of the best choice so far
     using Change = std::function<void(Choice &)>;
     std::vector<Change> changes = {
