@@ -42,10 +42,11 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2511_16356_amd", "csrc", "kc_device.hip")
 MEASURED_TRAFFIC = {}
 
 
-# Measured ceilings of the device (bench.py --calibrate-random 16, libkc_probe.so;
-# profiles/memory_ceilings_mi355x.md): a streaming read and independent random
-# reads of whole 64-byte lines over a 16 GiB buffer.
-MEASURED_CEILINGS = {"stream_read_GBps": 5207.0, "random_64B_read_GBps": 1262.0}
+# Measured ceilings of the device (bench.py --calibrate-random 128, libkc_probe.so;
+# profiles/memory_ceilings_mi355x.md): the best streaming read, and independent
+# random 8-byte reads by each lane to a line of its own, over a 128 GiB buffer,
+# swept over reads in flight per lane and workgroups per CU.
+MEASURED_CEILINGS = {"stream_read_GBps": 6362.0, "random_64B_read_GBps": 3179.0}
 
 
 def log(*a):

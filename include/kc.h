@@ -99,14 +99,9 @@ enum {
     KC_OPT_CHAINS = 7,     /* walks one sample may hold open at once: 1024 (default) or 2048.
                               More finish one sample in fewer rounds; fewer let more samples
                               run at once.  Results do not depend on it. */
-    KC_OPT_MAINTENANCE = 8, /* KC_MAINT_*: how kc_apply_updates maintains the resident set;
+    KC_OPT_MAINTENANCE = 8 /* KC_MAINT_*: how kc_apply_updates maintains the resident set;
                               may change while the set's weights are all equal (always under
                               basic maintenance), else KC_ERR_INVALID */
-    KC_OPT_SPECULATE = 9   /* speculative first draw: a walker that claims a vertex also computes
-                              that vertex's first draw (Philox counter k = 0) and requests its row
-                              entry in the same round, used when the claim finds no earlier draw
-                              there.  0 = off, 1 = on, 2 = when the mean degree exceeds 12
-                              (default).  Results do not depend on it. */
 };
 
 /* Sample maintenance of a resident set (section 4). */
@@ -272,7 +267,7 @@ kc_status kc_estimate_static(kc_graph *g, uint64_t seed, int64_t first_sample, i
  * exact sums of each job, the launch counter) is captured once as a HIP graph
  * at creation and replayed by kc_batch_launch with no host round trip: the
  * status and sums stay on the device until kc_batch_results reads them.
- * Launch options (step limit, walkers, traversal, speculative draw) are each
+ * Launch options (step limit, walkers, traversal) are each
  * graph's; the chain-table size, samples in flight and memory budget are the
  * first graph's.  The batch owns its workspace (slots sized for the largest
  * graph) and copies of the graphs' device array pointers: the graphs must
@@ -311,7 +306,7 @@ kc_status kc_batch_destroy(kc_batch *b);
 
 /* Launch options chosen by kc_autotune. */
 typedef struct {
-    int32_t chains, slots, walkers, traversal, speculate; /* as KC_OPT_* values */
+    int32_t chains, slots, walkers, traversal; /* as KC_OPT_* values */
     int32_t from_cache;   /* 1 if read from the cache file, 0 if measured now */
     int32_t trials;       /* trial estimates run */
     double samples_per_s; /* rate of the chosen options in their trial (0 from the cache) */
@@ -322,7 +317,7 @@ typedef struct {
  * Choose g's launch options for estimates of `count` samples by timing short
  * trial estimates (one wave of samples in flight, at least 64, on sample ids
  * from 2^40 upward): starting from the current options, one option at a
- * time (speculative draw, traversal for tau0 depth <= 64, chain-table size,
+ * time (traversal for tau0 depth <= 64, chain-table size,
  * 3/4 and 1/2 of the samples in flight, walkers 32/64), a change kept only for
  * a gain above 2%.  The choice is applied to g (kc_set_option) and appended to
  * cache_path (HOST string or NULL: no cache) as one JSON line keyed by device

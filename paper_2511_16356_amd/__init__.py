@@ -27,7 +27,6 @@ KC_OPT_CHAINS = 7
 KC_TAU0_BFS, KC_TAU0_DFS, KC_TAU0_GIVEN = 0, 1, 2
 KC_OPT_MAINTENANCE = 8
 KC_MAINT_BASIC, KC_MAINT_IMPROVED = 0, 1
-KC_OPT_SPECULATE = 9
 
 # every symbol include/kc.h declares
 EXPORTS = ("kc_graph_create", "kc_graph_destroy", "kc_graph_get_info", "kc_set_option", "kc_set_tau0",
@@ -55,7 +54,7 @@ class _Info(ctypes.Structure):
 
 class _Tune(ctypes.Structure):
     _fields_ = [("chains", ctypes.c_int32), ("slots", ctypes.c_int32), ("walkers", ctypes.c_int32),
-                ("traversal", ctypes.c_int32), ("speculate", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("traversal", ctypes.c_int32), ("from_cache", ctypes.c_int32),
                 ("trials", ctypes.c_int32), ("samples_per_s", ctypes.c_double),
                 ("start_samples_per_s", ctypes.c_double)]
 

@@ -134,32 +134,37 @@ constexpr int VREC_INLINE = 6;
 // Two 8-byte words per (sample, vertex), in two arrays, so that the claim
 // (an atomic on the tag word) and the read of the arrow word go to different
 // cache lines and overlap:
-//   tag word   low half: bits 0..27 tag (0 = arrow not revealed ("free"),
-//              1 = in the tree, 2 + c = on the path of chain c); bit 29 need
-//              (the vertex's turn as a walk start passed while it was on a path)
+//   tag word   low half: bits 0..30 tag (0 = arrow not revealed ("free"),
+//              1 = in the tree from the start, 2 + c + CH g = on the path of
+//              chain c in its generation g); bit 31 need (the vertex's turn as
+//              a walk start passed while it was on a path)
 //              high half: 1 + the first of the chains parked on this vertex
 //              (their head's arrow points here), 0 if none; the list continues
 //              through the chain table's wnext links
 //   arrow word low half: the current arrow target (the tree parent at the
 //              end); high half: how many arrows the vertex has drawn
-// A free vertex's tag word is 0; a tree vertex's is T_TREE.  Every change of
-// a tag word is one atomic operation, so claims, parks, need marks, erases
-// and retraces of the same round may meet on a vertex in any order.
+// A free vertex's tag word is 0; a start vertex's is T_TREE.  A path that
+// reaches the tree joins it as a whole: its chain records the generation as
+// finished (fin in LDS), and every vertex tagged with a finished generation is
+// a tree vertex from then on, with no write to its tag word.  Every change of
+// a tag word is one atomic operation, so claims, parks, need marks and erases
+// of the same round may meet on a vertex in any order.
 constexpr uint32_t T_FREE = 0, T_TREE = 1, T_CHAIN0 = 2;
 
 __device__ __forceinline__ uint32_t *tag_high(uint64_t *w) { return reinterpret_cast<uint32_t *>(w) + 1; }
 __device__ __forceinline__ uint64_t arrow_of(int32_t nxt, uint32_t drw) {
     return (uint64_t)(uint32_t)nxt | ((uint64_t)drw << 32);
 }
-constexpr uint32_t TW_TAG = (1u << 28) - 1;
-constexpr uint32_t TW_NEED = 1u << 29;
+constexpr uint32_t TW_TAG = (1u << 31) - 1;
+constexpr uint32_t TW_NEED = 1u << 31;
+constexpr int GEN_MAX = 32767;  // generations of one chain id (fin is int16)
 
 // A chain is a loop-erased path of revealed arrows owned by one walk: from
 // its start vertex to its head.  A lane drives at most one chain at a time.
 // When the head's arrow lands on another chain's path, the chain is parked
 // (it joins the vertex's waiter list) and the lane takes other work; the chain is
-// woken when that vertex is popped (resume there) or joins the tree
-// (retrace).  A start vertex that already lies on a path is skipped with its
+// woken when that vertex is popped (resume there), and joins the tree with
+// the chain it waits on.  A start vertex that already lies on a path is skipped with its
 // need bit set; if it is popped later its eraser queues it for a restart.
 // Popped vertices are also offered as optional extra starts (a small LIFO):
 // revealing any free vertex is work the cycle-popping order fixes anyway.
@@ -170,8 +175,8 @@ constexpr uint32_t TW_NEED = 1u << 29;
 constexpr int MAX_CHAINS = 2048;
 constexpr int HINTS = 128; // optional restart hints
 
-enum : int { CS_FREE = 0, CS_ACTIVE = 1, CS_PARKED = 2, CS_QUEUED = 3 };
-enum : int { T_RESUME = 0, T_RETRACE = 1, T_POP = 2 };
+enum : int { CS_FREE = 0, CS_ACTIVE = 1, CS_PARKED = 2, CS_QUEUED = 3, CS_DONE = 4 };
+enum : int { T_RESUME = 0, T_POP = 2 };
 
 // Lane modes.  Each issues exactly one round of memory operations per sampler
 // round, and all lanes' operations are in flight together.
@@ -183,9 +188,7 @@ enum : int {
     M_NEED = 3,    // set the need bit of start vertex `tgt` if its tag word is still `seen`
     M_ADJ = 4,     // the drawn neighbour lies beyond the inline ones: fetch it
     M_ERASE0 = 5,  // popping: load the kept vertex `tgt` (the new head)
-    M_ERASE = 6,   // popping: free `tgt`, follow next until `stopv`
-    M_RETRACE = 7, // path met the tree: mark from `tgt` until `stopv`
-    M_RETRACE0 = 8 // path met the tree: read the chain's start vertex first
+    M_ERASE = 6    // popping: free `tgt`, follow next until `stopv`
 };
 
 template <int CH>
@@ -195,7 +198,9 @@ struct SamplerShared {
     int16_t wnext[CH];   // parked: next / previous chain parked on the same vertex (-1: none)
     int16_t wprev[CH];
     int8_t state[CH];    // CS_*
-    int16_t freestk[CH]; // free chain ids
+    int16_t fin[CH];     // last generation of the chain id whose path joined the tree (-1: none);
+                         // the id's current generation is fin + 1
+    int16_t ring[CH];    // free chain ids, taken first in, first out (so generations grow evenly)
     int32_t hint[HINTS];
 };
 
@@ -228,7 +233,7 @@ template <int CH>
 __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerShared<CH> &sh,
                                uint64_t seed, uint64_t s, int walkers, int64_t iter_cap,
                                int32_t *ctl, int idx, int64_t *iters_used, int32_t root_u,
-                               int32_t root_v, bool speculate) {
+                               int32_t root_v) {
     const int lane = threadIdx.x;
     const int n = g.n, root = g.root;
     const bool two_roots = root_u >= 0;  // start from {u, v} instead of {root}
@@ -241,7 +246,8 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
     }
     for (int c = lane; c < CH; c += WAVE) {
         sh.state[c] = CS_FREE;
-        sh.freestk[c] = (int16_t)(CH - 1 - c);
+        sh.fin[c] = -1;
+        sh.ring[c] = (int16_t)c;
     }
     fence_wg();
     __syncthreads();
@@ -257,10 +263,21 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
     // so that the record stays in registers)
     int hoff = 0, hdeg = 0, hn0 = -1, hn1 = -1, hn2 = -1, hn3 = -1, hn4 = -1, hn5 = -1;
     // wave-uniform bookkeeping
-    int next_start = 0, q_head = 0, q_tail = 0, free_top = CH, parked = 0, hint_top = 0;
+    int next_start = 0, q_head = 0, q_tail = 0, f_head = 0, f_tail = CH, parked = 0, hint_top = 0;
     int64_t rq_head = 0, rq_tail = 0;
     int64_t iters = 0, mysteps = 0;
     int err = 0;
+
+    // tag of chain c's path in its current generation
+    auto tag_of = [&](int c) __attribute__((always_inline)) {
+        return T_CHAIN0 + (uint32_t)c + (uint32_t)CH * (uint32_t)(sh.fin[c] + 1);
+    };
+    // a tree vertex: a start vertex, or on a path whose generation has joined the tree
+    auto in_tree = [&](uint32_t t) __attribute__((always_inline)) {
+        if (t < T_CHAIN0) return t == T_TREE;
+        const uint32_t x = t - T_CHAIN0;
+        return (int)(x / (uint32_t)CH) <= (int)sh.fin[x % (uint32_t)CH];
+    };
 
     // the head `cur` (its graph record in registers, dcur draws so far) draws its next arrow;
     // called once per round for the lanes that set `drawing`
@@ -293,7 +310,7 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             const uint64_t idle = __ballot(worker && mode == M_IDLE);
             const int nidle = __popcll(idle);
             const int take_q = min(nidle, q_tail - q_head);
-            int left = nidle - take_q, room = free_top;
+            int left = nidle - take_q, room = f_tail - f_head;
             const int take_r = (int)min((int64_t)min(left, room), rq_tail - rq_head);
             left -= take_r; room -= take_r;
             const int take_s = min(min(left, room), n - next_start);
@@ -317,22 +334,19 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
                 }
                 if (r < take_q) {
                     chain = t.x;
-                    ctag = T_CHAIN0 + (uint32_t)chain;
+                    ctag = tag_of(chain);
                     if (t.y == T_RESUME) {
                         tgt = t.z;
                         haspath = true;
                         mode = M_LOOK;
-                    } else if (t.y == T_RETRACE) {
-                        stopv = t.z;
-                        mode = M_RETRACE0;
                     } else {
                         tgt = t.z;
                         stopv = t.w;
                         mode = M_ERASE0;
                     }
                 } else if (k < take_r + take_s + take_h) {
-                    chain = sh.freestk[free_top - 1 - k];
-                    ctag = T_CHAIN0 + (uint32_t)chain;
+                    chain = sh.ring[(f_head + k) & (CH - 1)];
+                    ctag = tag_of(chain);
                     tgt = k < take_r ? t_rq : (k < take_r + take_s ? t_ord : t_hint);
                     astore(&ws.start[chain], tgt);
                     haspath = false;
@@ -344,7 +358,7 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             rq_head += take_r;
             next_start += take_s;
             hint_top -= take_h;
-            free_top -= take_r + take_s + take_h;
+            f_head += take_r + take_s + take_h;
         }
         if (__ballot(mode != M_IDLE) == 0ull) {
             if (next_start < n || q_tail != q_head || parked != 0 || rq_tail != rq_head)
@@ -352,18 +366,17 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             break;
         }
         if (++iters > iter_cap) err = DEV_LIMIT;
-        if (err == 0 && mode != M_IDLE && mode != M_ADJ && mode != M_RETRACE0 && (unsigned)tgt >= (unsigned)n)
+        if (err == 0 && mode != M_IDLE && mode != M_ADJ && (unsigned)tgt >= (unsigned)n)
             err = DEV_PROTOCOL;
         if (err == 0 && mode == M_ADJ && (unsigned)adjpos >= (unsigned)g.two_m) err = DEV_PROTOCOL;
         const int m0 = err == 0 ? mode : M_IDLE;
 
         // ---- memory: every lane issues its operations before any result is used
         const bool do_cas = m0 == M_LOOK || m0 == M_PARK || m0 == M_NEED;
-        const bool do_xchg = m0 == M_ERASE || (m0 == M_RETRACE && tgt != stopv);
+        const bool do_xchg = m0 == M_ERASE;
         const bool do_arrow = m0 == M_LOOK || m0 == M_ERASE0 || do_xchg;
         const bool do_rec = m0 == M_LOOK || m0 == M_ERASE0;
         if (m0 == M_LOOK && pend) astore(&arw[cur], arrow_of(tgt, dcur));
-        // the graph record first: the speculative draw below waits for it alone
         int4 r0 = make_int4(0, 0, 0, 0), r1 = make_int4(0, 0, 0, 0);
         if (do_rec) {
             r0 = g.vrec[2 * (size_t)tgt];
@@ -380,36 +393,21 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             o_cas = acas(&tagw[tgt], expect, want);
         }
         if (do_xchg)
-            o_xchg = __hip_atomic_exchange(&tagw[tgt], (uint64_t)(m0 == M_ERASE ? T_FREE : T_TREE),
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            o_xchg = __hip_atomic_exchange(&tagw[tgt], (uint64_t)T_FREE, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
         if (m0 == M_ERASE0) o_tag = aload(&tagw[tgt]);
         uint64_t ar = 0;
         if (do_arrow) ar = aload(&arw[tgt]);
-        // speculative first draw of the looked-at vertex: if the claim finds it with
-        // no draws yet, its draw uses counter k = 0, so the Philox bits are computed
-        // while the claim is in flight, and a slot beyond the inline neighbours has
-        // its row entry requested in this same round
-        uint32_t sj = 0;
-        int32_t sy = -1;
-        const bool spec = speculate && m0 == M_LOOK;
-        if (spec) {
-            const Bits x0 = philox_bits(seed, s, (uint32_t)tgt, 0u);
-            sj = slot_of(x0, (uint32_t)r0.y);
-            if (sj >= (uint32_t)VREC_INLINE && sj < (uint32_t)r0.y && (unsigned)(r0.x + (int)sj) < (unsigned)g.two_m)
-                sy = g.adj[r0.x + (int)sj];
-        }
         auto take_record = [&]() __attribute__((always_inline)) {
             hoff = r0.x; hdeg = r0.y; hn0 = r0.z; hn1 = r0.w;
             hn2 = r1.x; hn3 = r1.y; hn4 = r1.z; hn5 = r1.w;
         };
         int32_t y = -1;
         if (m0 == M_ADJ) y = g.adj[adjpos];
-        int32_t st0 = -1;
-        if (m0 == M_RETRACE0) st0 = aload(&ws.start[chain]);
         const uint64_t o64 = do_cas ? o_cas : (do_xchg ? o_xchg : o_tag);
 
         // ---- apply the results
-        bool retire = false, park = false, drawing = false;
+        bool retire = false, park = false, drawing = false, finish = false;
         int park_head = -1;
         int wake_kind = -1, wake_vtx = -1, wake_head = -1, restart_vtx = -1, hint_vtx = -1;
         const uint32_t old = (uint32_t)o64;
@@ -424,33 +422,7 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
                 cur = tgt;
                 dcur = dt;
                 take_record();
-                if (spec && dt == 0u && (sj < (uint32_t)VREC_INLINE || sy >= 0)) {
-                    // the speculative draw was this draw
-                    mysteps++;
-                    dcur = 1;
-                    haspath = true;
-                    if (sj < (uint32_t)VREC_INLINE) {
-                        const bool odd = (sj & 1u) != 0u;
-                        int p01 = odd ? hn1 : hn0;
-                        int p23 = odd ? hn3 : hn2;
-                        int p45 = odd ? hn5 : hn4;
-                        asm volatile("" : "+v"(p01), "+v"(p23), "+v"(p45));
-                        tgt = sj < 2u ? p01 : (sj < 4u ? p23 : p45);
-                    } else {
-                        tgt = sy;
-                    }
-                    pend = true;
-                    mode = M_LOOK;
-                } else {
-                    drawing = true;
-                }
-            } else if (tg == T_TREE) {
-                if (haspath) {
-                    stopv = tgt;
-                    mode = M_RETRACE0;
-                } else {
-                    retire = true;  // a fresh chain whose start is already in the tree
-                }
+                drawing = true;
             } else if (tg == ctag) {
                 // own path: the new arrow closed a loop at tgt; pop it, keep tgt as head
                 if (!drew) err = DEV_PROTOCOL;
@@ -460,7 +432,10 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
                 stopv = tgt;
                 tgt = nt;
                 mode = M_ERASE;
-            } else if (tg >= T_CHAIN0 && tg < T_CHAIN0 + CH) {
+            } else if (in_tree(tg)) {
+                if (haspath) finish = true;  // the path reaches the tree and joins it
+                else retire = true;          // a fresh chain whose start is already in the tree
+            } else if (tg >= T_CHAIN0) {
                 seen = o64;
                 mode = haspath ? M_PARK : M_NEED;
             } else {
@@ -476,14 +451,10 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
                 }
             } else if (o64 == (uint64_t)T_FREE) {
                 mode = M_LOOK;  // popped meanwhile: look again
-            } else if (tg == T_TREE) {
-                if (m0 == M_PARK) {
-                    stopv = tgt;
-                    mode = M_RETRACE0;
-                } else {
-                    retire = true;
-                }
-            } else if (tg >= T_CHAIN0 && tg < T_CHAIN0 + CH && tg != ctag) {
+            } else if (in_tree(tg)) {
+                if (m0 == M_PARK) finish = true;
+                else retire = true;
+            } else if (tg >= T_CHAIN0 && tg != ctag) {
                 seen = o64;  // another park or a new owner: try again
             } else {
                 err = DEV_PROTOCOL;
@@ -492,9 +463,6 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             tgt = y;
             pend = true;
             mode = M_LOOK;
-        } else if (m0 == M_RETRACE0) {
-            tgt = st0;
-            mode = M_RETRACE;
         } else if (m0 == M_ERASE) {
             if (tg != ctag) err = DEV_PROTOCOL;
             wake_head = (int)(o64 >> 32) - 1;
@@ -509,17 +477,23 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             take_record();
             if (nt == stopv) drawing = true;
             else { mode = M_ERASE; tgt = nt; }
-        } else if (m0 == M_RETRACE) {
-            if (tgt == stopv) {
-                retire = true;  // empty chain: nothing to mark
-            } else {
-                if (tg != ctag) err = DEV_PROTOCOL;
-                wake_head = (int)(o64 >> 32) - 1;
-                if (wake_head >= 0) { wake_kind = T_RETRACE; wake_vtx = tgt; }
-                if (nt == stopv) retire = true; else tgt = nt;
-            }
         }
         if (drawing) draw();
+        // paths that reached the tree join it: their generation is finished
+        auto finish_chain = [&](int c) __attribute__((always_inline)) {
+            if ((int)sh.fin[c] + 1 > GEN_MAX) err = DEV_LIMIT;
+            sh.fin[c] = (int16_t)(sh.fin[c] + 1);
+            sh.state[c] = CS_DONE;
+        };
+        if (finish) finish_chain(chain);
+        __syncthreads();
+        // a new park on a path that has joined the tree (in this round, or since its
+        // owner was looked at) joins the tree with it instead
+        if (park && in_tree(tg)) {
+            park = false;
+            finish = true;
+            finish_chain(chain);
+        }
         // new parks join their vertex's list before any wake walks a list
         if (park) {
             int h = park_head;
@@ -528,7 +502,7 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             sh.wprev[chain] = -1;
             if (h >= 0) sh.wprev[h] = (int16_t)chain;
             sh.block[chain] = tgt;
-            sh.up[chain] = (int16_t)(tg - T_CHAIN0);
+            sh.up[chain] = (int16_t)((tg - T_CHAIN0) % (uint32_t)CH);
             sh.state[chain] = CS_PARKED;
         }
         // popped vertices: need-restarts to the restart ring, the rest offered as hints
@@ -543,20 +517,54 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             }
             hint_top = min(HINTS, hint_top + __popcll(hm));
         }
-        // retired chains return to the free stack
+        // retired chains return to the free ring
         {
             const uint64_t rm = __ballot(retire);
             if (retire) {
-                sh.freestk[free_top + rank_in(rm)] = (int16_t)chain;
+                sh.ring[(f_tail + rank_in(rm)) & (CH - 1)] = (int16_t)chain;
                 sh.state[chain] = CS_FREE;
                 mode = M_IDLE;
                 chain = -1;
             }
-            free_top += __popcll(rm);
+            f_tail += __popcll(rm);
         }
         const uint64_t pm0 = __ballot(park);
         parked += __popcll(pm0);
         __syncthreads();
+        // a parked chain whose head's arrow points into a path that joined the tree
+        // joins it too, transitively (a scan of the chain table per step); then the
+        // chains of this round's joins return to the free ring
+        if (__ballot(finish) != 0ull) {
+            for (int pass = 0; parked > 0; ++pass) {
+                int fresh = 0;
+                for (int c = lane; c < CH; c += WAVE) {
+                    if (sh.state[c] == CS_PARKED && sh.state[sh.up[c]] == CS_DONE) {
+                        finish_chain(c);
+                        ++fresh;
+                    }
+                }
+                __syncthreads();
+                const int tot = (int)wave_sum((int64_t)fresh);
+                parked -= tot;
+                if (tot == 0) break;
+                if (pass > CH) { err = DEV_PROTOCOL; break; }
+            }
+            for (int c0 = 0; c0 < CH; c0 += WAVE) {
+                const int c = c0 + lane;
+                const bool done = sh.state[c] == CS_DONE;
+                const uint64_t dm = __ballot(done);
+                if (done) {
+                    sh.ring[(f_tail + rank_in(dm)) & (CH - 1)] = (int16_t)c;
+                    sh.state[c] = CS_FREE;
+                }
+                f_tail += __popcll(dm);
+            }
+            if (finish) {
+                mode = M_IDLE;
+                chain = -1;
+            }
+            __syncthreads();
+        }
         // wake the chains parked on vertices that were popped or joined the tree:
         // each such lane walks the list its atomic detached, one chain per pass
         if ((unsigned)(wake_head + 1) > (unsigned)CH) { err = DEV_PROTOCOL; wake_head = -1; }
@@ -1256,7 +1264,7 @@ __device__ bool process_one(const GraphDev &g, const SlotPtrs &sp, KernelShared<
     int64_t steps = 0, iters = 0;
     if (!CROSS && (rp.mode == RUN_SAMPLE || rp.mode == RUN_ESTIMATE)) {
         steps = sample_tree<CH>(g, sp.ws, lds.samp, rp.seed, s, rp.walkers, rp.iter_cap, rp.ctl, idx, &iters,
-                                rp.root_u, rp.root_v, rp.speculate != 0);
+                                rp.root_u, rp.root_v);
         if (steps < 0) return false;
     }
     if (!CROSS && rp.mode == RUN_SAMPLE) {
@@ -1359,7 +1367,6 @@ __global__ void __launch_bounds__(WAVE) batch_kernel(BatchArgs a, SlotDev sd, in
         rp.walkers = job.walkers;
         rp.traversal = job.traversal;
         rp.iter_cap = job.iter_cap;
-        rp.speculate = job.speculate;
         rp.ctl = ctl;
         rp.f_out = a.f;
         rp.steps_out = a.steps;

@@ -253,9 +253,6 @@ kc::GraphDev kc_host::graph_dev(const kc_graph *g) {
 void kc_host::fill_run_options(const kc_graph *g, kc::RunParams &rp) {
     rp.walkers = g->walkers;
     rp.traversal = g->traversal;
-    // the speculative first draw pays off when most draws land past the six inline
-    // neighbours of a vertex record: by default when the mean degree exceeds 12
-    rp.speculate = g->speculate_opt == 1 || (g->speculate_opt == 2 && g->two_m > 12 * g->n);
     rp.iter_cap = g->step_limit > 0 ? g->step_limit : 1024 * g->n + (1 << 22);
     rp.ctl = g->d_ctl;
 }
@@ -826,10 +823,6 @@ kc_status kc_set_option(kc_graph *g, int option, int64_t value) {
                         return fail(KC_ERR_INVALID, "the resident trees carry unequal weights; "
                                                     "re-initialise the set to change the maintenance");
             g->maint = (int32_t)value;
-            return KC_OK;
-        case 9: /* KC_OPT_SPECULATE */
-            if (value < 0 || value > 2) return fail(KC_ERR_INVALID, "speculate must be 0, 1 or 2");
-            g->speculate_opt = (int32_t)value;
             return KC_OK;
         case KC_OPT_START_ORDER: {
             if (value < 0 || value > 2) return fail(KC_ERR_INVALID, "start order must be 0, 1 or 2");

@@ -24,7 +24,6 @@ struct kc_graph {
     int32_t chains = 1024;
     int32_t slots_opt = 0;
     int32_t trav_opt = KC_TRAV_AUTO;
-    int32_t speculate_opt = 2;        // speculative first draw: 0 off, 1 on, 2 by mean degree
     int64_t step_limit = 0;
     int64_t mem_budget = 0;
     int64_t graph_bytes = 0;

@@ -50,7 +50,7 @@ struct BatchJob {
     uint64_t seed;
     int64_t first;      // sample index of the job's first item at launch 0
     int64_t iter_cap;   // sampler rounds per sample
-    int32_t walkers, traversal, speculate;
+    int32_t walkers, traversal;
 };
 
 constexpr int BATCH_MAX = 8;  // graphs in one batch launch
@@ -79,8 +79,6 @@ struct RunParams {
     int32_t mode;       // RunMode
     int32_t traversal;  // 1 walk, 2 sweep
     int64_t iter_cap;   // sampler iterations per sample
-    int32_t speculate;  // 1: a claim also computes the vertex's first draw (k = 0) and fetches
-                        //    its row entry in the same round; results do not depend on it
     const int32_t *parents_in; // RUN_EVALUATE input [count*n]
     int32_t *parents_out;      // RUN_SAMPLE  [count*n]
     uint32_t *cnt_out;         // RUN_SAMPLE  [count*n] (optional)

@@ -1,13 +1,12 @@
 // kc_tune.cpp -- kc_autotune: chooses a graph's launch options (samples in
-// flight, chain-table size, walkers per sample, traversal, speculative first
-// draw) by timing short estimates, and keeps the choice in a cache file.
+// flight, chain-table size, walkers per sample, traversal) by timing short estimates, and keeps the choice in a cache file.
 // None of these options changes any tree, f or estimate: the tree of sample s
 // is the cycle-popping outcome of its arrows (section 2.2) whatever the launch
 // shape, and f is Theorem 3.4's sum whatever the traversal.
 //
 // Cache: one JSON object per line,
 //   {"key": "<arch>|n=..|two_m=..|dmax=..|depth0=..|count=..", "chains": C, "slots": S,
-//    "walkers": W, "traversal": T, "speculate": P, "samples_per_s": R}
+//    "walkers": W, "traversal": T, "samples_per_s": R}
 // The last line with the graph's key wins.
 
 #include <algorithm>
@@ -25,7 +24,7 @@ using namespace kc_host;
 namespace {
 
 struct Choice {
-    int32_t chains, slots, walkers, traversal, speculate;
+    int32_t chains, slots, walkers, traversal;
 };
 
 std::string cache_key(const kc_graph *g, int32_t count) {
@@ -60,7 +59,6 @@ bool cache_lookup(const char *path, const std::string &key, Choice *c) {
         c->slots = (int32_t)field(l, "slots", 0);
         c->walkers = (int32_t)field(l, "walkers", 64);
         c->traversal = (int32_t)field(l, "traversal", KC_TRAV_AUTO);
-        c->speculate = (int32_t)field(l, "speculate", 2);
         found = true;
     }
     std::fclose(fh);
@@ -72,8 +70,8 @@ void cache_store(const char *path, const std::string &key, const Choice &c, doub
     if (!fh) return;
     std::fprintf(fh,
                  "{\"key\": \"%s\", \"chains\": %d, \"slots\": %d, \"walkers\": %d, \"traversal\": %d, "
-                 "\"speculate\": %d, \"samples_per_s\": %.3f}\n",
-                 key.c_str(), c.chains, c.slots, c.walkers, c.traversal, c.speculate, rate);
+                 "\"samples_per_s\": %.3f}\n",
+                 key.c_str(), c.chains, c.slots, c.walkers, c.traversal, rate);
     std::fclose(fh);
 }
 
@@ -82,7 +80,6 @@ kc_status apply(kc_graph *g, const Choice &c) {
     if (st == KC_OK) st = kc_set_option(g, KC_OPT_SLOTS, c.slots);
     if (st == KC_OK) st = kc_set_option(g, KC_OPT_WALKERS, c.walkers);
     if (st == KC_OK) st = kc_set_option(g, KC_OPT_TRAVERSAL, c.traversal);
-    if (st == KC_OK) st = kc_set_option(g, KC_OPT_SPECULATE, c.speculate);
     return st;
 }
 
@@ -102,11 +99,10 @@ extern "C" kc_status kc_autotune(kc_graph *g, int32_t count, const char *cache_p
         out->slots = best.slots;
         out->walkers = best.walkers;
         out->traversal = best.traversal;
-        out->speculate = best.speculate;
         out->from_cache = 1;
         return KC_OK;
     }
-    const Choice start{g->chains, g->slots_opt, g->walkers, g->trav_opt, g->speculate_opt};
+    const Choice start{g->chains, g->slots_opt, g->walkers, g->trav_opt};
     // samples in flight by default: the kernel's resident workgroups, as many as fit the
     // memory budget (measured with the graph's own workspace freed first)
     kc_status st = kc_trim(g, hip_stream);
@@ -146,10 +142,7 @@ extern "C" kc_status kc_autotune(kc_graph *g, int32_t count, const char *cache_p
     out->start_samples_per_s = best_rate;
     // one dimension at a time, each candidate a change of the best choice so far
     using Change = std::function<void(Choice &)>;
-    std::vector<Change> changes = {
-        [](Choice &c) { c.speculate = 0; },
-        [](Choice &c) { c.speculate = 1; },
-    };
+    std::vector<Change> changes;
     if (g->depth0 <= 64) {  // the walk costs n * depth0 per tree: only shallow reference trees try both
         changes.push_back([](Choice &c) { c.traversal = KC_TRAV_WALK; });
         changes.push_back([](Choice &c) { c.traversal = KC_TRAV_SWEEP; });
@@ -181,7 +174,6 @@ extern "C" kc_status kc_autotune(kc_graph *g, int32_t count, const char *cache_p
     out->slots = best.slots;
     out->walkers = best.walkers;
     out->traversal = best.traversal;
-    out->speculate = best.speculate;
     out->samples_per_s = best_rate;
     return KC_OK;
 }

@@ -117,21 +117,7 @@ def test_autotuned_options_give_identical_results(kc, graphs, tmp_path):
     with kc.Graph.from_graph(g) as G2:
         again = G2.autotune(300, cache_path=cache)
         assert again["from_cache"] == 1
-        for key in ("chains", "slots", "walkers", "traversal", "speculate"):
+        for key in ("chains", "slots", "walkers", "traversal"):
             assert again[key] == tune[key]
         est2 = G2.estimate(21, 0, 300)
         _same(est2, ref)
-
-
-@pytest.mark.parametrize("spec", [0, 1])
-def test_speculative_draw_changes_nothing(kc, oracle_lib, graphs, spec):
-    for name in ("dstar", "social3k", "road3k", "K5"):
-        g = graphs[name]
-        P = oracle_lib.prepare_graph(g)
-        ref_par, ref_cnt, ref_steps = oracle_lib.sample(P, seed=44, s0=9, count=24, threads=8)
-        with kc.Graph.from_graph(g) as G:
-            G.set_option(kc.KC_OPT_SPECULATE, spec)
-            par, cnt, stp = G.sample_trees(44, 9, 24)
-            assert np.array_equal(par.cpu().numpy(), ref_par)
-            assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ref_cnt)
-            assert np.array_equal(stp.cpu().numpy(), ref_steps)
