@@ -92,7 +92,7 @@ enum {
     KC_OPT_SLOTS = 2,      /* samples in flight per launch (0 = sized from free HBM) */
     KC_OPT_TRAVERSAL = 3,  /* KC_TRAV_* */
     KC_OPT_STEP_LIMIT = 4, /* per-sample cap on sampler rounds (0 = default 1024 n + 2^22) */
-    KC_OPT_MEM_BUDGET = 5, /* bytes of device workspace the library may allocate (0 = 60% of free) */
+    KC_OPT_MEM_BUDGET = 5, /* bytes of device workspace the library may allocate (0 = 80% of free) */
     KC_OPT_START_ORDER = 6, /* order in which walks are started (results do not depend on it):
                               0 = BFS order from the root, 1 = reverse BFS order,
                               2 = a fixed pseudo-random permutation (default) */
@@ -162,7 +162,7 @@ kc_status kc_set_tau0(kc_graph *g, int kind, const int32_t *parent, void *hip_st
  * later call allocates nothing.  Calls also allocate on first use when this
  * is skipped.  The workspace lives until kc_graph_destroy.
  * Errors: KC_ERR_INVALID (count < 1), KC_ERR_NOMEM (the budget of
- * KC_OPT_MEM_BUDGET, or 60% of free device memory, cannot hold one sample),
+ * KC_OPT_MEM_BUDGET, or 80% of free device memory, cannot hold one sample),
  * KC_ERR_DEVICE.
  */
 kc_status kc_reserve(kc_graph *g, int32_t count, void *hip_stream);

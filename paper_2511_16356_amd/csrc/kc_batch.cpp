@@ -96,7 +96,7 @@ kc_status kc_batch_create(kc_graph *const *graphs, int32_t k, const uint64_t *se
     // workgroups), within its memory budget for slots sized for the largest graph
     const size_t n = (size_t)max_n, ch = (size_t)kc::sampler_chains();
     const int64_t per_slot = (int64_t)(20 * n + 20 * ch + 16 * n + 16 * n + 4 * (n + 1) + 8 * (size_t)max_fen);
-    int want = graphs[0]->slots_opt > 0 ? graphs[0]->slots_opt : default_slots(graphs[0]);
+    int want = graphs[0]->slots_opt > 0 ? graphs[0]->slots_opt : default_slots(graphs[0], true);
     want = (int)std::min<int64_t>(want, total);
     size_t free_b = 0, total_b = 0;
     hipError_t e = hipMemGetInfo(&free_b, &total_b);
@@ -104,7 +104,7 @@ kc_status kc_batch_create(kc_graph *const *graphs, int32_t k, const uint64_t *se
         batch_free(b);
         return fail(KC_ERR_DEVICE, "hipMemGetInfo: %s", hipGetErrorString(e));
     }
-    const int64_t budget = graphs[0]->mem_budget > 0 ? graphs[0]->mem_budget : (int64_t)(0.6 * (double)free_b);
+    const int64_t budget = workspace_budget(graphs[0], free_b);
     int slots = (int)std::min<int64_t>(want, budget / per_slot);
     slots = balanced_slots(slots, total);
     if (slots < 1) {

@@ -225,8 +225,9 @@ struct SamplerWS {
 //
 // A round: idle lanes take work; every busy lane issues its memory operations
 // (one dependent round trip); the results are applied (draws from the head's
-// inline neighbours, wakes, pushes); newly parked chains are checked for a
-// cycle one at a time.
+// inline neighbours, wakes, pushes); chains that reached the tree finish, with
+// the parked chains that wait on them; newly parked chains are checked for a
+// cycle of the wait-for forest, all in lockstep.
 //
 // Returns the total number of draws, or -1 (error recorded in ctl).
 template <int CH>
@@ -1321,14 +1322,21 @@ __device__ bool process_one(const GraphDev &g, const SlotPtrs &sp, KernelShared<
 __device__ __forceinline__ int next_item(int32_t *ctl) {
     int idx = 0;
     if (threadIdx.x == 0) idx = __hip_atomic_fetch_add(&ctl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __shfl(idx, 0);
+    // lane 0 is the first active lane: the index becomes a wave-uniform (scalar) value
+    return __builtin_amdgcn_readfirstlane(idx);
 }
 __device__ __forceinline__ bool stopped(const int32_t *ctl) {
     return __hip_atomic_load(const_cast<int32_t *>(&ctl[1]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
+// Waves per SIMD the kernel is built to fit: three at 1,024 chains (168 VGPRs;
+// the LDS then allows ten workgroups per CU), two at 2,048 (LDS allows five).
+template <int CH>
+constexpr int waves_per_simd() { return CH <= 1024 ? 3 : 2; }
+
 template <int CH, bool CROSS = false>
-__global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd, RunParams rp) {
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(waves_per_simd<CH>())))
+persistent_kernel(GraphDev g, SlotDev sd, RunParams rp) {
     __shared__ KernelShared<CH> lds;
     const SlotPtrs sp = slot_ptrs(sd, (size_t)g.n);
     int64_t done = 0;
@@ -1350,7 +1358,8 @@ __global__ void __launch_bounds__(WAVE) persistent_kernel(GraphDev g, SlotDev sd
 // memory, advanced by advance_kernel after each launch).  Every item's f,
 // draws and rounds go to position idx of the batch arrays.
 template <int CH>
-__global__ void __launch_bounds__(WAVE) batch_kernel(BatchArgs a, SlotDev sd, int32_t *ctl,
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(waves_per_simd<CH>())))
+batch_kernel(BatchArgs a, SlotDev sd, int32_t *ctl,
                                                      const int64_t *launch) {
     __shared__ KernelShared<CH> lds;
     const SlotPtrs sp = slot_ptrs(sd, (size_t)sd.stride);
@@ -1561,6 +1570,20 @@ hipError_t launch_persistent(const GraphDev &g, const SlotDev &s, const RunParam
 }
 
 int sampler_chains() { return MAX_CHAINS; }
+
+int batch_blocks_per_cu(int chains) {
+    int blocks = 0;
+#define KC_CASE(C)                                                                                   \
+    if (chains == C) {                                                                              \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel<C>, WAVE, 0) !=        \
+            hipSuccess)                                                                             \
+            return 0;                                                                               \
+        return blocks;                                                                              \
+    }
+    KC_CHAIN_VARIANTS(KC_CASE)
+#undef KC_CASE
+    return 0;
+}
 
 int persistent_blocks_per_cu(int chains) {
     int blocks = 0;

@@ -159,7 +159,7 @@ kc_status ensure_workspace(kc_graph *g, int want, bool trav, bool fen, hipStream
     free_workspace(g);
     size_t free_b = 0, total_b = 0;
     HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-    int64_t budget = g->mem_budget > 0 ? g->mem_budget : (int64_t)(0.6 * (double)free_b);
+    const int64_t budget = workspace_budget(g, free_b);
     const int64_t per = slot_bytes(g, trav, fen);
     int64_t fit = budget / per;
     if (fit < 1) return fail(KC_ERR_NOMEM, "one sample needs %lld bytes of workspace, budget %lld",
@@ -207,14 +207,19 @@ kc_status ensure_fbuf(kc_graph *g, int64_t count) {
 }  // namespace
 
 // One slot per resident single-wave workgroup of the persistent kernel.
-int kc_host::default_slots(const kc_graph *g) {
-    (void)g;
+int kc_host::default_slots(const kc_graph *g, bool batch) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1024;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1024;
-    per_cu = kc::persistent_blocks_per_cu(g->chains);
+    per_cu = batch ? kc::batch_blocks_per_cu(g->chains) : kc::persistent_blocks_per_cu(g->chains);
     if (cus <= 0 || per_cu <= 0) return 1024;
     return cus * per_cu;
+}
+
+// Workspace bytes a launch may allocate: the graph's budget option, else 80%
+// of the device memory free before the allocation.
+int64_t kc_host::workspace_budget(const kc_graph *g, size_t free_b) {
+    return g->mem_budget > 0 ? g->mem_budget : (int64_t)(0.8 * (double)free_b);
 }
 
 

@@ -93,7 +93,8 @@ kc_status fail(kc_status st, const char *fmt, ...);
 // arrays (trav) and the sweep's Fenwick tree (fen).
 int64_t slot_bytes(const kc_graph *g, bool trav, bool fen);
 // Samples in flight when the graph's slots option is 0: resident workgroups of the kernel.
-int default_slots(const kc_graph *g);
+int default_slots(const kc_graph *g, bool batch = false);  // resident workgroups of the launch's kernel
+int64_t workspace_budget(const kc_graph *g, size_t free_b);
 // Slots that split `count` samples into equal waves (at most `slots`).
 int balanced_slots(int slots, int64_t count);
 // The graph's device arrays as the kernels see them.

@@ -132,6 +132,7 @@ hipError_t launch_flag_trees(const int32_t *par, int32_t count, int64_t n, const
                              const int32_t *ev, int32_t ne, uint8_t *flags, hipStream_t stream);
 bool valid_chains(int chains);            // a built chain-table size?
 int persistent_blocks_per_cu(int chains);  // resident workgroups per CU for that size
+int batch_blocks_per_cu(int chains);       // the same for the batch kernel
 int sampler_chains();                      // queue / chain-start entries to allocate per slot
 
 }  // namespace kc

@@ -109,7 +109,7 @@ extern "C" kc_status kc_autotune(kc_graph *g, int32_t count, const char *cache_p
     if (st != KC_OK) return st;
     size_t free_b = 0, total_b = 0;
     HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-    const int64_t budget = g->mem_budget > 0 ? g->mem_budget : (int64_t)(0.6 * (double)free_b);
+    const int64_t budget = workspace_budget(g, free_b);
     const int64_t fit = budget / std::max<int64_t>(1, slot_bytes(g, true, g->traversal == KC_TRAV_SWEEP));
     const int full = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(default_slots(g), count), fit));
     // trial estimates: one wave of samples in flight (at least 64), on sample ids far
