@@ -21,9 +21,9 @@ struct kc_batch {
     int slots = 0, chains = 1024;
     int64_t total = 0;
     // device memory owned by the batch
-    uint64_t *d_tagw = nullptr, *d_arrow = nullptr;
-    int32_t *d_rq = nullptr, *d_cstart = nullptr, *d_grp = nullptr, *d_ctl = nullptr;
-    int4 *d_queue = nullptr, *d_rec = nullptr, *d_ord = nullptr;
+    unsigned char *d_state = nullptr;
+    int32_t *d_cstart = nullptr, *d_ctl = nullptr;
+    int4 *d_queue = nullptr, *d_rec = nullptr;
     int64_t *d_fen = nullptr, *d_f = nullptr, *d_steps = nullptr, *d_iters = nullptr, *d_launch = nullptr;
     kc::ReduceOut *d_red = nullptr;
     hipStream_t cap = nullptr;
@@ -37,8 +37,8 @@ void batch_free(kc_batch *b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
-    void *bufs[] = {b->d_tagw, b->d_arrow, b->d_rq, b->d_cstart, b->d_grp, b->d_ctl, b->d_queue, b->d_rec,
-                    b->d_ord, b->d_fen, b->d_f, b->d_steps, b->d_iters, b->d_launch, b->d_red};
+    void *bufs[] = {b->d_state, b->d_cstart, b->d_ctl, b->d_queue, b->d_rec, b->d_fen, b->d_f, b->d_steps,
+                    b->d_iters, b->d_launch, b->d_red};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     delete b;
@@ -95,7 +95,7 @@ kc_status kc_batch_create(kc_graph *const *graphs, int32_t k, const uint64_t *se
     // samples in flight: the first graph's slots option (else the kernel's resident
     // workgroups), within its memory budget for slots sized for the largest graph
     const size_t n = (size_t)max_n, ch = (size_t)kc::sampler_chains();
-    const int64_t per_slot = (int64_t)(20 * n + 20 * ch + 16 * n + 16 * n + 4 * (n + 1) + 8 * (size_t)max_fen);
+    const int64_t per_slot = kc::state_bytes(max_n) + (int64_t)(20 * ch + 16 * n + 8 * (size_t)max_fen);
     int want = graphs[0]->slots_opt > 0 ? graphs[0]->slots_opt : default_slots(graphs[0], true);
     want = (int)std::min<int64_t>(want, total);
     size_t free_b = 0, total_b = 0;
@@ -114,14 +114,10 @@ kc_status kc_batch_create(kc_graph *const *graphs, int32_t k, const uint64_t *se
     }
     b->slots = slots;
     const size_t S = (size_t)slots;
-    e = alloc_n(&b->d_tagw, S * n);
-    if (e == hipSuccess) e = alloc_n(&b->d_arrow, S * n);
-    if (e == hipSuccess) e = alloc_n(&b->d_rq, S * n);
+    e = alloc_n(&b->d_state, S * (size_t)kc::state_bytes(max_n));
     if (e == hipSuccess) e = alloc_n(&b->d_queue, S * ch);
     if (e == hipSuccess) e = alloc_n(&b->d_cstart, S * ch);
     if (e == hipSuccess) e = alloc_n(&b->d_rec, S * n);
-    if (e == hipSuccess) e = alloc_n(&b->d_ord, S * n);
-    if (e == hipSuccess) e = alloc_n(&b->d_grp, S * (n + 1));
     if (e == hipSuccess && max_fen > 0) e = alloc_n(&b->d_fen, S * (size_t)max_fen);
     if (e == hipSuccess) e = alloc_n(&b->d_f, (size_t)total);
     if (e == hipSuccess) e = alloc_n(&b->d_steps, (size_t)total);
@@ -138,15 +134,11 @@ kc_status kc_batch_create(kc_graph *const *graphs, int32_t k, const uint64_t *se
         return fail(e == hipErrorOutOfMemory ? KC_ERR_NOMEM : KC_ERR_DEVICE, "batch set-up: %s", hipGetErrorString(e));
     }
     kc::SlotDev &sd = b->sd;
-    sd.tagw = b->d_tagw;
-    sd.arrow = b->d_arrow;
-    sd.rq = b->d_rq;
+    sd.state = b->d_state;
     sd.queue = b->d_queue;
     sd.cstart = b->d_cstart;
     sd.chains = (int64_t)ch;
     sd.rec = b->d_rec;
-    sd.ord = b->d_ord;
-    sd.grp = b->d_grp;
     sd.fen = b->d_fen;
     sd.fen_len = max_fen;
     sd.stride = max_n;

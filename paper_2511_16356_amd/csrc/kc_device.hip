@@ -682,14 +682,42 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
 
 // --------------------------------------------------------- tree traversal
 
+// The numbered tree: one 16-byte record per vertex, two 8-byte words, so that
+// every step of the numbering touches one line per vertex it visits:
+//   rec[2v]     pending children << 44 | volume while the volumes are summed;
+//               from the vertex's own top-down step on, the next free tin of its
+//               interval (tin + deg, plus the volumes of the children placed so
+//               far); tin(v) + vol(v) once the numbering is done
+//   rec[2v + 1] parent (low half, -1 at the root) | deg(v) (high half) until the
+//               top-down step, then parent | tin(v)
 struct SlotPtrs {
     SamplerWS ws;
-    uint64_t *word, *rec;  // rec: 2 words per vertex {vol<<32 | tin, parent}
-    int4 *ord;             // finished vertices {v, parent, vol, 0} in completion order; the
-                           // leaves {v, parent, deg, 0} wait at the end of the same array
+    uint64_t *rec;
+    int4 *ord;             // finished vertices {v, parent, vol, deg} in completion order; the
+                           // leaves {v, parent, deg, deg} wait at the end of the same array
     int32_t *grp;
     int64_t *fen;
 };
+
+__device__ __forceinline__ int32_t rec_parent(const uint64_t *rec, int v) {
+    return (int32_t)(uint32_t)aload(&rec[2 * (size_t)v + 1]);
+}
+// The numbering of a vertex once it is complete: tin, vol and tree parent.
+struct TNum {
+    uint32_t tin, vol;
+    int32_t par;
+};
+__device__ __forceinline__ TNum rec_num(const uint64_t *rec, int v) {
+    const uint64_t w = aload(&rec[2 * (size_t)v]), h = aload(&rec[2 * (size_t)v + 1]);
+    TNum t;
+    t.tin = (uint32_t)(h >> 32);
+    t.vol = (uint32_t)(w - (h >> 32));
+    t.par = (int32_t)(uint32_t)h;
+    return t;
+}
+__device__ __forceinline__ uint32_t rec_tin(const uint64_t *rec, int v) {
+    return (uint32_t)(aload(&rec[2 * (size_t)v + 1]) >> 32);
+}
 
 // Vertices each lane keeps in flight in the tree numbering: the memory
 // operations of one step are issued together, so a wavefront has this many
@@ -735,19 +763,15 @@ struct Items {
 __device__ __forceinline__ Items items_of(const GraphDev &g, const uint64_t *rec, int x) {
     Items it{0u, 0u, 0u, 0u, 0, 0};
     if (x == g.root) return it;
-    const uint64_t rx = aload(&rec[2 * (size_t)x]);
-    const int32_t px = (int32_t)aload(&rec[2 * (size_t)x + 1]);
+    const TNum nx = rec_num(rec, x);
     const int z = g.p0[x];
-    if (px == z) {
-        const uint32_t t = (uint32_t)rx, vol = (uint32_t)(rx >> 32);
-        it.flo = t; it.fhi = t + vol; it.fw = g.two_m - (int64_t)vol;
+    if (nx.par == z) {
+        it.flo = nx.tin; it.fhi = nx.tin + nx.vol; it.fw = g.two_m - (int64_t)nx.vol;
     }
     if (z != g.root) {
-        const uint64_t rz = aload(&rec[2 * (size_t)z]);
-        const int32_t pz = (int32_t)aload(&rec[2 * (size_t)z + 1]);
-        if (pz == x) {
-            const uint32_t t = (uint32_t)rz, vol = (uint32_t)(rz >> 32);
-            it.rlo = t; it.rhi = t + vol; it.rw = (int64_t)vol - g.two_m;
+        const TNum nz = rec_num(rec, z);
+        if (nz.par == x) {
+            it.rlo = nz.tin; it.rhi = nz.tin + nz.vol; it.rw = (int64_t)nz.vol - g.two_m;
         }
     }
     return it;
@@ -760,8 +784,8 @@ __device__ __forceinline__ int64_t items_at(const Items &it, uint32_t t) {
 }
 
 // Volumes and the volume-weighted preorder of the tree whose parents are in
-// rec[2v+1] (word[v] = deg(v) already).  Returns false if the parents do not
-// form a tree rooted at r.
+// rec (rec[2v] = deg(v), rec[2v+1] = parent | deg(v) << 32 already).  Returns
+// false if the parents do not form a tree rooted at r.
 //
 // Bottom-up: each lane carries up to NB finished vertices; a carrier pushes
 // its vertex's volume into the parent's word with one atomic, and the last
@@ -779,30 +803,30 @@ __device__ bool tree_numbering(const GraphDev &g, const SlotPtrs &sp) {
 #pragma unroll
         for (int k = 0; k < NBS; ++k) {
             const int v = b + k * WAVE + lane;
-            p[k] = v < n ? (int32_t)aload(&sp.rec[2 * (size_t)v + 1]) : -1;
+            p[k] = v < n ? rec_parent(sp.rec, v) : -1;
         }
 #pragma unroll
         for (int k = 0; k < NBS; ++k)
-            if (p[k] >= 0) afetch_add(&sp.word[p[k]], PEND_ONE);
+            if (p[k] >= 0) afetch_add(&sp.rec[2 * (size_t)p[k]], PEND_ONE);
     }
     fence_wg();
-    // leaves {v, parent, deg}: leaf number j at ord[n - 1 - j]
+    // leaves {v, parent, deg, deg}: leaf number j at ord[n - 1 - j]
     int L = 0;
     for (int b = 0; b < n; b += WAVE * NBS) {
-        uint64_t w[NBS];
-        int32_t p[NBS];
+        uint64_t w[NBS], h[NBS];
 #pragma unroll
         for (int k = 0; k < NBS; ++k) {
             const int v = b + k * WAVE + lane;
-            w[k] = v < n ? aload(&sp.word[v]) : PEND_ONE;  // past the end: not a leaf
-            p[k] = v < n ? (int32_t)aload(&sp.rec[2 * (size_t)v + 1]) : -1;
+            w[k] = v < n ? aload(&sp.rec[2 * (size_t)v]) : PEND_ONE;  // past the end: not a leaf
+            h[k] = v < n ? aload(&sp.rec[2 * (size_t)v + 1]) : 0;
         }
 #pragma unroll
         for (int k = 0; k < NBS; ++k) {
             const bool leaf = (w[k] >> 44) == 0;
             const uint64_t m = __ballot(leaf);
             if (leaf)
-                sp.ord[n - 1 - (L + rank_in(m))] = make_int4(b + k * WAVE + lane, p[k], (int)(w[k] & VOL_MASK), 0);
+                sp.ord[n - 1 - (L + rank_in(m))] = make_int4(b + k * WAVE + lane, (int32_t)(uint32_t)h[k],
+                                                             (int)(w[k] & VOL_MASK), (int)(h[k] >> 32));
             L += __popcll(m);
         }
     }
@@ -810,10 +834,10 @@ __device__ bool tree_numbering(const GraphDev &g, const SlotPtrs &sp) {
     // bottom-up.  Leaves are taken from the low end of their block, ord[n-L ..]:
     // the finished entries written at ord[0 .. nord) never reach an untaken leaf,
     // since nord + (leaves not yet taken) <= n.
-    int cv[NB], cp[NB];
+    int cv[NB], cp[NB], cdeg[NB];
     uint64_t cval[NB];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) { cv[k] = -1; cp[k] = -1; cval[k] = 0; }
+    for (int k = 0; k < NB; ++k) { cv[k] = -1; cp[k] = -1; cdeg[k] = 0; cval[k] = 0; }
     int li = 0, nord = 0, ngrp = 0;
     while (true) {
         if (li < L) {
@@ -826,6 +850,7 @@ __device__ bool tree_numbering(const GraphDev &g, const SlotPtrs &sp) {
                     cv[k] = e.x;
                     cp[k] = e.y;
                     cval[k] = (uint64_t)(uint32_t)e.z;
+                    cdeg[k] = e.w;
                 }
                 li = min(L, li + (int)__popcll(freem));
             }
@@ -840,10 +865,10 @@ __device__ bool tree_numbering(const GraphDev &g, const SlotPtrs &sp) {
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
             const uint64_t bm = __ballot(cv[k] >= 0);
-            if (cv[k] >= 0) sp.ord[nord + rank_in(bm)] = make_int4(cv[k], cp[k], (int)cval[k], 0);
+            if (cv[k] >= 0) sp.ord[nord + rank_in(bm)] = make_int4(cv[k], cp[k], (int)cval[k], cdeg[k]);
             nord += __popcll(bm);
             old[k] = 0;
-            if (cv[k] >= 0 && cp[k] >= 0) old[k] = afetch_add(&sp.word[cp[k]], cval[k] - PEND_ONE);
+            if (cv[k] >= 0 && cp[k] >= 0) old[k] = afetch_add(&sp.rec[2 * (size_t)cp[k]], cval[k] - PEND_ONE);
         }
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
@@ -851,9 +876,15 @@ __device__ bool tree_numbering(const GraphDev &g, const SlotPtrs &sp) {
             cv[k] = last ? cp[k] : -1;
             if (last) cval[k] = (old[k] & VOL_MASK) + cval[k];
         }
+        // the new carrier's parent and degree, from the record line the atomic just used
 #pragma unroll
-        for (int k = 0; k < NB; ++k)
-            if (cv[k] >= 0) cp[k] = (int32_t)aload(&sp.rec[2 * (size_t)cv[k] + 1]);
+        for (int k = 0; k < NB; ++k) {
+            if (cv[k] >= 0) {
+                const uint64_t h = aload(&sp.rec[2 * (size_t)cv[k] + 1]);
+                cp[k] = (int32_t)(uint32_t)h;
+                cdeg[k] = (int)(h >> 32);
+            }
+        }
         if (nord > n) break;  // more entries than vertices: not a tree
     }
     if (lane == 0) astore(&sp.grp[ngrp], nord);
@@ -873,24 +904,20 @@ __device__ bool tree_numbering(const GraphDev &g, const SlotPtrs &sp) {
                     const int i = i0 + k * WAVE + lane;
                     e[k] = i < hi ? sp.ord[i] : make_int4(-1, -1, 0, 0);
                 }
-                uint64_t rp[NB], old[NB];
-                uint32_t dp[NB];
+                // a vertex's tin is the next free position of its parent's interval,
+                // taken with one atomic on the parent's word
+                uint64_t tin[NB];
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
-                    rp[k] = 0; old[k] = 0; dp[k] = 0;
-                    if (e[k].x >= 0 && e[k].y >= 0) {
-                        rp[k] = aload(&sp.rec[2 * (size_t)e[k].y]);
-                        old[k] = afetch_add(&sp.word[e[k].y], (uint64_t)(uint32_t)e[k].z);
-                        dp[k] = degree(g, e[k].y);
-                    }
+                    tin[k] = 0;
+                    if (e[k].x >= 0 && e[k].y >= 0)
+                        tin[k] = afetch_add(&sp.rec[2 * (size_t)e[k].y], (uint64_t)(uint32_t)e[k].z);
                 }
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
                     if (e[k].x < 0) continue;
-                    const uint64_t vol = (uint32_t)e[k].z;
-                    uint64_t tin = 0;
-                    if (e[k].y >= 0) tin = (rp[k] & 0xFFFFFFFFull) + dp[k] + (old[k] - (rp[k] >> 32));
-                    astore(&sp.rec[2 * (size_t)e[k].x], (vol << 32) | tin);
+                    astore(&sp.rec[2 * (size_t)e[k].x], tin[k] + (uint64_t)(uint32_t)e[k].w);
+                    astore(&sp.rec[2 * (size_t)e[k].x + 1], (uint64_t)(uint32_t)e[k].y | (tin[k] << 32));
                 }
             }
             fence_wg();  // the next group reads the intervals of this one
@@ -918,41 +945,32 @@ __device__ __forceinline__ int64_t q_of_table(const GraphDev &g, const SlotPtrs 
     int z[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) z[i] = g.anc0[(size_t)i * n + (size_t)u];
-    uint64_t rz[D];
-    int32_t pz[D];
+    TNum nz[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-        rz[i] = 0;
-        pz[i] = -2;
-        if (z[i] >= 0 && z[i] != root) {
-            rz[i] = aload(&sp.rec[2 * (size_t)z[i]]);
-            pz[i] = (int32_t)aload(&sp.rec[2 * (size_t)z[i] + 1]);
-        }
+        nz[i] = TNum{0u, 0u, -2};
+        if (z[i] >= 0 && z[i] != root) nz[i] = rec_num(sp.rec, z[i]);
     }
-    const uint64_t ru = aload(&sp.rec[2 * (size_t)u]);
-    const uint32_t tu = (uint32_t)ru;
+    const TNum nu = rec_num(sp.rec, u);
+    const uint32_t tu = nu.tin;
     int x = u;
-    uint64_t rx = ru;
-    int32_t px = (int32_t)aload(&sp.rec[2 * (size_t)u + 1]);
+    TNum nx = nu;
     int64_t q = 0;
     bool go = u != root;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
         if (go && z[i] >= 0) {
-            if (px == z[i]) {
-                const uint32_t t = (uint32_t)rx, vol = (uint32_t)(rx >> 32);
-                if (t <= tu && tu < t + vol) q += two_m - (int64_t)vol;
+            if (nx.par == z[i]) {
+                if (nx.tin <= tu && tu < nx.tin + nx.vol) q += two_m - (int64_t)nx.vol;
             }
             if (z[i] == root) {
                 go = false;
             } else {
-                if (pz[i] == x) {
-                    const uint32_t t = (uint32_t)rz[i], vol = (uint32_t)(rz[i] >> 32);
-                    if (t <= tu && tu < t + vol) q -= two_m - (int64_t)vol;
+                if (nz[i].par == x) {
+                    if (nz[i].tin <= tu && tu < nz[i].tin + nz[i].vol) q -= two_m - (int64_t)nz[i].vol;
                 }
                 x = z[i];
-                rx = rz[i];
-                px = pz[i];
+                nx = nz[i];
             }
         }
     }
@@ -991,28 +1009,23 @@ __device__ int64_t f_walk(const GraphDev &g, const SlotPtrs &sp) {
     const int64_t two_m = g.two_m;
     int64_t acc = 0;
     for (int u = lane; u < n; u += WAVE) {
-        const uint64_t ru = aload(&sp.rec[2 * (size_t)u]);
-        const uint32_t tu = (uint32_t)ru;
+        const TNum nu = rec_num(sp.rec, u);
+        const uint32_t tu = nu.tin;
         int64_t q = 0;
         int x = u;
-        uint64_t rx = ru;
-        int32_t px = (int32_t)aload(&sp.rec[2 * (size_t)u + 1]);
+        TNum nx = nu;
         while (x != root) {
             const int z = g.p0[x];
-            if (px == z) {
-                const uint32_t t = (uint32_t)rx, vol = (uint32_t)(rx >> 32);
-                if (t <= tu && tu < t + vol) q += two_m - (int64_t)vol;
+            if (nx.par == z) {
+                if (nx.tin <= tu && tu < nx.tin + nx.vol) q += two_m - (int64_t)nx.vol;
             }
             if (z == root) break;
-            const uint64_t rz = aload(&sp.rec[2 * (size_t)z]);
-            const int32_t pz = (int32_t)aload(&sp.rec[2 * (size_t)z + 1]);
-            if (pz == x) {
-                const uint32_t t = (uint32_t)rz, vol = (uint32_t)(rz >> 32);
-                if (t <= tu && tu < t + vol) q -= two_m - (int64_t)vol;
+            const TNum nz = rec_num(sp.rec, z);
+            if (nz.par == x) {
+                if (nz.tin <= tu && tu < nz.tin + nz.vol) q -= two_m - (int64_t)nz.vol;
             }
             x = z;
-            rx = rz;
-            px = pz;
+            nx = nz;
         }
         acc += (int64_t)degree(g, u) * q;
     }
@@ -1051,7 +1064,7 @@ __device__ int64_t f_sweep(const GraphDev &g, const SlotPtrs &sp, int64_t fen_le
             u = g.pre0[p];
             it = items_of(g, sp.rec, u);
             o = g.out0[u];
-            tu = (uint32_t)aload(&sp.rec[2 * (size_t)u]);
+            tu = rec_tin(sp.rec, u);
         }
         int64_t S = valid ? fen_prefix(sp.fen, fen_len, tu) : 0;
         sh_it[lane] = it;
@@ -1108,24 +1121,15 @@ __device__ int64_t f_sweep(const GraphDev &g, const SlotPtrs &sp, int64_t fen_le
 __device__ int64_t path_current(const SlotPtrs &sp, const int32_t *path, int len) {
     const int lane = threadIdx.x;
     const int u = path[0], v = path[len - 1];
-    auto tinv = [&](int x, uint32_t &t, uint32_t &vol) {
-        const uint64_t r = aload(&sp.rec[2 * (size_t)x]);
-        t = (uint32_t)r;
-        vol = (uint32_t)(r >> 32);
-    };
-    uint32_t tu, vu, tv, vv;
-    tinv(u, tu, vu);
-    tinv(v, tv, vv);
+    const uint32_t tu = rec_tin(sp.rec, u), tv = rec_tin(sp.rec, v);
     auto anc_u = [&](uint32_t t, uint32_t vol) { return t <= tu && tu < t + vol; };
     auto anc_v = [&](uint32_t t, uint32_t vol) { return t <= tv && tv < t + vol; };
     int64_t c = 0;
     for (int i = lane; i + 1 < len; i += WAVE) {
         const int a = path[i], b = path[i + 1];
-        uint32_t ta, va, tb, vb;
-        tinv(a, ta, va);
-        tinv(b, tb, vb);
-        const int32_t pa = (int32_t)aload(&sp.rec[2 * (size_t)a + 1]);
-        const int32_t pb = (int32_t)aload(&sp.rec[2 * (size_t)b + 1]);
+        const TNum na = rec_num(sp.rec, a), nb = rec_num(sp.rec, b);
+        const uint32_t ta = na.tin, va = na.vol, tb = nb.tin, vb = nb.vol;
+        const int32_t pa = na.par, pb = nb.par;
         const bool up_a = anc_u(ta, va) && !anc_v(ta, va), up_b = anc_u(tb, vb) && !anc_v(tb, vb);
         const bool dn_a = anc_v(ta, va) && !anc_u(ta, va), dn_b = anc_v(tb, vb) && !anc_u(tb, vb);
         if ((up_a && pa == b) || (dn_b && pb == a)) c += 1;
@@ -1146,17 +1150,17 @@ __device__ int64_t crossing_edges(const GraphDev &g, const SlotPtrs &sp, const R
     const int lane = threadIdx.x;
     const int n = g.n;
     const int a = rp.cut_u, b = rp.cut_v;
-    const int32_t pa = (int32_t)aload(&sp.rec[2 * (size_t)a + 1]);
-    const int32_t pb = (int32_t)aload(&sp.rec[2 * (size_t)b + 1]);
+    const int32_t pa = rec_parent(sp.rec, a);
+    const int32_t pb = rec_parent(sp.rec, b);
     const int c = pa == b ? a : (pb == a ? b : -1);
     if (c < 0) {
         report_error(rp.ctl, DEV_BADTREE, idx);
         return 0;
     }
-    const uint64_t rc = aload(&sp.rec[2 * (size_t)c]);
-    const uint32_t lo = (uint32_t)rc, hi = lo + (uint32_t)(rc >> 32);
+    const TNum nc = rec_num(sp.rec, c);
+    const uint32_t lo = nc.tin, hi = nc.tin + nc.vol;
     auto inside = [&](int x) {
-        const uint32_t t = (uint32_t)aload(&sp.rec[2 * (size_t)x]);
+        const uint32_t t = rec_tin(sp.rec, x);
         return lo <= t && t < hi;
     };
     auto row_count = [&](int x, bool ix) {
@@ -1206,7 +1210,7 @@ __device__ int64_t crossing_edges(const GraphDev &g, const SlotPtrs &sp, const R
                     int32_t *out = rp.parents_mut + (size_t)slot * (size_t)n;
                     int32_t prev = yo, z = xi;
                     for (int guard = 0; guard <= n; ++guard) {
-                        const int32_t nz = (int32_t)aload(&sp.rec[2 * (size_t)z + 1]);
+                        const int32_t nz = rec_parent(sp.rec, z);
                         out[z] = prev;
                         if (z == c) break;
                         if (nz < 0 || nz >= n) {  // c is an ancestor of xi: not reached
@@ -1238,16 +1242,16 @@ union KernelShared {
 __device__ __forceinline__ SlotPtrs slot_ptrs(const SlotDev &sd, size_t stride) {
     SlotPtrs sp;
     const size_t b = (size_t)blockIdx.x;
-    sp.ws.tagw = sd.tagw + b * stride;
-    sp.ws.arrow = sd.arrow + b * stride;
-    sp.ws.rq = sd.rq + b * stride;
+    unsigned char *st = sd.state + b * (size_t)state_bytes((int64_t)stride);
+    sp.ws.tagw = reinterpret_cast<uint64_t *>(st);
+    sp.ws.arrow = reinterpret_cast<uint64_t *>(st + 8 * stride);
+    sp.ws.rq = reinterpret_cast<int32_t *>(st + 16 * stride);
     sp.ws.queue = sd.queue + b * (size_t)sd.chains;
     sp.ws.start = sd.cstart + b * (size_t)sd.chains;
-    // the numbering's word array reuses the sampler's tag words (dead once the tree is drawn)
-    sp.word = sd.rec ? sp.ws.tagw : nullptr;
     sp.rec = sd.rec ? reinterpret_cast<uint64_t *>(sd.rec) + 2 * b * stride : nullptr;
-    sp.ord = sd.ord ? sd.ord + b * stride : nullptr;
-    sp.grp = sd.grp ? sd.grp + b * (stride + 1) : nullptr;
+    // the numbering's arrays reuse the sampler's block (dead once the parents are in rec)
+    sp.ord = sd.rec ? reinterpret_cast<int4 *>(st) : nullptr;
+    sp.grp = sd.rec ? reinterpret_cast<int32_t *>(st + 16 * stride) : nullptr;
     sp.fen = sd.fen ? sd.fen + b * (size_t)sd.fen_len : nullptr;
     return sp;
 }
@@ -1277,7 +1281,7 @@ __device__ bool process_one(const GraphDev &g, const SlotPtrs &sp, KernelShared<
             if (co) co[v] = (uint32_t)(ar >> 32);
         }
     } else {
-        // parents into rec[2v+1]; the numbering's volume words start at deg(v)
+        // parent and degree into each vertex's tree record; its volume word starts at deg(v)
         const size_t row = rp.rows ? (size_t)rp.rows[idx] : (size_t)idx;
         bool bad = false;
         for (int b = 0; b < g.n; b += WAVE * NBS) {
@@ -1295,8 +1299,9 @@ __device__ bool process_one(const GraphDev &g, const SlotPtrs &sp, KernelShared<
                 const int v = b + k * WAVE + lane;
                 if (v >= g.n) continue;
                 if (v != g.root && (p[k] < 0 || p[k] >= g.n || p[k] == v)) { bad = true; p[k] = g.root; }
-                astore(&sp.rec[2 * (size_t)v + 1], (uint64_t)(uint32_t)p[k]);
-                astore(&sp.word[v], (uint64_t)degree(g, v));
+                const uint64_t d = degree(g, v);
+                astore(&sp.rec[2 * (size_t)v], d);
+                astore(&sp.rec[2 * (size_t)v + 1], (uint64_t)(uint32_t)p[k] | (d << 32));
             }
         }
         fence_wg();

@@ -86,13 +86,10 @@ int64_t parallel_first(int64_t n, F body) {
 namespace {
 
 void free_workspace(kc_graph *g) {
-    dev_free(g->d_tagw); dev_free(g->d_arrow); dev_free(g->d_rq);
-    dev_free(g->d_queue); dev_free(g->d_cstart); dev_free(g->d_rec); dev_free(g->d_ord);
-    dev_free(g->d_grp); dev_free(g->d_fen);
-    g->d_tagw = g->d_arrow = nullptr; g->d_rq = nullptr; g->d_queue = nullptr;
-    g->d_cstart = nullptr;
-    g->d_rec = nullptr; g->d_ord = nullptr;
-    g->d_grp = nullptr; g->d_fen = nullptr;
+    dev_free(g->d_state); dev_free(g->d_queue); dev_free(g->d_cstart); dev_free(g->d_rec);
+    dev_free(g->d_fen);
+    g->d_state = nullptr; g->d_queue = nullptr; g->d_cstart = nullptr;
+    g->d_rec = nullptr; g->d_fen = nullptr;
     g->ws_slots = 0; g->ws_asked = 0; g->ws_trav = g->ws_fen = false;
 }
 
@@ -134,8 +131,9 @@ std::vector<int32_t> start_order_of(const std::vector<int32_t> &bfs, int kind) {
 }  // namespace
 
 int64_t kc_host::slot_bytes(const kc_graph *g, bool trav, bool fen) {
-    int64_t b = 20 * g->n + 20 * (int64_t)kc::sampler_chains();  // state records, restart ring, tasks
-    if (trav) b += 16 * g->n + 16 * g->n + 4 * (g->n + 1);  // rec, ord, grp (word reuses tagw)
+    // sampler state (reused by the numbering's ord and grp), tasks and chain starts
+    int64_t b = kc::state_bytes(g->n) + 20 * (int64_t)kc::sampler_chains();
+    if (trav) b += 16 * g->n;  // rec
     if (fen) b += 8 * (g->two_m + 2);
     return b;
 }
@@ -166,16 +164,10 @@ kc_status ensure_workspace(kc_graph *g, int want, bool trav, bool fen, hipStream
                              (long long)per, (long long)budget);
     int slots = (int)std::min<int64_t>(want, fit);
     const size_t n = (size_t)g->n;
-    HIP_TRY(dev_alloc(&g->d_tagw, (size_t)slots * n));
-    HIP_TRY(dev_alloc(&g->d_arrow, (size_t)slots * n));
-    HIP_TRY(dev_alloc(&g->d_rq, (size_t)slots * n));
+    HIP_TRY(dev_alloc(&g->d_state, (size_t)slots * (size_t)kc::state_bytes(g->n)));
     HIP_TRY(dev_alloc(&g->d_queue, (size_t)slots * (size_t)kc::sampler_chains()));
     HIP_TRY(dev_alloc(&g->d_cstart, (size_t)slots * (size_t)kc::sampler_chains()));
-    if (trav) {
-        HIP_TRY(dev_alloc(&g->d_rec, (size_t)slots * n));
-        HIP_TRY(dev_alloc(&g->d_ord, (size_t)slots * n));
-        HIP_TRY(dev_alloc(&g->d_grp, (size_t)slots * (n + 1)));
-    }
+    if (trav) HIP_TRY(dev_alloc(&g->d_rec, (size_t)slots * n));
     if (fen) {
         const int64_t len = (int64_t)slots * (g->two_m + 2);
         HIP_TRY(dev_alloc(&g->d_fen, (size_t)len));
@@ -299,15 +291,12 @@ kc_status run_persistent(kc_graph *g, kc::RunParams rp, hipStream_t stream) {
     if (st != KC_OK) return st;
     slots = balanced_slots(slots, rp.count);
     kc::SlotDev sd;
-    sd.tagw = g->d_tagw;
-    sd.arrow = g->d_arrow;
-    sd.rq = g->d_rq;
+    sd.state = g->d_state;
     sd.queue = g->d_queue;
     sd.cstart = g->d_cstart;
     sd.chains = kc::sampler_chains();
     sd.rec = trav ? g->d_rec : nullptr;
-    sd.ord = trav ? g->d_ord : nullptr;
-    sd.grp = trav ? g->d_grp : nullptr;
+    sd.stride = g->n;
     sd.fen = fen ? g->d_fen : nullptr;
     sd.fen_len = fen ? g->two_m + 2 : 0;
     fill_run_options(g, rp);

@@ -59,13 +59,10 @@ struct kc_graph {
     int ws_asked = 0;         // slots the allocation was asked for (the budget may have held fewer)
     bool ws_trav = false, ws_fen = false;
     int64_t ws_fen_len = 0;  // per-slot Fenwick length the buffer was sized for (2m + 2)
-    uint64_t *d_tagw = nullptr, *d_arrow = nullptr;
-    int32_t *d_rq = nullptr;
+    unsigned char *d_state = nullptr;  // per slot: kc::state_bytes(n)
     int4 *d_queue = nullptr;
     int32_t *d_cstart = nullptr;
     int4 *d_rec = nullptr;
-    int4 *d_ord = nullptr;
-    int32_t *d_grp = nullptr;
     int64_t *d_fen = nullptr;
     int64_t *d_f = nullptr, *d_steps = nullptr, *d_iters = nullptr;  // internal per-sample buffers
     int64_t fbuf_len = 0;

@@ -28,21 +28,30 @@ struct GraphDev {
 };
 
 // Per-slot workspace: one slot = one sample in flight = one wavefront.
+//
+// A slot's state block (state_bytes(stride) bytes) holds the sampler's arrays:
+//   tag words  uint64 [stride] at 0: tag/flag bits | first parked chain + 1 << 32
+//   arrow words uint64 [stride] at 8 stride: arrow target | draws << 32
+//   restart ring int32 [stride] at 16 stride
+// Once the tree's parents are copied into rec they are dead, and the tree
+// numbering reuses the block:
+//   ord  int4 [stride] at 0: finished vertices {v, parent, vol, deg}, leaves {v, parent, deg, deg}
+//   grp  int32 [stride + 1] at 16 stride: completion group boundaries
 struct SlotDev {
-    uint64_t *tagw;  // [slots*n] sampler: tag/flag bits | first parked chain + 1 << 32
-    uint64_t *arrow; // [slots*n] sampler: arrow target | draws << 32
-    int32_t *rq;     // [slots*n] sampler: restart queue
+    unsigned char *state; // [slots * state_bytes(stride)]
     int4 *queue;     // [slots*chains] sampler: ready tasks
     int32_t *cstart; // [slots*chains] sampler: chain start vertices
     int64_t chains;  // per-slot stride of queue and cstart
-    int4 *rec;       // [slots*n] {tin, vol, parent, unused}; null without the traversal
-                     // (the numbering's pending-children | volume words reuse tagw)
-    int4 *ord;       // [slots*n] finished vertices {v, parent, vol} and leaves {v, parent, deg}
-    int32_t *grp;    // [slots*(n+1)] completion group boundaries
+    int4 *rec;       // [slots*stride] the numbered tree, 16 bytes per vertex: numbering word, then
+                     // parent | deg, later parent | tin; null without the traversal
     int64_t *fen;    // [slots*fen_len] Fenwick tree (sweep traversal only)
     int64_t fen_len; // per-slot length of fen: 2m + 2 (0 if not allocated)
-    int64_t stride;  // vertices per slot in the n-sized arrays (a batch: its largest graph's n)
+    int64_t stride;  // vertices per slot (a batch: its largest graph's n)
 };
+
+// Bytes of one slot's state block: 20 bytes per vertex, the 4 of grp's last
+// entry, rounded up to 256 so that every slot's block starts 256-aligned.
+__host__ __device__ inline int64_t state_bytes(int64_t stride) { return (20 * stride + 4 + 255) / 256 * 256; }
 
 // One graph's share of a batch launch (batch_kernel).
 struct BatchJob {

@@ -83,9 +83,8 @@ extern "C" kc_status kc_estimate_static(kc_graph *g, uint64_t seed, int64_t firs
     // bytes of the slot arrays for s samples in flight, each array starting on 256 bytes
     auto r256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
     auto need = [&](size_t s) {
-        return r256(8 * s * n) + r256(8 * s * n) + r256(4 * s * n) + r256(16 * s * chains) +
-               r256(4 * s * chains) + r256(16 * s * n) + r256(16 * s * n) + r256(4 * s * (n + 1)) +
-               (fen ? r256(8 * s * (size_t)(g->two_m + 2)) : 0);
+        return r256(s * (size_t)kc::state_bytes(g->n)) + r256(16 * s * chains) + r256(4 * s * chains) +
+               r256(16 * s * n) + (fen ? r256(8 * s * (size_t)(g->two_m + 2)) : 0);
     };
     const size_t room = STATIC_SCRATCH_BYTES - r256(c.used);
     int slots = g->slots_opt > 0 ? g->slots_opt : default_slots(g);
@@ -96,19 +95,15 @@ extern "C" kc_status kc_estimate_static(kc_graph *g, uint64_t seed, int64_t firs
                     "workspace are left after the per-sample results", need(1), room, STATIC_SCRATCH_BYTES);
     slots = balanced_slots(slots, count);
     kc::SlotDev sd;
-    sd.tagw = c.take<uint64_t>((size_t)slots * n);
-    sd.arrow = c.take<uint64_t>((size_t)slots * n);
-    sd.rq = c.take<int32_t>((size_t)slots * n);
+    sd.state = c.take<unsigned char>((size_t)slots * (size_t)kc::state_bytes(g->n));
     sd.queue = c.take<int4>((size_t)slots * chains);
     sd.cstart = c.take<int32_t>((size_t)slots * chains);
     sd.chains = (int64_t)chains;
     sd.rec = c.take<int4>((size_t)slots * n);
-    sd.ord = c.take<int4>((size_t)slots * n);
-    sd.grp = c.take<int32_t>((size_t)slots * (n + 1));
+    sd.stride = g->n;
     sd.fen = fen ? c.take<int64_t>((size_t)slots * (size_t)(g->two_m + 2)) : nullptr;
     sd.fen_len = fen ? g->two_m + 2 : 0;
-    if (!sd.tagw || !sd.arrow || !sd.rq || !sd.queue || !sd.cstart || !sd.rec || !sd.ord || !sd.grp ||
-        (fen && !sd.fen))
+    if (!sd.state || !sd.queue || !sd.cstart || !sd.rec || (fen && !sd.fen))
         return fail(KC_ERR_DEVICE, "static workspace layout overflow (%d slots of %zu bytes)", slots, need(1));
     // the sweep's Fenwick trees must start at zero; an earlier call may have left anything
     if (fen) HIP_TRY(kc::launch_zero_i64(sd.fen, (int64_t)slots * sd.fen_len, stream));
