@@ -32,14 +32,22 @@ sys.path.insert(0, ROOT)
 METRIC = "spanning-tree samples/s and K at ε=0.01 vs exact; served query p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
 SECTOR = 64
-KERNEL_SRC = os.path.join(ROOT, "paper_2511_16356_amd", "csrc", "kc_device.hip")
+LIB_SRC = os.path.join(ROOT, "paper_2511_16356_amd", "csrc")
 
-# HBM bytes per launch of the persistent kernel, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs of this script, each scaled by what the counter reads for a
-# plain copy of known size (profiles/).  Keyed by the SHA-256 of the kernel
-# source the counters were taken on: another kernel source, or another
-# workload, reports traffic = null.
-MEASURED_TRAFFIC = {}
+# HBM bytes per launch of the sampling kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs of this script (each in a run of its own), scaled by what the
+# counter reads for a plain 1 GiB copy (FETCH_SIZE x 1.99993, WRITE_SIZE x 1;
+# profiles/hbm_traffic_*.md).  Keyed by the SHA-256 of the library sources the
+# counters were taken on (library_sha): other sources, or another workload,
+# sample count or seed, report traffic = null.
+MEASURED_TRAFFIC = {
+    "a08d42dab15486e1d2fa53e40f5506e2bbcefa52d8878a0f220070ac855779f6": [
+        {"workload": "dense", "samples": 4096, "seed": 0,
+         "fetch_bytes": 9.6546e12, "write_bytes": 4.5782e12, "bytes": 1.42328e13},
+        {"workload": "social", "samples": 8192, "seed": 0,
+         "fetch_bytes": 6.3707e12, "write_bytes": 3.0315e12, "bytes": 9.4022e12},
+    ],
+}
 
 
 # Measured ceilings of the device (bench.py --calibrate-random 128, libkc_probe.so;
@@ -53,12 +61,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(draws: int, n: int, depth0: int, samples: int) -> int:
-    """Random 64-byte sectors the method itself must touch: one per Wilson draw
-    (the drawn vertex's per-sample state), one per vertex for the retrace, and
-    n * min(depth0, ceil(log2 n)) for the per-tree path-mapping sums."""
+MALL_BYTES = 256 << 20  # the last-level cache (Infinity Cache) of one MI355X
+
+
+def algorithmic_bytes(draws: int, n: int, two_m: int, depth0: int, samples: int) -> int:
+    """Random 64-byte sectors the method itself must touch per launch: per
+    Wilson draw the drawn vertex's per-sample state, plus its CSR offset and
+    neighbour when the CSR does not fit the last-level cache (they are L2/MALL
+    hits when it does); per tree one sector per vertex to join it to the tree,
+    and n * min(depth0, ceil(log2 n)) for the path-mapping sums."""
+    csr_bytes = 8 * (n + 1) + 4 * two_m
+    per_draw = 3 if csr_bytes > MALL_BYTES else 1
     per_tree_trav = n * min(depth0, math.ceil(math.log2(max(2, n))))
-    return SECTOR * (draws + samples * (n + per_tree_trav))
+    return SECTOR * (per_draw * draws + samples * (n + per_tree_trav))
 
 
 def host_cpu():
@@ -338,10 +353,17 @@ def study_roots(points: int, samples: int, seed: int):
     return {"study": "root degree (section 5, Exp-III)", "seed": seed, "rows": rows}
 
 
-def kernel_sha() -> str:
+def library_sha() -> str:
+    """SHA-256 over the estimator library's sources (name, then contents, in
+    name order; the memory-ceiling probe is not part of it)."""
     import hashlib
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(LIB_SRC)):
+        if name.endswith((".hip", ".cpp", ".h")) and name != "kc_probe.hip":
+            h.update(name.encode())
+            with open(os.path.join(LIB_SRC, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
 
 
 def calibrate_copy(mib: int):
@@ -508,6 +530,17 @@ def main():
         G.reserve(B)
     torch.cuda.synchronize()
 
+    import threading
+    watch_stop = threading.Event()
+    if batch is None:
+        # a direct launch can run for minutes (road-like graphs): report the samples
+        # it has finished every 30 s, read from the counters the kernel publishes
+        def watch():
+            while not watch_stop.wait(30.0):
+                log("  %d of %d samples of the running launch done" % (G.progress(), B))
+
+        threading.Thread(target=watch, daemon=True).start()
+
     def step(k):
         if batch is None:
             return G.estimate(args.seed, k * B, B)
@@ -534,6 +567,7 @@ def main():
         log("step %d: kappa=%.1f +- %.1f draws/sample=%.0f" % (k, est.kappa, est.std_error, est.total_steps / B))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    watch_stop.set()
     launch_ms = [starts[k].elapsed_time(ends[k]) for k in range(args.steps)]
     if batch is not None:
         batch.close()
@@ -541,12 +575,15 @@ def main():
     total = B * args.steps
     pooled = G.combine(ests)
     draws = pooled.total_steps
-    alg = algorithmic_bytes(draws, g.n, info["depth0"], total)
+    alg = algorithmic_bytes(draws, g.n, g.two_m, info["depth0"], total)
     avg_launch_s = sum(launch_ms) / len(launch_ms) / 1e3
     achieved = alg / args.steps / avg_launch_s / 1e9  # GB/s: algorithmic bytes per launch over its duration
-    meas = MEASURED_TRAFFIC.get(kernel_sha())
+    meas = None
+    for m in MEASURED_TRAFFIC.get(library_sha(), []):
+        if (m["workload"], m["samples"], m["seed"]) == (args.workload, B, args.seed):
+            meas = m
     traffic = None  # HBM bytes per launch, when counters exist for this kernel and workload
-    if meas and (meas["workload"], meas["samples"], meas["seed"]) == (args.workload, B, args.seed):
+    if meas:
         traffic = meas["bytes"]
     value = total / wall
     out = {
@@ -588,6 +625,10 @@ def main():
             "frac_of_random_64B_ceiling": achieved / MEASURED_CEILINGS["random_64B_read_GBps"],
         },
     }
+    if traffic:
+        # the counted bytes against the algorithmic ones, and the HBM rate they imply
+        out["roofline"]["traffic_over_algorithmic"] = traffic / (alg / args.steps)
+        out["roofline"]["traffic_GBps"] = traffic / avg_launch_s / 1e9
     log("timed: %.1f samples/s, %.1f ms per launch, %.0f GB/s algorithmic" % (value, avg_launch_s * 1e3, achieved))
 
     def budget_left(need_s: float) -> bool:

@@ -217,9 +217,12 @@ def test_bench_exact_kemeny_closed_forms(gen):
 
 def test_bench_algorithmic_bytes():
     import bench
-    # one sector per draw, per vertex (retrace), and per path-mapping term
-    assert bench.algorithmic_bytes(draws=100, n=8, depth0=2, samples=3) == 64 * (100 + 3 * (8 + 8 * 2))
-    assert bench.algorithmic_bytes(draws=0, n=1024, depth0=60, samples=1) == 64 * (1024 + 1024 * 10)
+    # one sector per draw, per vertex (joining the tree), and per path-mapping term
+    assert bench.algorithmic_bytes(draws=100, n=8, two_m=20, depth0=2, samples=3) == 64 * (100 + 3 * (8 + 8 * 2))
+    assert bench.algorithmic_bytes(draws=0, n=1024, two_m=3968, depth0=60, samples=1) == 64 * (1024 + 1024 * 10)
+    # a CSR larger than the last-level cache adds its offset and neighbour sectors to every draw
+    n, two_m = 3_000_000, 227_000_000
+    assert bench.algorithmic_bytes(draws=100, n=n, two_m=two_m, depth0=3, samples=1) == 64 * (300 + n + 3 * n)
 
 
 def test_bench_refuses_more_than_one_gpu():
