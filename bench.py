@@ -46,6 +46,8 @@ MEASURED_TRAFFIC = {
          "fetch_bytes": 9.6546e12, "write_bytes": 4.5782e12, "bytes": 1.42328e13},
         {"workload": "social", "samples": 8192, "seed": 0,
          "fetch_bytes": 6.3707e12, "write_bytes": 3.0315e12, "bytes": 9.4022e12},
+        {"workload": "road", "samples": 4096, "seed": 0, "direct": True,
+         "fetch_bytes": 6.0750e13, "write_bytes": 7.2729e13, "bytes": 1.3348e14},
     ],
 }
 
@@ -256,26 +258,137 @@ def plain_leg(G, seed: int, count: int):
             "draws_per_sample": draws / count}
 
 
-def serve_sweep(seed: int, graphs: int, samples: int, n_req: int):
-    """Served latency against offered load under improved maintenance: first
-    the capacity (all requests at once, requests per second over the
-    makespan), then Poisson arrivals at 0.25, 0.5 and 0.8 of it; the same
-    graphs and requests every time."""
-    sat = serving_leg(seed, graphs, 10_000, 30_000, samples, 1.0, 0.0, maintenance=1, n_req=n_req,
-                      saturate=True)
-    cap = sat["throughput_req_per_s"]
-    levels = []
-    for frac in (0.25, 0.5, 0.8):
-        rate = frac * cap
-        leg = serving_leg(seed, graphs, 10_000, 30_000, samples, rate, n_req / rate, maintenance=1, n_req=n_req)
-        levels.append({"load": frac, "rate_req_per_s": rate, "query": leg["query"], "update": leg["update"],
-                       "throughput_req_per_s": leg["throughput_req_per_s"], "errors": leg["errors"]})
-        log("sweep: load %.2f (%.1f req/s): query p99 %.2f ms, update p99 %.1f ms" %
-            (frac, rate, leg["query"]["p99_ms"], leg["update"]["p99_ms"]))
-    return {"sweep": "served latency vs offered load, improved maintenance (Algorithm 3)",
-            "workload": sat["workload"].split(";")[0] + "; %d requests per level, same mix" % n_req,
-            "capacity_req_per_s": cap, "saturated": {"query": sat["query"], "update": sat["update"]},
-            "levels": levels}
+def plan_requests(cur: list, n_req: int, rate: float, rng, saturate: bool = False):
+    """n_req requests on the graphs `cur` (updated in place as the plan's
+    updates would change them): Poisson arrivals at `rate` per second (all at
+    once if `saturate`), 80% Kemeny queries and 20% update batches, half
+    deletions (sizes log-uniform in [1, 1000], batches that keep the graph
+    connected) and half insertions (sizes log-uniform in [1, 10]); edges drawn
+    with probability proportional to d(u) d(v)."""
+    import numpy as np
+    import graphgen
+    times = np.zeros(n_req) if saturate else np.cumsum(rng.exponential(1.0, size=n_req)) / rate
+    plan = []
+    for t in times:
+        gid = int(rng.integers(0, len(cur)))
+        if rng.random() < 0.2:
+            if rng.random() < 0.5:
+                size = int(round(math.exp(rng.uniform(0.0, math.log(1000.0)))))
+                batch = graphgen.deletion_batch(cur[gid], size, rng)
+                cur[gid] = graphgen.remove_edges(cur[gid], batch)
+                plan.append((float(t), gid, "update", batch, False))
+            else:
+                size = int(round(math.exp(rng.uniform(0.0, math.log(10.0)))))
+                batch = graphgen.insertion_batch(cur[gid], size, rng)
+                cur[gid] = graphgen.add_edges(cur[gid], batch)
+                plan.append((float(t), gid, "update", batch, True))
+        else:
+            plan.append((float(t), gid, "query", [], False))
+    return plan
+
+
+def run_plan(srv, plan, label: str):
+    """Submit the planned requests at their arrival times and wait for all of
+    them; latency is arrival to completion."""
+    from paper_2511_16356_amd.serve import Request, latency_stats
+    reqs = []
+    t0 = time.perf_counter()
+    for t, gid, kind, batch, ins in plan:
+        while True:
+            now = time.perf_counter() - t0
+            if t <= now:
+                break
+            time.sleep(min(t - now, 20.0))
+            if t > time.perf_counter() - t0:
+                log("serving %s: %d of %d requests submitted, %d served" %
+                    (label, len(reqs), len(plan), sum(1 for r in reqs if r.t_done > 0.0)))
+        r = Request(gid, kind, batch, insert=ins)
+        reqs.append(r)
+        srv.submit(r)
+    while True:
+        done = sum(1 for r in reqs if r.t_done > 0.0)
+        if done == len(reqs):
+            break
+        log("serving %s: %d of %d requests served" % (label, done, len(reqs)))
+        srv.drain(timeout=20.0)
+    makespan = time.perf_counter() - t0
+    return {"requests": len(reqs), "errors": sum(1 for r in reqs if r.error), "makespan_s": makespan,
+            "throughput_req_per_s": len(reqs) / makespan,
+            "query": latency_stats(reqs, "query"), "update": latency_stats(reqs, "update"),
+            "trees_changed": int(sum(r.result for r in reqs if r.kind == "update" and not r.error))}
+
+
+def serve_sweep(seed: int, graphs: int, lo: int, hi: int, samples: int, n_req: int,
+                workspace_share: int, init_share: int, deadline_s: float = 0.0):
+    """Served latency against offered load under improved maintenance, on one
+    set of resident graphs: the graphs are admitted by footprint (their trees
+    drawn concurrently), then the capacity is measured (n_req requests all at
+    once: requests per second over the makespan), then Poisson arrivals at
+    0.25, 0.5 and 0.8 of it, and at 0.5 the plain form (one request at a time)
+    on the same graphs.  Every run draws fresh requests from the same mix on the
+    graphs as the earlier runs left them."""
+    import numpy as np
+    import torch
+    import graphgen
+    from paper_2511_16356_amd.serve import Server
+    t0 = time.perf_counter()
+    gs = graphgen.serving_graphs(graphs, lo, hi, seed)
+    sizes = sorted(g.n for g in gs)
+    log("serving sweep: %d graphs generated, n from %d to %d, sum %d (%.1f s)" %
+        (graphs, sizes[0], sizes[-1], sum(sizes), time.perf_counter() - t0))
+    free = torch.cuda.mem_get_info()[0]
+    budget = int(0.85 * free)
+    srv = Server(budget_bytes=budget, workspace_share=workspace_share, maintenance=1, init_share=init_share)
+    try:
+        t0 = time.perf_counter()
+        # largest first, so that the longest initial draws start first
+        order = sorted(range(graphs), key=lambda i: -gs[i].n)
+        def added(gid, secs, err):
+            log("serving sweep: graph %d (n=%d) %s in %.1f s" % (gid, gs[gid].n, "refused" if err else "resident", secs))
+
+        errors = srv.add_graphs([(gid, gs[gid], seed + gid, samples) for gid in order], workers=8, on_added=added)
+        t_init = time.perf_counter() - t0
+        resident = sum(srv.held.values())
+        log("serving sweep: %d graphs resident with %d trees each (%.1f s), %.1f GB held of a %.1f GB budget; "
+            "refused: %s" % (len(srv.graphs), samples, t_init, resident / 1e9, budget / 1e9, errors or "none"))
+        cur = [gs[i] for i in range(graphs)]
+        rng = np.random.default_rng(seed + 1)
+        sat = run_plan(srv, plan_requests(cur, n_req, 1.0, rng, saturate=True), "saturated")
+        cap = sat["throughput_req_per_s"]
+        log("serving sweep: capacity %.2f requests/s" % cap)
+        levels = []
+
+        def time_left(frac):
+            # a run at `frac` of the capacity takes about n_req / (frac * cap) seconds
+            return not deadline_s or time.perf_counter() - T_START + 1.2 * n_req / (frac * cap) < deadline_s
+
+        for frac in (0.25, 0.5, 0.8):
+            if not time_left(frac):
+                levels.append({"load": frac, "skipped": "deadline of %.0f s" % deadline_s})
+                continue
+            leg = run_plan(srv, plan_requests(cur, n_req, frac * cap, rng), "load %.2f" % frac)
+            leg.update({"load": frac, "rate_req_per_s": frac * cap})
+            levels.append(leg)
+            q, u = leg["query"] or {}, leg["update"] or {}
+            log("serving sweep: load %.2f (%.3f req/s): query p50 %s p99 %s ms, update p50 %s p99 %s ms" %
+                (frac, frac * cap, q.get("p50_ms"), q.get("p99_ms"), u.get("p50_ms"), u.get("p99_ms")))
+        if time_left(0.5):
+            srv.set_schedule(True)
+            plain = run_plan(srv, plan_requests(cur, n_req, 0.5 * cap, rng), "plain form, load 0.50")
+            plain.update({"load": 0.5, "rate_req_per_s": 0.5 * cap, "scheduling": "one request at a time"})
+            srv.set_schedule(False)
+        else:
+            plain = {"skipped": "deadline of %.0f s" % deadline_s}
+        return {"sweep": "served latency vs offered load, improved maintenance (Algorithm 3)",
+                "workload": "%d resident graphs (cycle of grid, road-like, Chung-Lu types), %d-%d vertices "
+                            "log-uniform (sum %d), %d trees each; 80%% queries / 20%% update batches: half "
+                            "deletions (1-1000 edges), half insertions (1-10 edges), edges with prob. ~ d(u)d(v); "
+                            "%d requests per run" % (graphs, lo, hi, sum(sizes), samples, n_req),
+                "admission": {"budget_bytes": budget, "resident_bytes": resident, "workspace_share": workspace_share,
+                              "init_share": init_share, "refused": errors, "init_s": t_init},
+                "capacity_req_per_s": cap, "saturated": sat, "levels": levels, "plain_at_0.5": plain}
+    finally:
+        srv.close()
 
 
 def study_graphs(points: int):
@@ -433,7 +546,11 @@ WORKLOADS = {
 DEFAULT_SAMPLES = {"dense": 4096, "road": 4096, "social": 8192}
 
 
+T_START = time.perf_counter()  # reset when main() starts; the wall-clock budgets count from it
+
+
 def main():
+    global T_START
     T_START = time.perf_counter()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -457,6 +574,14 @@ def main():
     ap.add_argument("--serve-graphs", type=int, default=8)
     ap.add_argument("--serve-rate", type=float, default=5.0, help="requests per second")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-lo", type=int, default=10_000, help="--serve-sweep: smallest graph (vertices)")
+    ap.add_argument("--serve-hi", type=int, default=2_000_000, help="--serve-sweep: largest graph (vertices)")
+    ap.add_argument("--serve-samples", type=int, default=1024, help="--serve-sweep: resident trees per graph")
+    ap.add_argument("--serve-requests", type=int, default=60, help="--serve-sweep: requests per run")
+    ap.add_argument("--serve-workspace", type=int, default=1024, metavar="MIB",
+                    help="--serve-sweep: workspace one graph keeps")
+    ap.add_argument("--serve-init-workspace", type=int, default=16384, metavar="MIB",
+                    help="--serve-sweep: workspace one graph may use while its trees are first drawn")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the exact-K leg on the 32x32 grid")
     ap.add_argument("--plain-samples", type=int, default=2,
                     help="sample ids run one launch each on the benchmark graph (plain form)")
@@ -485,7 +610,9 @@ def main():
     if args.serve_sweep:
         import torch
         torch.cuda.set_device(0)
-        print(json.dumps(serve_sweep(args.seed + 7, args.serve_graphs, 1024, 60)), flush=True)
+        print(json.dumps(serve_sweep(args.seed + 7, args.serve_graphs, args.serve_lo, args.serve_hi,
+                                     args.serve_samples, args.serve_requests, args.serve_workspace << 20,
+                                     args.serve_init_workspace << 20, args.budget)), flush=True)
         return
     if args.study:
         import torch
@@ -580,7 +707,8 @@ def main():
     achieved = alg / args.steps / avg_launch_s / 1e9  # GB/s: algorithmic bytes per launch over its duration
     meas = None
     for m in MEASURED_TRAFFIC.get(library_sha(), []):
-        if (m["workload"], m["samples"], m["seed"]) == (args.workload, B, args.seed):
+        if (m["workload"], m["samples"], m["seed"], m.get("direct", False)) == \
+                (args.workload, B, args.seed, bool(args.direct)):
             meas = m
     traffic = None  # HBM bytes per launch, when counters exist for this kernel and workload
     if meas:

@@ -53,11 +53,19 @@ hipError_t dev_alloc(T **p, size_t count) {
 template <typename T>
 struct DevTmp {
     T *p = nullptr;
+    hipStream_t s = nullptr;
     DevTmp() = default;
     DevTmp(const DevTmp &) = delete;
     DevTmp &operator=(const DevTmp &) = delete;
-    ~DevTmp() { dev_free(p); }
-    hipError_t alloc(size_t count) { return dev_alloc(&p, count); }
+    ~DevTmp() {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+    // stream-ordered: neither the allocation nor the free waits for work on other
+    // streams (a plain hipFree synchronises the whole device)
+    hipError_t alloc(size_t count, hipStream_t stream) {
+        s = stream;
+        return hipMallocAsync(reinterpret_cast<void **>(&p), std::max<size_t>(count, 1) * sizeof(T), stream);
+    }
 };
 
 // Runs body(lo, hi) over [0, n) in contiguous chunks on up to 16 host threads
@@ -1114,9 +1122,9 @@ static std::vector<uint8_t> trees_with_edges(kc_graph *g, const std::vector<int3
     *st = KC_OK;
     DevTmp<int32_t> d_eu, d_ev;
     DevTmp<uint8_t> d_flags;
-    hipError_t e = d_eu.alloc(eu.size());
-    if (e == hipSuccess) e = d_ev.alloc(ev.size());
-    if (e == hipSuccess) e = d_flags.alloc((size_t)g->res_count);
+    hipError_t e = d_eu.alloc(eu.size(), stream);
+    if (e == hipSuccess) e = d_ev.alloc(ev.size(), stream);
+    if (e == hipSuccess) e = d_flags.alloc((size_t)g->res_count, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_eu.p, eu.data(), eu.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
@@ -1141,7 +1149,7 @@ struct RowBackup {
     kc_status save(kc_graph *g, const std::vector<int32_t> &r, hipStream_t stream) {
         rows = r;
         if (rows.empty()) return KC_OK;
-        HIP_TRY(buf.alloc(rows.size() * (size_t)g->n));
+        HIP_TRY(buf.alloc(rows.size() * (size_t)g->n, stream));
         for (size_t i = 0; i < rows.size(); ++i)
             HIP_TRY(hipMemcpyAsync(buf.p + i * (size_t)g->n, g->d_res_par + (size_t)rows[i] * (size_t)g->n,
                                    (size_t)g->n * sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
@@ -1231,7 +1239,7 @@ static kc_status apply_deletions(kc_graph *g, const int32_t *u, const int32_t *v
         const int32_t k = (int32_t)redo.size();
         if (k > 0) {
             DevTmp<int32_t> tmp;
-            hipError_t e = tmp.alloc((size_t)k * (size_t)n);
+            hipError_t e = tmp.alloc((size_t)k * (size_t)n, stream);
             if (e != hipSuccess) return sw.undo(fail(KC_ERR_NOMEM, "allocation failed: %s", hipGetErrorString(e)), stream);
             st = kc_sample_trees(g, g->res_seed, g->res_next, k, tmp.p, nullptr, nullptr, (void *)stream);
             if (st != KC_OK) return sw.undo(st, stream);
@@ -1295,8 +1303,8 @@ static kc_status path_currents(kc_graph *g, int32_t a, int32_t b, std::vector<in
     if (path.size() < 2) return fail(KC_ERR_DEVICE, "no path between %d and %d", a, b);
     DevTmp<int32_t> d_path;
     DevTmp<int64_t> d_c;
-    HIP_TRY(d_path.alloc(path.size()));
-    HIP_TRY(d_c.alloc((size_t)g->res_count));
+    HIP_TRY(d_path.alloc(path.size(), stream));
+    HIP_TRY(d_c.alloc((size_t)g->res_count, stream));
     HIP_TRY(hipMemcpyAsync(d_path.p, path.data(), path.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
     kc::RunParams rp{};
     rp.count = g->res_count;
@@ -1352,7 +1360,7 @@ static kc_status apply_insertion(kc_graph *g, int32_t a, int32_t b, int32_t *res
         if (k > 0) {
             // uniform spanning trees of G' through (a, b): a and b start in the tree
             DevTmp<int32_t> tmp;
-            hipError_t e = tmp.alloc((size_t)k * (size_t)n);
+            hipError_t e = tmp.alloc((size_t)k * (size_t)n, stream);
             if (e != hipSuccess) return sw.undo(fail(KC_ERR_NOMEM, "allocation failed: %s", hipGetErrorString(e)), stream);
             kc::RunParams rp{};
             rp.seed = g->res_seed;
@@ -1392,8 +1400,8 @@ static kc_status ism_link_cut(kc_graph *g, const std::vector<int32_t> &rows, int
     if (k == 0) return KC_OK;
     DevTmp<int32_t> d_rows;
     DevTmp<int64_t> d_d;
-    HIP_TRY(d_rows.alloc((size_t)k));
-    HIP_TRY(d_d.alloc((size_t)k));
+    HIP_TRY(d_rows.alloc((size_t)k, stream));
+    HIP_TRY(d_d.alloc((size_t)k, stream));
     HIP_TRY(hipMemcpyAsync(d_rows.p, rows.data(), (size_t)k * sizeof(int32_t), hipMemcpyHostToDevice, stream));
     HIP_TRY(kc::launch_reset_ctl(g->d_ctl, stream));
     HIP_TRY(kc::launch_link_cut(g->d_res_par, d_rows.p, k, g->n, a, b, g->res_seed, (uint32_t)g->res_serial, relink,
@@ -1413,8 +1421,8 @@ static kc_status ism_cross(kc_graph *g, const std::vector<int32_t> &rows, int32_
     if (k == 0) return KC_OK;
     DevTmp<int32_t> d_rows;
     DevTmp<int64_t> d_d;
-    HIP_TRY(d_rows.alloc((size_t)k));
-    HIP_TRY(d_d.alloc((size_t)k));
+    HIP_TRY(d_rows.alloc((size_t)k, stream));
+    HIP_TRY(d_d.alloc((size_t)k, stream));
     HIP_TRY(hipMemcpyAsync(d_rows.p, rows.data(), (size_t)k * sizeof(int32_t), hipMemcpyHostToDevice, stream));
     kc::RunParams rp{};
     rp.count = k;

@@ -12,7 +12,8 @@ on different graphs run on the device at the same time and a request is
 started as soon as its graph is free and the HBM it may need is available.
 Requests on one graph run in arrival order, so every graph's results are the
 same alone and in any mix.  For comparison, ``one_at_a_time`` serves every
-request in one worker, one after another (the plain form).
+request in one worker, one after another (the plain form); ``set_schedule``
+switches between the two on the same resident graphs.
 
 Admission is by HBM footprint, against one device budget:
   - a resident graph holds, for as long as it is resident, its graph arrays
@@ -63,9 +64,11 @@ class _Budget:
         self.free = total
         self.cv = threading.Condition()
 
-    def acquire(self, nbytes: int, timeout: float = None) -> bool:
-        """Take nbytes once they are free (False after `timeout` seconds, or at
-        once if nbytes exceeds the whole budget)."""
+    def acquire(self, nbytes: int, timeout: float = None, hopeless=None, taken=None) -> bool:
+        """Take nbytes once they are free (False after `timeout` seconds, at
+        once if nbytes exceeds the whole budget, or as soon as hopeless()
+        says that nothing held now will be released); taken() runs under the
+        same lock once the bytes are taken."""
         if nbytes > self.total:
             return False
         end = None if timeout is None else time.perf_counter() + timeout
@@ -74,8 +77,12 @@ class _Budget:
                 left = None if end is None else end - time.perf_counter()
                 if left is not None and left <= 0:
                     return False
-                self.cv.wait(left)
+                if hopeless is not None and hopeless():
+                    return False
+                self.cv.wait(left if hopeless is None else min(1.0, left) if left is not None else 1.0)
             self.free -= nbytes
+            if taken is not None:
+                taken()
         return True
 
     def release(self, nbytes: int):
@@ -101,12 +108,15 @@ class Server:
     """Resident graphs and their request workers."""
 
     def __init__(self, budget_bytes: int, workspace_share: int, maintenance: int = KC_MAINT_BASIC,
-                 one_at_a_time: bool = False):
+                 one_at_a_time: bool = False, init_share: int = 0):
         """budget_bytes: device bytes the server may hold in all; workspace_share:
         the most workspace one graph's estimates and updates may keep
-        (KC_OPT_MEM_BUDGET); one_at_a_time: the plain form for comparison, one
-        worker for all graphs, so requests run strictly one after another."""
+        (KC_OPT_MEM_BUDGET); init_share: the workspace a graph may use while its
+        resident trees are first drawn (freed afterwards; 0: workspace_share);
+        one_at_a_time: the plain form for comparison, one worker for all graphs,
+        so requests run strictly one after another."""
         self.one_at_a_time = one_at_a_time
+        self.init_share = init_share
         self.budget = _Budget(budget_bytes)
         self.workspace_share = workspace_share
         self.maintenance = maintenance     # KC_MAINT_BASIC (Algorithm 2) or KC_MAINT_IMPROVED (Algorithm 3)
@@ -119,40 +129,88 @@ class Server:
         self.done = []
         self.done_cv = threading.Condition()
         self.submitted = 0
+        self.solo_q = queue.Queue()    # the one queue of the plain form
+        self.solo_t = None
+        self.drawing = 0               # graphs drawing their resident trees now
 
-    def add_graph(self, gid: int, g, seed: int, samples: int, timeout: float = None):
+    def add_graph(self, gid: int, g, seed: int, samples: int, timeout: float = None, hopeless=None):
         """Make g resident with `samples` trees once its footprint fits the
-        budget (KcError KC_ERR_NOMEM if it never can, or not within `timeout`)."""
+        budget (KcError KC_ERR_NOMEM if it never can, not within `timeout`, or
+        once hopeless() is true while it waits)."""
         import torch
         stream = torch.cuda.Stream()
         G = Graph.from_graph(g, stream=stream)
         info = G.info
         workspace = min(self.workspace_share, samples * int(info["sample_bytes"]))
+        init_ws = max(workspace, min(self.init_share, samples * int(info["sample_bytes"])))
         need = resident_bytes(info, samples, workspace)
-        if not self.budget.acquire(need, timeout):
+        need_init = resident_bytes(info, samples, init_ws)
+
+        def drawing_starts():
+            self.drawing += 1
+
+        if not self.budget.acquire(need_init, timeout, hopeless, taken=drawing_starts):
             G.close()
             raise KcError(3, "graph %s needs %d device bytes resident; %d of %d are free" %
-                          (gid, need, self.budget.free, self.budget.total))
+                          (gid, need_init, self.budget.free, self.budget.total))
         try:
-            G.set_option(KC_OPT_MEM_BUDGET, workspace)
+            G.set_option(KC_OPT_MEM_BUDGET, init_ws)
             G.set_option(KC_OPT_MAINTENANCE, self.maintenance)
             G.samples_init(seed, samples, stream=stream)
+            if init_ws > workspace:
+                # keep only the steady-state workspace: the rest returns to the budget
+                G.trim(stream)
+                G.set_option(KC_OPT_MEM_BUDGET, workspace)
         except Exception:
             G.close()
-            self.budget.release(need)
+            with self.budget.cv:
+                self.drawing -= 1
+            self.budget.release(need_init)
             raise
-        self.graphs[gid] = G
-        self.held[gid] = need
-        self.tmp[gid] = update_bytes(info, samples)
-        self.streams[gid] = stream
-        if self.one_at_a_time and self.threads:
-            self.queues[gid] = next(iter(self.queues.values()))
-            return
-        q = queue.Queue()
-        self.queues[gid] = q
-        t = threading.Thread(target=self._worker, args=(q,), daemon=True)
-        self.threads[gid] = t
+        with self.budget.cv:
+            self.drawing -= 1
+        self.budget.release(need_init - need)
+        with self.done_cv:
+            self.graphs[gid] = G
+            self.held[gid] = need
+            self.tmp[gid] = update_bytes(info, samples)
+            self.streams[gid] = stream
+            q = queue.Queue()
+            self.queues[gid] = q
+            t = threading.Thread(target=self._worker, args=(q,), daemon=True)
+            self.threads[gid] = t
         t.start()
+
+    def add_graphs(self, items, workers: int = 8, on_added=None):
+        """add_graph for many (gid, g, seed, samples) at once, `workers` at a
+        time: their resident trees are drawn concurrently, each on its own
+        stream.  on_added(gid, seconds, error) is called as each one ends.
+        Returns {gid: error message} for the graphs refused."""
+        from concurrent.futures import ThreadPoolExecutor
+        errors = {}
+
+        def one(item):
+            gid, g, seed, samples = item
+            t0 = time.perf_counter()
+            err = None
+            try:
+                # a graph waits for memory only while another one is drawing its trees
+                # (which then returns its extra workspace)
+                self.add_graph(gid, g, seed=seed, samples=samples, hopeless=lambda: self.drawing == 0)
+            except KcError as exc:
+                err = errors[gid] = str(exc)
+            if on_added:
+                on_added(gid, time.perf_counter() - t0, err)
+
+        with ThreadPoolExecutor(max_workers=max(1, workers)) as pool:
+            list(pool.map(one, items))
+        return errors
+
+    def set_schedule(self, one_at_a_time: bool):
+        """Switch between per-graph workers (continuous batching) and the plain
+        form; requests already submitted finish under the old schedule first."""
+        self.drain()
+        self.one_at_a_time = one_at_a_time
 
     def remove_graph(self, gid: int):
         """Free a resident graph once its queued requests are done; its bytes
@@ -167,7 +225,13 @@ class Server:
         with self.done_cv:
             self.submitted += 1
         req.t_arrive = time.perf_counter()
-        self.queues[req.gid].put(req)
+        if self.one_at_a_time:
+            if self.solo_t is None:
+                self.solo_t = threading.Thread(target=self._worker, args=(self.solo_q,), daemon=True)
+                self.solo_t.start()
+            self.solo_q.put(req)
+        else:
+            self.queues[req.gid].put(req)
 
     def _worker(self, q):
         while True:
@@ -213,9 +277,9 @@ class Server:
             return len(self.done)
 
     def close(self):
-        for q in {id(q): q for q in self.queues.values()}.values():
+        for q in list(self.queues.values()) + [self.solo_q]:
             q.put(None)
-        for t in self.threads.values():
+        for t in list(self.threads.values()) + ([self.solo_t] if self.solo_t else []):
             t.join()
         for gid, G in self.graphs.items():
             G.close()

@@ -12,6 +12,11 @@ class _FakeStream:
     cuda_stream = 0
 
 
+def _opt_mem_budget():
+    from paper_2511_16356_amd import KC_OPT_MEM_BUDGET
+    return KC_OPT_MEM_BUDGET
+
+
 class _FakeGraph:
     """Records (gid, kind, start, end) of every call; updates take longer."""
     log = []
@@ -36,6 +41,10 @@ class _FakeGraph:
 
     def samples_init(self, seed, count, stream=None):
         self.inits += 1
+        self.init_budget = self.options.get(_opt_mem_budget())
+
+    def trim(self, stream=None):
+        self.trimmed = True
 
     def _run(self, kind, seconds):
         with _FakeGraph.lock:
@@ -133,12 +142,63 @@ def test_one_at_a_time_runs_in_arrival_order(serve):
     try:
         for gid in range(3):
             srv.add_graph(gid, gid, seed=gid, samples=8)
-        assert len(srv.threads) == 1
         plan = [(k % 3, "update" if k % 3 == 0 else "query") for k in range(12)]
         reqs = _submit_all(srv, serve, plan)
+        assert srv.solo_t is not None
         assert _FakeGraph.max_running == 1
         for a, b in zip(reqs, reqs[1:]):
             assert a.t_done <= b.t_start + 1e-6
+    finally:
+        srv.close()
+
+
+def test_schedule_switches_on_the_same_graphs(serve):
+    """The plain form and continuous batching on the same resident graphs:
+    one request at a time, then requests on different graphs overlapping."""
+    srv = serve.Server(budget_bytes=1 << 30, workspace_share=1 << 20)
+    try:
+        errors = srv.add_graphs([(gid, gid, gid, 8) for gid in range(4)], workers=4)
+        assert errors == {} and sorted(srv.graphs) == [0, 1, 2, 3]
+        srv.set_schedule(True)
+        _submit_all(srv, serve, [(gid, "update") for gid in range(4)])
+        assert _FakeGraph.max_running == 1
+        srv.set_schedule(False)
+        for gid in range(4):
+            srv.submit(serve.Request(gid, "update", [(1, 2)]))
+        assert srv.drain(timeout=30.0) == 8
+        assert _FakeGraph.max_running > 1
+    finally:
+        srv.close()
+
+
+def test_concurrent_admission_refuses_what_cannot_fit(serve):
+    """Graphs admitted together wait for memory only while another graph is
+    drawing its trees: one that cannot fit beside the resident ones is refused
+    as soon as nothing is left to free, instead of waiting forever."""
+    one = _resident(serve)
+    srv = serve.Server(budget_bytes=int(2.5 * one), workspace_share=1 << 20)
+    try:
+        t0 = time.perf_counter()
+        errors = srv.add_graphs([(gid, gid, gid, 8) for gid in range(3)], workers=3)
+        assert time.perf_counter() - t0 < 10.0
+        assert len(srv.graphs) == 2 and len(errors) == 1
+        assert all("KC_ERR_NOMEM" in e or "needs" in e for e in errors.values())
+        assert srv.budget.free == srv.budget.total - 2 * one
+    finally:
+        srv.close()
+
+
+def test_init_share_is_returned_after_the_trees_are_drawn(serve):
+    """A graph may draw its resident trees with a larger workspace than it
+    keeps: the difference is charged while the trees are drawn, then trimmed
+    and returned to the budget."""
+    srv = serve.Server(budget_bytes=1 << 30, workspace_share=300, init_share=1 << 20)
+    try:
+        srv.add_graph(0, 0, seed=0, samples=8)
+        G = srv.graphs[0]
+        assert G.init_budget == 8 * 100 and getattr(G, "trimmed", False)
+        assert G.options[serve.KC_OPT_MEM_BUDGET] == 300
+        assert srv.budget.free == srv.budget.total - _resident(serve, share=300)
     finally:
         srv.close()
 
