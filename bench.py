@@ -565,6 +565,8 @@ def main():
     ap.add_argument("--tune-cache", default="", help="kc_autotune cache file (default: in the temp directory)")
     ap.add_argument("--direct", action="store_true",
                     help="time kc_estimate calls instead of replays of the captured launch")
+    ap.add_argument("--chains", type=int, default=0, choices=[0, 1024, 2048],
+                    help="chain-table size per sample (KC_OPT_CHAINS; 0: the library's default)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--budget", type=float, default=480.0,
                     help="wall-clock seconds after which the optional legs are skipped")
@@ -638,6 +640,8 @@ def main():
     # set-up (not a step): the launch over B samples, captured once as a HIP graph
     # (kc_batch) with its workspace; launch L estimates samples L*B .. (L+1)*B - 1,
     # so the warm-up launches take the first ids and the timed ones the next
+    if args.chains:
+        G.set_option(kc.KC_OPT_CHAINS, args.chains)
     tuned = None
     if args.autotune == "on" or (args.autotune == "auto" and args.workload == "social"):
         # set-up: choose the launch options for batches of B samples (trial estimates
@@ -733,6 +737,7 @@ def main():
                         (B, "" if args.direct else ", replayed from a captured HIP graph", args.seed),
             "samples_per_step": B,
             "parallelism": "1 GPU, one wavefront per sample in flight",
+            "chains_per_sample": tuned["chains"] if tuned else (args.chains or 1024),
         },
         "kappa": pooled.kappa,
         "kappa_std_error": pooled.std_error,
