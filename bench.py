@@ -737,7 +737,7 @@ def main():
                         (B, "" if args.direct else ", replayed from a captured HIP graph", args.seed),
             "samples_per_step": B,
             "parallelism": "1 GPU, one wavefront per sample in flight",
-            "chains_per_sample": tuned["chains"] if tuned else (args.chains or 1024),
+            "chains_per_sample": G.info["chains"],
         },
         "kappa": pooled.kappa,
         "kappa_std_error": pooled.std_error,

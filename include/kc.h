@@ -65,6 +65,7 @@ typedef struct {
     int32_t tau0;       /* KC_TAU0_* rule tau0 is built with */
     int64_t sample_bytes; /* device workspace one sample in flight needs in kc_estimate under the
                              current traversal (sampler state, tree numbering, sweep Fenwick tree) */
+    int32_t chains;     /* walks one sample may hold open at once (KC_OPT_CHAINS) */
 } kc_graph_info;
 
 /* How tau0, the fixed spanning tree whose root paths define the path mapping,
@@ -96,9 +97,10 @@ enum {
     KC_OPT_START_ORDER = 6, /* order in which walks are started (results do not depend on it):
                               0 = BFS order from the root, 1 = reverse BFS order,
                               2 = a fixed pseudo-random permutation (default) */
-    KC_OPT_CHAINS = 7,     /* walks one sample may hold open at once: 1024 (default) or 2048.
-                              More finish one sample in fewer rounds; fewer let more samples
-                              run at once.  Results do not depend on it. */
+    KC_OPT_CHAINS = 7,     /* walks one sample may hold open at once: 1024 or 2048 (default:
+                              2048 for graphs of at least 100,000 vertices and mean degree
+                              below 4, else 1024).  More finish one sample in fewer rounds;
+                              fewer let more samples run at once.  Results do not depend on it. */
     KC_OPT_MAINTENANCE = 8 /* KC_MAINT_*: how kc_apply_updates maintains the resident set;
                               may change while the set's weights are all equal (always under
                               basic maintenance), else KC_ERR_INVALID */

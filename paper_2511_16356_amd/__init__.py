@@ -49,7 +49,7 @@ class _Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("two_m", ctypes.c_int64), ("root", ctypes.c_int32),
                 ("depth0", ctypes.c_int32), ("max_degree", ctypes.c_int32),
                 ("traversal", ctypes.c_int32), ("device_bytes", ctypes.c_int64), ("tau0", ctypes.c_int32),
-                ("sample_bytes", ctypes.c_int64)]
+                ("sample_bytes", ctypes.c_int64), ("chains", ctypes.c_int32)]
 
 
 class _Tune(ctypes.Structure):

@@ -684,17 +684,15 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
 
 // The numbered tree: one 16-byte record per vertex, two 8-byte words, so that
 // every step of the numbering touches one line per vertex it visits:
-//   rec[2v]     pending children << 44 | volume while the volumes are summed;
-//               from the vertex's own top-down step on, the next free tin of its
-//               interval (tin + deg, plus the volumes of the children placed so
-//               far); tin(v) + vol(v) once the numbering is done
+//   rec[2v]     pending children << 44 | volume while the volumes are summed
+//               (starting at deg(v)); tin(v) + vol(v) once the numbering is done
 //   rec[2v + 1] parent (low half, -1 at the root) | deg(v) (high half) until the
 //               top-down step, then parent | tin(v)
 struct SlotPtrs {
     SamplerWS ws;
     uint64_t *rec;
-    int4 *ord;             // finished vertices {v, parent, vol, deg} in completion order; the
-                           // leaves {v, parent, deg, deg} wait at the end of the same array
+    int4 *ord;             // finished vertices {v, parent, vol, offset in the parent's interval} in
+                           // completion order; the leaves {v, parent, deg, 0} wait at its end
     int32_t *grp;
     int64_t *fen;
 };
@@ -789,11 +787,12 @@ __device__ __forceinline__ int64_t items_at(const Items &it, uint32_t t) {
 //
 // Bottom-up: each lane carries up to NB finished vertices; a carrier pushes
 // its vertex's volume into the parent's word with one atomic, and the last
-// child to arrive carries the parent on in the next round.  Every round's
-// finished vertices form a completion group.  Top-down: the groups in
+// child to arrive carries the parent on in the next round.  The volume part
+// the atomic returns is the parent's degree plus the volumes of the siblings
+// that arrived before: the vertex's offset in its parent's interval.  Every
+// round's finished vertices form a completion group.  Top-down: the groups in
 // reverse order (a parent always finishes in a later group than its
-// children); a vertex's interval starts after its parent's own degree and
-// the intervals of the siblings that reserved before it.
+// children); a vertex's tin is its parent's tin plus its offset.
 __device__ bool tree_numbering(const GraphDev &g, const SlotPtrs &sp) {
     const int lane = threadIdx.x;
     const int n = g.n;
@@ -810,7 +809,7 @@ __device__ bool tree_numbering(const GraphDev &g, const SlotPtrs &sp) {
             if (p[k] >= 0) afetch_add(&sp.rec[2 * (size_t)p[k]], PEND_ONE);
     }
     fence_wg();
-    // leaves {v, parent, deg, deg}: leaf number j at ord[n - 1 - j]
+    // leaves {v, parent, deg, 0}: leaf number j at ord[n - 1 - j]
     int L = 0;
     for (int b = 0; b < n; b += WAVE * NBS) {
         uint64_t w[NBS], h[NBS];
@@ -826,7 +825,7 @@ __device__ bool tree_numbering(const GraphDev &g, const SlotPtrs &sp) {
             const uint64_t m = __ballot(leaf);
             if (leaf)
                 sp.ord[n - 1 - (L + rank_in(m))] = make_int4(b + k * WAVE + lane, (int32_t)(uint32_t)h[k],
-                                                             (int)(w[k] & VOL_MASK), (int)(h[k] >> 32));
+                                                             (int)(w[k] & VOL_MASK), 0);
             L += __popcll(m);
         }
     }
@@ -834,10 +833,10 @@ __device__ bool tree_numbering(const GraphDev &g, const SlotPtrs &sp) {
     // bottom-up.  Leaves are taken from the low end of their block, ord[n-L ..]:
     // the finished entries written at ord[0 .. nord) never reach an untaken leaf,
     // since nord + (leaves not yet taken) <= n.
-    int cv[NB], cp[NB], cdeg[NB];
+    int cv[NB], cp[NB];
     uint64_t cval[NB];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) { cv[k] = -1; cp[k] = -1; cdeg[k] = 0; cval[k] = 0; }
+    for (int k = 0; k < NB; ++k) { cv[k] = -1; cp[k] = -1; cval[k] = 0; }
     int li = 0, nord = 0, ngrp = 0;
     while (true) {
         if (li < L) {
@@ -850,7 +849,6 @@ __device__ bool tree_numbering(const GraphDev &g, const SlotPtrs &sp) {
                     cv[k] = e.x;
                     cp[k] = e.y;
                     cval[k] = (uint64_t)(uint32_t)e.z;
-                    cdeg[k] = e.w;
                 }
                 li = min(L, li + (int)__popcll(freem));
             }
@@ -864,11 +862,15 @@ __device__ bool tree_numbering(const GraphDev &g, const SlotPtrs &sp) {
         uint64_t old[NB];
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
-            const uint64_t bm = __ballot(cv[k] >= 0);
-            if (cv[k] >= 0) sp.ord[nord + rank_in(bm)] = make_int4(cv[k], cp[k], (int)cval[k], cdeg[k]);
-            nord += __popcll(bm);
             old[k] = 0;
             if (cv[k] >= 0 && cp[k] >= 0) old[k] = afetch_add(&sp.rec[2 * (size_t)cp[k]], cval[k] - PEND_ONE);
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const uint64_t bm = __ballot(cv[k] >= 0);
+            if (cv[k] >= 0)
+                sp.ord[nord + rank_in(bm)] = make_int4(cv[k], cp[k], (int)cval[k], (int)(uint32_t)(old[k] & VOL_MASK));
+            nord += __popcll(bm);
         }
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
@@ -876,15 +878,10 @@ __device__ bool tree_numbering(const GraphDev &g, const SlotPtrs &sp) {
             cv[k] = last ? cp[k] : -1;
             if (last) cval[k] = (old[k] & VOL_MASK) + cval[k];
         }
-        // the new carrier's parent and degree, from the record line the atomic just used
+        // the new carrier's parent, from the record line the atomic just used
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            if (cv[k] >= 0) {
-                const uint64_t h = aload(&sp.rec[2 * (size_t)cv[k] + 1]);
-                cp[k] = (int32_t)(uint32_t)h;
-                cdeg[k] = (int)(h >> 32);
-            }
-        }
+        for (int k = 0; k < NB; ++k)
+            if (cv[k] >= 0) cp[k] = rec_parent(sp.rec, cv[k]);
         if (nord > n) break;  // more entries than vertices: not a tree
     }
     if (lane == 0) astore(&sp.grp[ngrp], nord);
@@ -904,19 +901,18 @@ __device__ bool tree_numbering(const GraphDev &g, const SlotPtrs &sp) {
                     const int i = i0 + k * WAVE + lane;
                     e[k] = i < hi ? sp.ord[i] : make_int4(-1, -1, 0, 0);
                 }
-                // a vertex's tin is the next free position of its parent's interval,
-                // taken with one atomic on the parent's word
+                // tin = the parent's tin (written by its own group) + the offset the
+                // bottom-up atomic returned
                 uint64_t tin[NB];
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
                     tin[k] = 0;
-                    if (e[k].x >= 0 && e[k].y >= 0)
-                        tin[k] = afetch_add(&sp.rec[2 * (size_t)e[k].y], (uint64_t)(uint32_t)e[k].z);
+                    if (e[k].x >= 0 && e[k].y >= 0) tin[k] = (uint64_t)rec_tin(sp.rec, e[k].y) + (uint32_t)e[k].w;
                 }
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
                     if (e[k].x < 0) continue;
-                    astore(&sp.rec[2 * (size_t)e[k].x], tin[k] + (uint64_t)(uint32_t)e[k].w);
+                    astore(&sp.rec[2 * (size_t)e[k].x], tin[k] + (uint64_t)(uint32_t)e[k].z);
                     astore(&sp.rec[2 * (size_t)e[k].x + 1], (uint64_t)(uint32_t)e[k].y | (tin[k] << 32));
                 }
             }

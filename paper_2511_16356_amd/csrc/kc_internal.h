@@ -35,7 +35,7 @@ struct GraphDev {
 //   restart ring int32 [stride] at 16 stride
 // Once the tree's parents are copied into rec they are dead, and the tree
 // numbering reuses the block:
-//   ord  int4 [stride] at 0: finished vertices {v, parent, vol, deg}, leaves {v, parent, deg, deg}
+//   ord  int4 [stride] at 0: finished vertices {v, parent, vol, offset}, leaves {v, parent, deg, 0}
 //   grp  int32 [stride + 1] at 16 stride: completion group boundaries
 struct SlotDev {
     unsigned char *state; // [slots * state_bytes(stride)]
