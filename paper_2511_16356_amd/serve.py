@@ -214,10 +214,16 @@ class Server:
 
     def remove_graph(self, gid: int):
         """Free a resident graph once its queued requests are done; its bytes
-        return to the budget."""
+        return to the budget and its worker ends."""
         self.drain()
+        with self.done_cv:
+            q = self.queues.pop(gid)
+            t = self.threads.pop(gid)
+        q.put(None)
+        t.join()
         G = self.graphs.pop(gid)
         G.close()
+        self.streams.pop(gid, None)
         self.budget.release(self.held.pop(gid))
         self.tmp.pop(gid, None)
 
