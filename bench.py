@@ -36,18 +36,18 @@ LIB_SRC = os.path.join(ROOT, "paper_2511_16356_amd", "csrc")
 
 # HBM bytes per launch of the sampling kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs of this script (each in a run of its own), scaled by what the
-# counter reads for a plain 1 GiB copy (FETCH_SIZE x 1.99993, WRITE_SIZE x 1;
+# counter reads for a plain 1 GiB copy (FETCH_SIZE x 1.99992, WRITE_SIZE x 1;
 # profiles/hbm_traffic_*.md).  Keyed by the SHA-256 of the library sources the
 # counters were taken on (library_sha): other sources, or another workload,
 # sample count or seed, report traffic = null.
 MEASURED_TRAFFIC = {
-    "a08d42dab15486e1d2fa53e40f5506e2bbcefa52d8878a0f220070ac855779f6": [
+    "b049347fd167b424567c63761557e6006c70dd9cfd6ef897f165fff66afc39ff": [
         {"workload": "dense", "samples": 4096, "seed": 0,
-         "fetch_bytes": 9.6546e12, "write_bytes": 4.5782e12, "bytes": 1.42328e13},
+         "fetch_bytes": 1.1188e13, "write_bytes": 4.1845e12, "bytes": 1.5372e13},
         {"workload": "social", "samples": 8192, "seed": 0,
-         "fetch_bytes": 6.3707e12, "write_bytes": 3.0315e12, "bytes": 9.4022e12},
+         "fetch_bytes": 7.3610e12, "write_bytes": 2.7790e12, "bytes": 1.0140e13},
         {"workload": "road", "samples": 4096, "seed": 0, "direct": True,
-         "fetch_bytes": 6.0750e13, "write_bytes": 7.2729e13, "bytes": 1.3348e14},
+         "fetch_bytes": 3.5062e13, "write_bytes": 6.8268e13, "bytes": 1.0333e14},
     ],
 }
 
