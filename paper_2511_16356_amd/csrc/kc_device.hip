@@ -532,34 +532,36 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
         const uint64_t pm0 = __ballot(park);
         parked += __popcll(pm0);
         __syncthreads();
-        // a parked chain whose head's arrow points into a path that joined the tree
-        // joins it too, transitively (a scan of the chain table per step); then the
-        // chains of this round's joins return to the free ring
-        if (__ballot(finish) != 0ull) {
+        // the chains whose walk reached the tree go back to the free ring at once; a
+        // parked chain whose head's arrow points into a path that joined the tree
+        // joins it too, transitively (a scan of the chain table per step, only
+        // while chains are parked), and goes back to the ring as it is found.
+        // Their state reads "done" until the closure is over.
+        const uint64_t fm = __ballot(finish);
+        if (fm != 0ull) {
+            const int f0 = f_tail;
+            if (finish) sh.ring[(f_tail + rank_in(fm)) & (CH - 1)] = (int16_t)chain;
+            f_tail += __popcll(fm);
+            __syncthreads();
             for (int pass = 0; parked > 0; ++pass) {
-                int fresh = 0;
-                for (int c = lane; c < CH; c += WAVE) {
-                    if (sh.state[c] == CS_PARKED && sh.state[sh.up[c]] == CS_DONE) {
+                int tot = 0;
+                for (int c0 = 0; c0 < CH; c0 += WAVE) {
+                    const int c = c0 + lane;
+                    const bool join = sh.state[c] == CS_PARKED && sh.state[sh.up[c]] == CS_DONE;
+                    const uint64_t jm = __ballot(join);
+                    if (join) {
                         finish_chain(c);
-                        ++fresh;
+                        sh.ring[(f_tail + rank_in(jm)) & (CH - 1)] = (int16_t)c;
                     }
+                    f_tail += __popcll(jm);
+                    tot += __popcll(jm);
                 }
                 __syncthreads();
-                const int tot = (int)wave_sum((int64_t)fresh);
                 parked -= tot;
                 if (tot == 0) break;
                 if (pass > CH) { err = DEV_PROTOCOL; break; }
             }
-            for (int c0 = 0; c0 < CH; c0 += WAVE) {
-                const int c = c0 + lane;
-                const bool done = sh.state[c] == CS_DONE;
-                const uint64_t dm = __ballot(done);
-                if (done) {
-                    sh.ring[(f_tail + rank_in(dm)) & (CH - 1)] = (int16_t)c;
-                    sh.state[c] = CS_FREE;
-                }
-                f_tail += __popcll(dm);
-            }
+            for (int i = f0 + lane; i < f_tail; i += WAVE) sh.state[sh.ring[i & (CH - 1)]] = CS_FREE;
             if (finish) {
                 mode = M_IDLE;
                 chain = -1;
