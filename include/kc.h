@@ -101,9 +101,14 @@ enum {
                               2048 for graphs of at least 100,000 vertices and mean degree
                               below 4, else 1024).  More finish one sample in fewer rounds;
                               fewer let more samples run at once.  Results do not depend on it. */
-    KC_OPT_MAINTENANCE = 8 /* KC_MAINT_*: how kc_apply_updates maintains the resident set;
+    KC_OPT_MAINTENANCE = 8, /* KC_MAINT_*: how kc_apply_updates maintains the resident set;
                               may change while the set's weights are all equal (always under
                               basic maintenance), else KC_ERR_INVALID */
+    KC_OPT_LEAN_LOOKS = 9  /* a walk's look at its next vertex is the claim alone, and a vertex
+                              it claims has its arrow word and graph record read in the next
+                              round (fewer lines where most looks meet the tree, one more
+                              round per claim): 0 = when the mean degree is at least 8
+                              (default), 1 = off, 2 = on.  Results do not depend on it. */
 };
 
 /* Sample maintenance of a resident set (section 4). */

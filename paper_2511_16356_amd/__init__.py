@@ -26,6 +26,7 @@ KC_OPT_START_ORDER = 6
 KC_OPT_CHAINS = 7
 KC_TAU0_BFS, KC_TAU0_DFS, KC_TAU0_GIVEN = 0, 1, 2
 KC_OPT_MAINTENANCE = 8
+KC_OPT_LEAN_LOOKS = 9
 KC_MAINT_BASIC, KC_MAINT_IMPROVED = 0, 1
 
 # every symbol include/kc.h declares

@@ -91,6 +91,7 @@ kc_status kc_batch_create(kc_graph *const *graphs, int32_t k, const uint64_t *se
         job.iter_cap = rp.iter_cap;
         job.walkers = rp.walkers;
         job.traversal = rp.traversal;
+        job.lean = rp.lean;
     }
     // samples in flight: the first graph's slots option (else the kernel's resident
     // workgroups), within its memory budget for slots sized for the largest graph

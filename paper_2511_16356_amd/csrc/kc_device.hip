@@ -188,7 +188,8 @@ enum : int {
     M_NEED = 3,    // set the need bit of start vertex `tgt` if its tag word is still `seen`
     M_ADJ = 4,     // the drawn neighbour lies beyond the inline ones: fetch it
     M_ERASE0 = 5,  // popping: load the kept vertex `tgt` (the new head)
-    M_ERASE = 6    // popping: free `tgt`, follow next until `stopv`
+    M_ERASE = 6,   // popping: free `tgt`, follow next until `stopv`
+    M_FETCH = 7    // lean looks: load the arrow word and graph record of the head just claimed
 };
 
 template <int CH>
@@ -232,7 +233,7 @@ struct SamplerWS {
 // Returns the total number of draws, or -1 (error recorded in ctl).
 template <int CH>
 __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerShared<CH> &sh,
-                               uint64_t seed, uint64_t s, int walkers, int64_t iter_cap,
+                               uint64_t seed, uint64_t s, int walkers, int lean, int64_t iter_cap,
                                int32_t *ctl, int idx, int64_t *iters_used, int32_t root_u,
                                int32_t root_v) {
     const int lane = threadIdx.x;
@@ -375,13 +376,18 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
         // ---- memory: every lane issues its operations before any result is used
         const bool do_cas = m0 == M_LOOK || m0 == M_PARK || m0 == M_NEED;
         const bool do_xchg = m0 == M_ERASE;
-        const bool do_arrow = m0 == M_LOOK || m0 == M_ERASE0 || do_xchg;
-        const bool do_rec = m0 == M_LOOK || m0 == M_ERASE0;
+        // a lean look at a walk's next vertex is the claim alone: most such looks
+        // meet the tree, and a claimed vertex's arrow word and record are fetched
+        // in the next round (M_FETCH)
+        const bool thin = lean && m0 == M_LOOK && haspath;
+        const bool do_arrow = (m0 == M_LOOK && !thin) || m0 == M_ERASE0 || m0 == M_FETCH || do_xchg;
+        const bool do_rec = (m0 == M_LOOK && !thin) || m0 == M_ERASE0 || m0 == M_FETCH;
         if (m0 == M_LOOK && pend) astore(&arw[cur], arrow_of(tgt, dcur));
         int4 r0 = make_int4(0, 0, 0, 0), r1 = make_int4(0, 0, 0, 0);
+        const int rv = m0 == M_FETCH ? cur : tgt;  // the vertex whose words are read
         if (do_rec) {
-            r0 = g.vrec[2 * (size_t)tgt];
-            r1 = g.vrec[2 * (size_t)tgt + 1];
+            r0 = g.vrec[2 * (size_t)rv];
+            r1 = g.vrec[2 * (size_t)rv + 1];
         }
         // (each operation returns into a register of its own: a shared one would make
         // every later issue wait for the earlier operations' results)
@@ -398,7 +404,7 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
         if (m0 == M_ERASE0) o_tag = aload(&tagw[tgt]);
         uint64_t ar = 0;
-        if (do_arrow) ar = aload(&arw[tgt]);
+        if (do_arrow) ar = aload(&arw[rv]);
         auto take_record = [&]() __attribute__((always_inline)) {
             hoff = r0.x; hdeg = r0.y; hn0 = r0.z; hn1 = r0.w;
             hn2 = r1.x; hn3 = r1.y; hn4 = r1.z; hn5 = r1.w;
@@ -419,20 +425,28 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             const bool drew = pend;  // the arrow into tgt was just published
             pend = false;
             if (old == T_FREE) {
-                // claimed: the new head draws at once
+                // claimed: the new head draws at once (after a lean look, next round)
                 cur = tgt;
-                dcur = dt;
-                take_record();
-                drawing = true;
+                if (thin) {
+                    mode = M_FETCH;
+                } else {
+                    dcur = dt;
+                    take_record();
+                    drawing = true;
+                }
             } else if (tg == ctag) {
                 // own path: the new arrow closed a loop at tgt; pop it, keep tgt as head
                 if (!drew) err = DEV_PROTOCOL;
-                cur = tgt;
-                dcur = dt;
-                take_record();
                 stopv = tgt;
-                tgt = nt;
-                mode = M_ERASE;
+                if (thin) {
+                    mode = M_ERASE0;  // reads tgt's words, then erases from its arrow on
+                } else {
+                    cur = tgt;
+                    dcur = dt;
+                    take_record();
+                    tgt = nt;
+                    mode = M_ERASE;
+                }
             } else if (in_tree(tg)) {
                 if (haspath) finish = true;  // the path reaches the tree and joins it
                 else retire = true;          // a fresh chain whose start is already in the tree
@@ -478,6 +492,10 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             take_record();
             if (nt == stopv) drawing = true;
             else { mode = M_ERASE; tgt = nt; }
+        } else if (m0 == M_FETCH) {
+            dcur = dt;
+            take_record();
+            drawing = true;
         }
         if (drawing) draw();
         // paths that reached the tree join it: their generation is finished
@@ -1266,7 +1284,7 @@ __device__ bool process_one(const GraphDev &g, const SlotPtrs &sp, KernelShared<
     const size_t n = (size_t)g.n;
     int64_t steps = 0, iters = 0;
     if (!CROSS && (rp.mode == RUN_SAMPLE || rp.mode == RUN_ESTIMATE)) {
-        steps = sample_tree<CH>(g, sp.ws, lds.samp, rp.seed, s, rp.walkers, rp.iter_cap, rp.ctl, idx, &iters,
+        steps = sample_tree<CH>(g, sp.ws, lds.samp, rp.seed, s, rp.walkers, rp.lean, rp.iter_cap, rp.ctl, idx, &iters,
                                 rp.root_u, rp.root_v);
         if (steps < 0) return false;
     }
@@ -1378,6 +1396,7 @@ batch_kernel(BatchArgs a, SlotDev sd, int32_t *ctl,
         rp.mode = RUN_ESTIMATE;
         rp.walkers = job.walkers;
         rp.traversal = job.traversal;
+        rp.lean = job.lean;
         rp.iter_cap = job.iter_cap;
         rp.ctl = ctl;
         rp.f_out = a.f;

@@ -258,6 +258,9 @@ kc::GraphDev kc_host::graph_dev(const kc_graph *g) {
 void kc_host::fill_run_options(const kc_graph *g, kc::RunParams &rp) {
     rp.walkers = g->walkers;
     rp.traversal = g->traversal;
+    // lean looks pay where walks are short, so that most looks at a walk's next
+    // vertex meet the tree: by default when the mean degree is at least 8
+    rp.lean = g->lean_opt == 2 || (g->lean_opt == 0 && g->two_m >= 8 * g->n);
     rp.iter_cap = g->step_limit > 0 ? g->step_limit : 1024 * g->n + (1 << 22);
     rp.ctl = g->d_ctl;
 }
@@ -802,6 +805,10 @@ kc_status kc_set_option(kc_graph *g, int option, int64_t value) {
         case KC_OPT_CHAINS:
             if (!kc::valid_chains((int)value)) return fail(KC_ERR_INVALID, "chains per sample must be 1024 or 2048");
             g->chains = (int32_t)value;
+            return KC_OK;
+        case KC_OPT_LEAN_LOOKS:
+            if (value < 0 || value > 2) return fail(KC_ERR_INVALID, "lean looks must be 0, 1 or 2");
+            g->lean_opt = (int32_t)value;
             return KC_OK;
         case KC_OPT_SLOTS:
             if (value < 0 || value > (1 << 20)) return fail(KC_ERR_INVALID, "slots must be 0..2^20");

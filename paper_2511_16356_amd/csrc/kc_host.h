@@ -22,6 +22,7 @@ struct kc_graph {
     int32_t traversal = KC_TRAV_WALK;
     int32_t walkers = 64;
     int32_t chains = 1024;
+    int32_t lean_opt = 0;  // KC_OPT_LEAN_LOOKS: 0 by mean degree, 1 off, 2 on
     int32_t slots_opt = 0;
     int32_t trav_opt = KC_TRAV_AUTO;
     int64_t step_limit = 0;

@@ -59,7 +59,7 @@ struct BatchJob {
     uint64_t seed;
     int64_t first;      // sample index of the job's first item at launch 0
     int64_t iter_cap;   // sampler rounds per sample
-    int32_t walkers, traversal;
+    int32_t walkers, traversal, lean;
 };
 
 constexpr int BATCH_MAX = 8;  // graphs in one batch launch
@@ -87,6 +87,8 @@ struct RunParams {
     int32_t walkers;    // 1..64
     int32_t mode;       // RunMode
     int32_t traversal;  // 1 walk, 2 sweep
+    int32_t lean;       // 1: a walk's look at its next vertex is the claim alone (results do
+                        //    not depend on it)
     int64_t iter_cap;   // sampler iterations per sample
     const int32_t *parents_in; // RUN_EVALUATE input [count*n]
     int32_t *parents_out;      // RUN_SAMPLE  [count*n]

@@ -122,6 +122,29 @@ def test_chain_table_size_invariance(kc, oracle_lib, graphs, chains):
             assert G.progress() == 20
 
 
+@pytest.mark.parametrize("lean", [1, 2])
+def test_lean_looks_change_nothing(kc, oracle_lib, graphs, lean):
+    """A walk's look at its next vertex as the claim alone, with the claimed
+    vertex's words read in the next round, or as one full round (either way on
+    every graph, whatever the mean-degree default), changes nothing: trees,
+    draw counts and f stay exact, also with more samples than slots."""
+    for name in ("K5", "petersen", "grid32", "road3k", "social3k", "torus12", "gnm300"):
+        g = graphs[name]
+        _say("lean", lean, name)
+        P = oracle_lib.prepare_graph(g)
+        ref_par, ref_cnt, ref_steps = oracle_lib.sample(P, seed=37, s0=300, count=24, threads=8)
+        ref_f = np.array([oracle_lib.f_of_tree(P, t) for t in ref_par], np.int64)
+        with kc.Graph.from_graph(g) as G:
+            G.set_option(kc.KC_OPT_LEAN_LOOKS, lean)
+            par, cnt, stp = G.sample_trees(37, 300, 24)
+            assert np.array_equal(par.cpu().numpy(), ref_par)
+            assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ref_cnt)
+            assert np.array_equal(stp.cpu().numpy(), ref_steps)
+            G.set_option(kc.KC_OPT_SLOTS, 5)
+            _, f, _ = G.estimate(37, 300, 24, per_sample=True)
+            assert np.array_equal(f.cpu().numpy(), ref_f)
+
+
 def test_batch_split_invariance(kc, graphs):
     g = graphs["road3k"]
     with kc.Graph.from_graph(g) as G:
