@@ -41,11 +41,17 @@ LIB_SRC = os.path.join(ROOT, "paper_2511_16356_amd", "csrc")
 # counters were taken on (library_sha): other sources, or another workload,
 # sample count or seed, report traffic = null.
 MEASURED_TRAFFIC = {
+    "3bc1c440df2c3d151af35ad1d81f4e825ce71d1c2097cee7f2da191f9d7aac12": [
+        {"workload": "dense", "samples": 4096, "seed": 0,
+         "fetch_bytes": 8.8783e12, "write_bytes": 4.2736e12, "bytes": 1.3152e13},
+        {"workload": "social", "samples": 8192, "seed": 0,
+         "fetch_bytes": 6.1436e12, "write_bytes": 2.8417e12, "bytes": 8.9853e12},
+    ],
+    # earlier sources (before lean looks and the chain-ring change): kept for the record
     "4564d6b8d6afc957cbc43894fc61214308b3a71b63e1d45e1c7d7078f7caff51": [
         {"workload": "dense", "samples": 4096, "seed": 0,
          "fetch_bytes": 1.1195e13, "write_bytes": 4.1896e12, "bytes": 1.5385e13},
     ],
-    # the sources before the last change to the sampler's chain ring (an LDS-only change)
     "b049347fd167b424567c63761557e6006c70dd9cfd6ef897f165fff66afc39ff": [
         {"workload": "dense", "samples": 4096, "seed": 0,
          "fetch_bytes": 1.1188e13, "write_bytes": 4.1845e12, "bytes": 1.5372e13},
