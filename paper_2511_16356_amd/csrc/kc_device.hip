@@ -231,9 +231,9 @@ struct SamplerWS {
 // cycle of the wait-for forest, all in lockstep.
 //
 // Returns the total number of draws, or -1 (error recorded in ctl).
-template <int CH>
+template <int CH, bool LEAN>
 __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerShared<CH> &sh,
-                               uint64_t seed, uint64_t s, int walkers, int lean, int64_t iter_cap,
+                               uint64_t seed, uint64_t s, int walkers, int64_t iter_cap,
                                int32_t *ctl, int idx, int64_t *iters_used, int32_t root_u,
                                int32_t root_v) {
     const int lane = threadIdx.x;
@@ -379,12 +379,14 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
         // a lean look at a walk's next vertex is the claim alone: most such looks
         // meet the tree, and a claimed vertex's arrow word and record are fetched
         // in the next round (M_FETCH)
-        const bool thin = lean && m0 == M_LOOK && haspath;
-        const bool do_arrow = (m0 == M_LOOK && !thin) || m0 == M_ERASE0 || m0 == M_FETCH || do_xchg;
-        const bool do_rec = (m0 == M_LOOK && !thin) || m0 == M_ERASE0 || m0 == M_FETCH;
+        // (LEAN: a compile-time choice, so that a kernel without lean looks carries none of it)
+        const bool thin = LEAN && m0 == M_LOOK && haspath;
+        const bool fetch = LEAN && m0 == M_FETCH;
+        const bool do_arrow = (m0 == M_LOOK && !thin) || m0 == M_ERASE0 || fetch || do_xchg;
+        const bool do_rec = (m0 == M_LOOK && !thin) || m0 == M_ERASE0 || fetch;
         if (m0 == M_LOOK && pend) astore(&arw[cur], arrow_of(tgt, dcur));
         int4 r0 = make_int4(0, 0, 0, 0), r1 = make_int4(0, 0, 0, 0);
-        const int rv = m0 == M_FETCH ? cur : tgt;  // the vertex whose words are read
+        const int rv = fetch ? cur : tgt;  // the vertex whose words are read
         if (do_rec) {
             r0 = g.vrec[2 * (size_t)rv];
             r1 = g.vrec[2 * (size_t)rv + 1];
@@ -492,7 +494,7 @@ __device__ int64_t sample_tree(const GraphDev &g, const SamplerWS &ws, SamplerSh
             take_record();
             if (nt == stopv) drawing = true;
             else { mode = M_ERASE; tgt = nt; }
-        } else if (m0 == M_FETCH) {
+        } else if (fetch) {
             dcur = dt;
             take_record();
             drawing = true;
@@ -1277,14 +1279,14 @@ __device__ __forceinline__ SlotPtrs slot_ptrs(const SlotDev &sd, size_t stride) 
 // f.  Returns false when the workgroup must stop (an error was recorded).
 // CROSS: the instantiation for RUN_CROSS only (no sampler, no f), kept apart
 // so that its code does not weigh on the sampler's register allocation.
-template <int CH, bool CROSS>
+template <int CH, bool CROSS, bool LEAN>
 __device__ bool process_one(const GraphDev &g, const SlotPtrs &sp, KernelShared<CH> &lds, const RunParams &rp,
                             int64_t fen_len, int idx, uint64_t s) {
     const int lane = threadIdx.x;
     const size_t n = (size_t)g.n;
     int64_t steps = 0, iters = 0;
     if (!CROSS && (rp.mode == RUN_SAMPLE || rp.mode == RUN_ESTIMATE)) {
-        steps = sample_tree<CH>(g, sp.ws, lds.samp, rp.seed, s, rp.walkers, rp.lean, rp.iter_cap, rp.ctl, idx, &iters,
+        steps = sample_tree<CH, LEAN>(g, sp.ws, lds.samp, rp.seed, s, rp.walkers, rp.iter_cap, rp.ctl, idx, &iters,
                                 rp.root_u, rp.root_v);
         if (steps < 0) return false;
     }
@@ -1355,7 +1357,7 @@ __device__ __forceinline__ bool stopped(const int32_t *ctl) {
 template <int CH>
 constexpr int waves_per_simd() { return CH <= 1024 ? 3 : 2; }
 
-template <int CH, bool CROSS = false>
+template <int CH, bool CROSS = false, bool LEAN = false>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(waves_per_simd<CH>())))
 persistent_kernel(GraphDev g, SlotDev sd, RunParams rp) {
     __shared__ KernelShared<CH> lds;
@@ -1364,7 +1366,7 @@ persistent_kernel(GraphDev g, SlotDev sd, RunParams rp) {
     while (true) {
         const int idx = next_item(rp.ctl);
         if (idx >= rp.count || stopped(rp.ctl)) break;
-        if (!process_one<CH, CROSS>(g, sp, lds, rp, sd.fen_len, idx, (uint64_t)(rp.first + idx))) break;
+        if (!process_one<CH, CROSS, LEAN>(g, sp, lds, rp, sd.fen_len, idx, (uint64_t)(rp.first + idx))) break;
         // samples finished by this workgroup, for a host that watches a long batch
         ++done;
         if (rp.progress && threadIdx.x == 0)
@@ -1378,7 +1380,7 @@ persistent_kernel(GraphDev g, SlotDev sd, RunParams rp) {
 // where `launch` counts the launches of the batch so far (read from device
 // memory, advanced by advance_kernel after each launch).  Every item's f,
 // draws and rounds go to position idx of the batch arrays.
-template <int CH>
+template <int CH, bool LEAN>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(waves_per_simd<CH>())))
 batch_kernel(BatchArgs a, SlotDev sd, int32_t *ctl,
                                                      const int64_t *launch) {
@@ -1396,14 +1398,13 @@ batch_kernel(BatchArgs a, SlotDev sd, int32_t *ctl,
         rp.mode = RUN_ESTIMATE;
         rp.walkers = job.walkers;
         rp.traversal = job.traversal;
-        rp.lean = job.lean;
         rp.iter_cap = job.iter_cap;
         rp.ctl = ctl;
         rp.f_out = a.f;
         rp.steps_out = a.steps;
         rp.iters_out = a.iters;
         const uint64_t s = (uint64_t)(job.first + L * (int64_t)(a.base[j + 1] - a.base[j]) + (idx - a.base[j]));
-        if (!process_one<CH, false>(job.g, sp, lds, rp, job.g.two_m + 2, idx, s)) break;
+        if (!process_one<CH, false, LEAN>(job.g, sp, lds, rp, job.g.two_m + 2, idx, s)) break;
     }
 }
 
@@ -1581,10 +1582,13 @@ hipError_t launch_persistent(const GraphDev &g, const SlotDev &s, const RunParam
         hipLaunchKernelGGL((persistent_kernel<1024, true>), dim3(slots), dim3(WAVE), 0, stream, g, s, rp);
         return hipGetLastError();
     }
-#define KC_CASE(C)                                                                              \
-    if (chains == C) {                                                                         \
-        hipLaunchKernelGGL(persistent_kernel<C>, dim3(slots), dim3(WAVE), 0, stream, g, s, rp); \
-        return hipGetLastError();                                                              \
+#define KC_CASE(C)                                                                                   \
+    if (chains == C) {                                                                              \
+        if (rp.lean)                                                                                \
+            hipLaunchKernelGGL((persistent_kernel<C, false, true>), dim3(slots), dim3(WAVE), 0, stream, g, s, rp); \
+        else                                                                                        \
+            hipLaunchKernelGGL((persistent_kernel<C, false, false>), dim3(slots), dim3(WAVE), 0, stream, g, s, rp); \
+        return hipGetLastError();                                                                   \
     }
     KC_CHAIN_VARIANTS(KC_CASE)
 #undef KC_CASE
@@ -1597,7 +1601,7 @@ int batch_blocks_per_cu(int chains) {
     int blocks = 0;
 #define KC_CASE(C)                                                                                   \
     if (chains == C) {                                                                              \
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel<C>, WAVE, 0) !=        \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel<C, false>, WAVE, 0) != \
             hipSuccess)                                                                             \
             return 0;                                                                               \
         return blocks;                                                                              \
@@ -1636,9 +1640,15 @@ hipError_t launch_batch(const BatchArgs &a, const SlotDev &s, int32_t *ctl, int6
     hipLaunchKernelGGL(reset_ctl_kernel, dim3(1), dim3(64), 0, stream, ctl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // lean looks when every job of the batch takes them
+    bool lean = true;
+    for (int j = 0; j < a.k; ++j) lean = lean && a.job[j].lean != 0;
 #define KC_CASE(C)                                                                                \
     if (chains == C) {                                                                           \
-        hipLaunchKernelGGL(batch_kernel<C>, dim3(slots), dim3(WAVE), 0, stream, a, s, ctl, launch); \
+        if (lean)                                                                                \
+            hipLaunchKernelGGL((batch_kernel<C, true>), dim3(slots), dim3(WAVE), 0, stream, a, s, ctl, launch); \
+        else                                                                                     \
+            hipLaunchKernelGGL((batch_kernel<C, false>), dim3(slots), dim3(WAVE), 0, stream, a, s, ctl, launch); \
         e = hipGetLastError();                                                                   \
     }
     e = hipErrorInvalidValue;
