@@ -275,6 +275,39 @@ def test_bench_exact_kemeny_closed_forms(gen):
     assert bench.exact_kemeny(g.offsets, g.indices) == pytest.approx(E.kemeny_exact(g.offsets, g.indices), rel=1e-12)
 
 
+def test_bench_request_plans(gen):
+    """The serving mix's request plans: the same seed gives the same plan,
+    about 80% queries and 20% update batches, deletions of at most 1,000 and
+    insertions of at most 10 edges, arrival times increasing at the offered
+    rate (all at zero when saturated), and each update applied to the
+    planned graph so that later updates see it."""
+    import numpy as np
+    import bench
+    import graphgen
+    base = [graphgen.road_like(3000, seed=1), gen.grid(12, 12)]
+    plans = []
+    for _ in range(2):
+        cur = list(base)
+        plans.append(bench.plan_requests(cur, 200, 50.0, np.random.default_rng(5)))
+    a, b = plans
+    assert [(t, g, k, len(e), i) for t, g, k, e, i in a] == [(t, g, k, len(e), i) for t, g, k, e, i in b]
+    kinds = [k for _, _, k, _, _ in a]
+    assert 0.7 < kinds.count("query") / len(kinds) < 0.9
+    times = [t for t, _, _, _, _ in a]
+    assert all(x < y for x, y in zip(times, times[1:]))
+    assert 2.0 < times[-1] < 6.0  # 200 requests at 50 per second
+    ups = [(e, ins) for _, _, kind, e, ins in a if kind == "update"]
+    # a deletion batch that would disconnect the graph is halved, possibly to nothing
+    assert all(len(e) <= (10 if ins else 1000) for e, ins in ups)
+    assert sum(1 for e, _ in ups if e) >= len(ups) // 2
+    cur = list(base)
+    sat = bench.plan_requests(cur, 40, 1.0, np.random.default_rng(6), saturate=True)
+    assert all(t == 0.0 for t, _, _, _, _ in sat)
+    removed = sum(len(e) for _, _, k, e, ins in sat if k == "update" and not ins)
+    added = sum(len(e) for _, _, k, e, ins in sat if k == "update" and ins)
+    assert sum(g.two_m for g in cur) == sum(g.two_m for g in base) - 2 * removed + 2 * added
+
+
 def test_bench_algorithmic_bytes():
     import bench
     # one sector per draw, per vertex (joining the tree), and per path-mapping term
