@@ -46,6 +46,8 @@ MEASURED_TRAFFIC = {
          "fetch_bytes": 8.8753e12, "write_bytes": 4.2740e12, "bytes": 1.3149e13},
         {"workload": "social", "samples": 8192, "seed": 0,
          "fetch_bytes": 6.1406e12, "write_bytes": 2.8420e12, "bytes": 8.9825e12},
+        {"workload": "road", "samples": 4096, "seed": 0, "direct": True,
+         "fetch_bytes": 3.5018e13, "write_bytes": 6.8240e13, "bytes": 1.0326e14},
     ],
     # earlier sources, kept for the record (lean looks as a run-time switch)
     "3bc1c440df2c3d151af35ad1d81f4e825ce71d1c2097cee7f2da191f9d7aac12": [
