@@ -36,6 +36,8 @@ def _check_prefix(kc, oracle_lib, g, count, tree_id):
     K, se, s1, s2 = oracle_lib.reduce_estimate(ref_f, g.two_m)
     with kc.Graph.from_graph(g) as G:
         assert G.root == P.root
+        # large sparse graphs get the 2,048-entry chain table by default, the others 1,024
+        assert G.info["chains"] == (2048 if g.n >= 100_000 and g.two_m < 4 * g.n else 1024)
         _say("gpu estimate")
         est, f, st = G.estimate(0, 0, count, per_sample=True)
         assert np.array_equal(f.cpu().numpy(), ref_f)
