@@ -24,7 +24,11 @@ Admission is by HBM footprint, against one device budget:
   - an update additionally holds, while it runs, the temporary buffers the
     library allocates for it (at most two parent arrays per resident tree);
   - a query allocates nothing.
-A graph whose footprint can never fit is refused with KC_ERR_NOMEM; one that
+A graph is admitted only while the resident footprints, its own included,
+leave room for the largest update of any resident graph: the bytes outside
+the resident graphs then always hold that update, so an update waits at most
+for the requests and initial draws running before it, never for good.  A
+graph whose footprint can never fit is refused with KC_ERR_NOMEM; one that
 does not fit now waits until removed graphs free memory (or is refused after
 ``timeout``).
 
@@ -33,6 +37,7 @@ estimator and of the maintenance runs in the library's kernels.
 """
 from __future__ import annotations
 
+import collections
 import queue
 import threading
 import time
@@ -57,23 +62,42 @@ class Request:
 
 
 class _Budget:
-    """Device bytes held by resident graphs and by the requests in flight."""
+    """Device bytes held by resident graphs and by the requests in flight.
+
+    free: bytes nothing holds now.  resident: the steady-state bytes of the
+    admitted graphs.  reserves: the temporary bytes one update of each
+    admitted graph may need; resident + max(reserves) never exceeds total."""
 
     def __init__(self, total: int):
         self.total = total
         self.free = total
+        self.resident = 0
+        self.reserves = collections.Counter()
         self.cv = threading.Condition()
 
-    def acquire(self, nbytes: int, timeout: float = None, hopeless=None, taken=None) -> bool:
-        """Take nbytes once they are free (False after `timeout` seconds, at
-        once if nbytes exceeds the whole budget, or as soon as hopeless()
-        says that nothing held now will be released); taken() runs under the
-        same lock once the bytes are taken."""
-        if nbytes > self.total:
+    def reserve(self) -> int:
+        return max(self.reserves, default=0)
+
+    def acquire(self, nbytes: int, timeout: float = None, hopeless=None, taken=None,
+                steady: int = 0, reserve: int = 0) -> bool:
+        """Take nbytes once they are free.  For a graph being admitted, steady
+        is what it keeps resident and reserve what one of its updates may
+        need: it also waits until the resident bytes with steady added still
+        leave room for the largest reserve.  False after `timeout` seconds, at
+        once if it could not fit even alone, or as soon as hopeless() says
+        that nothing held now will be released; taken() runs under the same
+        lock once the bytes are taken."""
+        if nbytes > self.total or steady + reserve > self.total:
             return False
         end = None if timeout is None else time.perf_counter() + timeout
+
+        def fits():
+            if self.free < nbytes:
+                return False
+            return steady == 0 or self.resident + steady + max(self.reserve(), reserve) <= self.total
+
         with self.cv:
-            while self.free < nbytes:
+            while not fits():
                 left = None if end is None else end - time.perf_counter()
                 if left is not None and left <= 0:
                     return False
@@ -81,13 +105,25 @@ class _Budget:
                     return False
                 self.cv.wait(left if hopeless is None else min(1.0, left) if left is not None else 1.0)
             self.free -= nbytes
+            if steady:
+                self.resident += steady
+                self.reserves[reserve] += 1
             if taken is not None:
                 taken()
         return True
 
-    def release(self, nbytes: int):
+    def release(self, nbytes: int, steady: int = 0, reserve: int = 0, then=None):
+        """Return nbytes (for a graph leaving: also its steady bytes and its
+        reserve); then() runs under the same lock, before the waiters wake."""
         with self.cv:
             self.free += nbytes
+            if steady:
+                self.resident -= steady
+                self.reserves[reserve] -= 1
+                if self.reserves[reserve] == 0:
+                    del self.reserves[reserve]
+            if then is not None:
+                then()
             self.cv.notify_all()
 
 
@@ -146,13 +182,19 @@ class Server:
         need = resident_bytes(info, samples, workspace)
         need_init = resident_bytes(info, samples, init_ws)
 
+        tmp = update_bytes(info, samples)
+
         def drawing_starts():
             self.drawing += 1
 
-        if not self.budget.acquire(need_init, timeout, hopeless, taken=drawing_starts):
+        def drawing_ends():
+            self.drawing -= 1
+
+        if not self.budget.acquire(need_init, timeout, hopeless, taken=drawing_starts, steady=need, reserve=tmp):
             G.close()
-            raise KcError(3, "graph %s needs %d device bytes resident; %d of %d are free" %
-                          (gid, need_init, self.budget.free, self.budget.total))
+            raise KcError(3, "graph %s needs %d device bytes resident and %d for an update; %d of %d are free, "
+                          "%d held resident" % (gid, need_init, tmp, self.budget.free, self.budget.total,
+                                                self.budget.resident))
         try:
             G.set_option(KC_OPT_MEM_BUDGET, init_ws)
             G.set_option(KC_OPT_MAINTENANCE, self.maintenance)
@@ -163,17 +205,14 @@ class Server:
                 G.set_option(KC_OPT_MEM_BUDGET, workspace)
         except Exception:
             G.close()
-            with self.budget.cv:
-                self.drawing -= 1
-            self.budget.release(need_init)
+            self.budget.release(need_init, steady=need, reserve=tmp, then=drawing_ends)
             raise
-        with self.budget.cv:
-            self.drawing -= 1
-        self.budget.release(need_init - need)
+        # the end of the draw and the bytes it returns are seen together
+        self.budget.release(need_init - need, then=drawing_ends)
         with self.done_cv:
             self.graphs[gid] = G
             self.held[gid] = need
-            self.tmp[gid] = update_bytes(info, samples)
+            self.tmp[gid] = tmp
             self.streams[gid] = stream
             q = queue.Queue()
             self.queues[gid] = q
@@ -224,8 +263,8 @@ class Server:
         G = self.graphs.pop(gid)
         G.close()
         self.streams.pop(gid, None)
-        self.budget.release(self.held.pop(gid))
-        self.tmp.pop(gid, None)
+        held = self.held.pop(gid)
+        self.budget.release(held, steady=held, reserve=self.tmp.pop(gid))
 
     def submit(self, req: Request):
         with self.done_cv:
@@ -289,9 +328,11 @@ class Server:
             t.join()
         for gid, G in self.graphs.items():
             G.close()
-            self.budget.release(self.held.get(gid, 0))
+            held = self.held.get(gid, 0)
+            self.budget.release(held, steady=held, reserve=self.tmp.get(gid, 0))
         self.graphs.clear()
         self.held.clear()
+        self.tmp.clear()
 
 
 def latency_stats(reqs, kind: str):

@@ -262,6 +262,41 @@ def test_admission_by_resident_footprint(serve):
     assert srv.budget.free == srv.budget.total
 
 
+def test_admission_keeps_room_for_an_update(serve):
+    """A budget that would hold two resident graphs but not, beside them, the
+    temporaries of one update: the second graph is refused, so the first
+    graph's updates still run instead of waiting for good.  The reserve goes
+    when its graph does."""
+    from paper_2511_16356_amd import KcError
+    one = _resident(serve)
+    tmp = serve.update_bytes(_FakeGraph.info, 8)
+    srv = serve.Server(budget_bytes=2 * one + tmp // 2, workspace_share=1 << 20)
+    try:
+        srv.add_graph(0, 0, seed=0, samples=8)
+        assert srv.budget.resident == one and srv.budget.reserve() == tmp
+        with pytest.raises(KcError) as ei:
+            srv.add_graph(1, 1, seed=1, samples=8, timeout=0.2)
+        assert ei.value.status == 3 and "for an update" in str(ei.value)
+        reqs = _submit_all(srv, serve, [(0, "update"), (0, "query"), (0, "update")])
+        assert all(not r.error for r in reqs) and [r.result for r in reqs] == [1, "estimate", 1]
+        # a smaller graph whose own update fits beside the first graph's reserve is admitted
+        small = dict(_FakeGraph.info, n=16, device_bytes=1000)
+        need = serve.resident_bytes(small, 8, 8 * 100)
+        assert one + need + tmp <= srv.budget.total
+        orig = _FakeGraph.info
+        _FakeGraph.info = small
+        try:
+            srv.add_graph(2, 2, seed=2, samples=8, timeout=0.2)
+        finally:
+            _FakeGraph.info = orig
+        assert srv.budget.resident == one + need and srv.budget.reserve() == tmp
+        srv.remove_graph(0)
+        assert srv.budget.resident == need and srv.budget.reserve() == serve.update_bytes(small, 8)
+    finally:
+        srv.close()
+    assert srv.budget.free == srv.budget.total and srv.budget.resident == 0 and srv.budget.reserve() == 0
+
+
 def test_bench_exact_kemeny_closed_forms(gen):
     import bench
     for n in (3, 5, 9):
