@@ -1,7 +1,9 @@
 """Host logic of the serving loop (paper_2511_16356_amd.serve), on the CPU:
 the graphs and streams are replaced by stand-ins that record what runs when,
 so the scheduling rules can be checked without a device.  Also the
-benchmark's exact-kappa helper against closed forms."""
+benchmark's host helpers: exact kappa against closed forms, the serving
+mix's request plans, the algorithmic byte count, the oracle leg's record,
+and the refusal of more than one GPU."""
 import threading
 import time
 
@@ -362,3 +364,13 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_bench_cpu_baseline_record(gen):
+    """The oracle leg of the benchmark on a tiny graph: a positive rate over
+    exactly threads x per_thread samples, and the host it ran on."""
+    import bench
+    rec = bench.cpu_baseline(gen.grid(6, 6), seed=3, first=10, threads=2, per_thread=3, what="the 6x6 grid")
+    assert rec["kind"] == "oracle" and rec["unit"] == "samples/s" and rec["cores"] == 2
+    assert rec["value"] > 0 and rec["nproc"] >= 1
+    assert rec["sample"].startswith("samples 10..15 of the 6x6 grid (3 per thread on 2 threads)")
