@@ -129,7 +129,7 @@ enum {
  *   root     : -1 to choose automatically, else the root vertex
  *   out      : receives the handle (NULL on failure)
  * Errors: KC_ERR_INVALID, KC_ERR_DISCONNECTED, KC_ERR_OVERFLOW, KC_ERR_NOMEM,
- * KC_ERR_DEVICE, KC_ERR_UNSUPPORTED (max degree >= 2^20).
+ * KC_ERR_DEVICE, KC_ERR_UNSUPPORTED (max degree >= 2^20, or n > 2^31 - 1024).
  */
 kc_status kc_graph_create(int64_t n, const void *offsets, int offsets_are_i64,
                           const int32_t *indices, int32_t root, void *hip_stream,
@@ -276,7 +276,8 @@ kc_status kc_estimate_static(kc_graph *g, uint64_t seed, int64_t first_sample, i
  * status and sums stay on the device until kc_batch_results reads them.
  * Launch options (step limit, walkers, traversal) are each
  * graph's; the chain-table size, samples in flight and memory budget are the
- * first graph's.  The batch owns its workspace (slots sized for the largest
+ * first graph's; lean looks (KC_OPT_LEAN_LOOKS) are taken only when every
+ * graph of the batch takes them (results do not depend on either).  The batch owns its workspace (slots sized for the largest
  * graph) and copies of the graphs' device array pointers: the graphs must
  * outlive the batch and must not be updated (kc_apply_updates, kc_set_tau0)
  * while it exists.
