@@ -526,8 +526,11 @@ def test_link_cut_bipartite_theorem_4_4(gen, oracle_lib):
     reached exactly d(tau_e) times (the number of edges of G joining the two
     parts of tau_e - e); hence the weighted mean of f' with weights
     d(tau)/d(tau_e) is the mean of f' over the trees of G' through e, and the
-    weights themselves average R/(1-R) with R the share of G''s trees through e."""
+    weights themselves average R/(1-R) with R the share of G''s trees through e.
+    Some new trees are reached more often than others, yet each carries the
+    same total weight (the point Example 4.3 makes on a schematic case)."""
     from oracle import exact as E
+    uneven = False
     for g, e in _ism_cases(gen):
         if e is None:
             e = _non_edge(g)
@@ -541,6 +544,7 @@ def test_link_cut_bipartite_theorem_4_4(gen, oracle_lib):
         new = E.spanning_trees(g2.offsets, g2.indices, root)
         through = {tuple(int(x) for x in t): t for t in new if t[u] == v or t[v] == u}
         reached = {k: 0 for k in through}
+        weight_of = {k: Fraction(0) for k in through}
         wf = Fraction(0)
         wsum = Fraction(0)
         for t in old:
@@ -556,11 +560,16 @@ def test_link_cut_bipartite_theorem_4_4(gen, oracle_lib):
                 w = Fraction(d, d_new) / d          # choice probability 1/d(tau), weight d(tau)/d(tau_e)
                 wf += w * oracle_lib.f_of_tree(P2, te)
                 wsum += w
+                weight_of[key] += w
         for key, t in through.items():
             assert reached[key] == len(oracle_lib.crossing_edges(g2.offsets, g2.indices, t, u, v)[0]) - 1
+        # reached unevenly, yet every new tree carries the same total weight (Example 4.3's point)
+        uneven |= len(set(reached.values())) > 1
+        assert set(weight_of.values()) == {Fraction(1)}
         mean_through = Fraction(sum(oracle_lib.f_of_tree(P2, t) for t in through.values()), len(through))
         assert wf / wsum == mean_through
         assert wsum / len(old) == Fraction(len(through), len(old))   # = R / (1 - R)
+    assert uneven
 
 
 def test_cut_link_bipartite_theorem_4_5(gen, oracle_lib):
