@@ -111,23 +111,34 @@ def host_cpu():
     return os.cpu_count() or 1, model
 
 
-def cpu_baseline(g, seed: int, first: int, threads: int, per_thread: int, what: str = "the same workload"):
+def cpu_baseline(g, seed: int, first: int, threads: int, per_thread: int, what: str = "the same workload",
+                 min_s: float = 10.0, target_s: float = 15.0):
     """The CPU oracle as it stands (sequential Wilson per sample, the per-edge
     f of Theorem 3.4, exact sums) on `threads` host threads, samples split
-    across them, over a bounded sample of `threads * per_thread` ids of the
-    workload; graph preparation is outside the timed region."""
+    across them, over a bounded sample of the workload: ids first ..
+    first + threads * per_thread - 1, then, if those took less than min_s
+    seconds, the next ids (whole rounds of `threads`, at most 64 times as
+    many), sized by the rate just measured to bring the timed work to about
+    target_s seconds.  Graph preparation is outside the timed region."""
     import oracle
     P = oracle.prepare_graph(g)
     count = threads * per_thread
     t0 = time.perf_counter()
     oracle.estimate_f(P, seed=seed, s0=first, count=count, threads=threads)
     dt = time.perf_counter() - t0
+    if dt < min_s:
+        rounds = min(64 * per_thread, max(1, math.ceil((target_s - dt) / max(dt, 1e-6) * per_thread)))
+        more = threads * rounds
+        t1 = time.perf_counter()
+        oracle.estimate_f(P, seed=seed, s0=first + count, count=more, threads=threads)
+        dt += time.perf_counter() - t1
+        count += more
     nproc, model = host_cpu()
     return {"value": count / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
             "nproc": nproc, "cpu_model": model,
-            "sample": "samples %d..%d of %s (%d per thread on %d threads), %.1f s; the rate over this "
+            "sample": "samples %d..%d of %s (%d on %d threads), %.1f s; the rate over this "
                       "bounded sample stands for the workload's" %
-                      (first, first + count - 1, what, per_thread, threads, dt)}
+                      (first, first + count - 1, what, count, threads, dt)}
 
 
 def serving_leg(seed: int, graphs: int, lo: int, hi: int, samples: int, rate: float, duration: float,

@@ -368,9 +368,18 @@ def test_bench_refuses_more_than_one_gpu():
 
 def test_bench_cpu_baseline_record(gen):
     """The oracle leg of the benchmark on a tiny graph: a positive rate over
-    exactly threads x per_thread samples, and the host it ran on."""
+    exactly threads x per_thread samples when that pass is long enough, and
+    the host it ran on; a pass shorter than min_s is followed by the next ids,
+    in whole rounds of the thread count, up to about target_s of work."""
     import bench
-    rec = bench.cpu_baseline(gen.grid(6, 6), seed=3, first=10, threads=2, per_thread=3, what="the 6x6 grid")
+    g = gen.grid(6, 6)
+    rec = bench.cpu_baseline(g, seed=3, first=10, threads=2, per_thread=3, what="the 6x6 grid", min_s=0.0)
     assert rec["kind"] == "oracle" and rec["unit"] == "samples/s" and rec["cores"] == 2
     assert rec["value"] > 0 and rec["nproc"] >= 1
-    assert rec["sample"].startswith("samples 10..15 of the 6x6 grid (3 per thread on 2 threads)")
+    assert rec["sample"].startswith("samples 10..15 of the 6x6 grid (6 on 2 threads)")
+    rec = bench.cpu_baseline(g, seed=3, first=10, threads=2, per_thread=3, what="the 6x6 grid",
+                             min_s=0.05, target_s=0.1)
+    first, last = (int(x) for x in rec["sample"].split()[1].split(".."))
+    count = last - first + 1
+    assert first == 10 and count > 6 and count % 2 == 0 and count <= 6 + 2 * 64 * 3
+    assert "(%d on 2 threads)" % count in rec["sample"]
