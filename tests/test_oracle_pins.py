@@ -46,6 +46,22 @@ def test_philox_matches_rocrand(oracle_lib, rocrand_probe):
         assert got.tolist() == r, (c, got, r)
 
 
+def test_arrow_counter_layout_with_high_words(oracle_lib):
+    """The arrow of (seed, s, v, k) is the Philox block (checked against
+    rocRAND above) at counter (k, v, s_lo, s_hi) and key (seed_lo, seed_hi),
+    mapped to floor(x deg / 2^64) with x = o0 | o1 << 32, also when the high
+    words of the seed and of the sample id are not zero."""
+    rng = np.random.default_rng(11)
+    for _ in range(300):
+        seed = int(rng.integers(0, 2 ** 63)) * 2 + int(rng.integers(0, 2))
+        s = int(rng.integers(0, 2 ** 40))
+        v, k = int(rng.integers(0, 2 ** 31)), int(rng.integers(0, 2 ** 20))
+        deg = int(rng.integers(1, 1 << 20))
+        o = oracle_lib.philox4x32_10([k, v, s & 0xFFFFFFFF, s >> 32], [seed & 0xFFFFFFFF, seed >> 32])
+        x = int(o[0]) | (int(o[1]) << 32)
+        assert oracle_lib.arrow(seed, s, v, k, deg) == (x * deg) >> 64
+
+
 def test_arrow_slots_uniform(oracle_lib):
     """Slots drawn for fixed degree are uniform (chi-square) and in range."""
     for deg in (2, 3, 7, 13):
