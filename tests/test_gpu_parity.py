@@ -145,6 +145,32 @@ def test_lean_looks_change_nothing(kc, oracle_lib, graphs, lean):
             assert np.array_equal(f.cpu().numpy(), ref_f)
 
 
+def test_lean_looks_with_the_large_chain_table(kc, oracle_lib, graphs):
+    """Lean looks together with the 2,048-chain table (kernel variants of
+    their own, in the persistent launch and in a captured batch): trees, draw
+    counts and f stay exact, also with more samples than slots."""
+    for name in ("K5", "grid32", "road3k", "social3k"):
+        g = graphs[name]
+        _say("lean + 2048 chains", name)
+        P = oracle_lib.prepare_graph(g)
+        ref_par, ref_cnt, ref_steps = oracle_lib.sample(P, seed=43, s0=600, count=24, threads=8)
+        ref_f = np.array([oracle_lib.f_of_tree(P, t) for t in ref_par], np.int64)
+        with kc.Graph.from_graph(g) as G:
+            G.set_option(kc.KC_OPT_CHAINS, 2048)
+            G.set_option(kc.KC_OPT_LEAN_LOOKS, 2)
+            par, cnt, stp = G.sample_trees(43, 600, 24)
+            assert np.array_equal(par.cpu().numpy(), ref_par)
+            assert np.array_equal(cnt.cpu().numpy().astype(np.uint32), ref_cnt)
+            assert np.array_equal(stp.cpu().numpy(), ref_steps)
+            G.set_option(kc.KC_OPT_SLOTS, 5)
+            _, f, _ = G.estimate(43, 600, 24, per_sample=True)
+            assert np.array_equal(f.cpu().numpy(), ref_f)
+            with kc.Batch([G], [43], [600], [24]) as B:
+                B.launch()
+                B.results()
+                assert np.array_equal(B.f(0).cpu().numpy(), ref_f)
+
+
 def test_batch_split_invariance(kc, graphs):
     g = graphs["road3k"]
     with kc.Graph.from_graph(g) as G:
