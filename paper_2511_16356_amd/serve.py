@@ -75,7 +75,7 @@ class _Budget:
         self.reserves = collections.Counter()
         self.cv = threading.Condition()
 
-    def reserve(self) -> int:
+    def largest_reserve(self) -> int:
         return max(self.reserves, default=0)
 
     def acquire(self, nbytes: int, timeout: float = None, hopeless=None, taken=None,
@@ -94,7 +94,7 @@ class _Budget:
         def fits():
             if self.free < nbytes:
                 return False
-            return steady == 0 or self.resident + steady + max(self.reserve(), reserve) <= self.total
+            return steady == 0 or self.resident + steady + max(self.largest_reserve(), reserve) <= self.total
 
         with self.cv:
             while not fits():

@@ -275,7 +275,7 @@ def test_admission_keeps_room_for_an_update(serve):
     srv = serve.Server(budget_bytes=2 * one + tmp // 2, workspace_share=1 << 20)
     try:
         srv.add_graph(0, 0, seed=0, samples=8)
-        assert srv.budget.resident == one and srv.budget.reserve() == tmp
+        assert srv.budget.resident == one and srv.budget.largest_reserve() == tmp
         with pytest.raises(KcError) as ei:
             srv.add_graph(1, 1, seed=1, samples=8, timeout=0.2)
         assert ei.value.status == 3 and "for an update" in str(ei.value)
@@ -291,12 +291,12 @@ def test_admission_keeps_room_for_an_update(serve):
             srv.add_graph(2, 2, seed=2, samples=8, timeout=0.2)
         finally:
             _FakeGraph.info = orig
-        assert srv.budget.resident == one + need and srv.budget.reserve() == tmp
+        assert srv.budget.resident == one + need and srv.budget.largest_reserve() == tmp
         srv.remove_graph(0)
-        assert srv.budget.resident == need and srv.budget.reserve() == serve.update_bytes(small, 8)
+        assert srv.budget.resident == need and srv.budget.largest_reserve() == serve.update_bytes(small, 8)
     finally:
         srv.close()
-    assert srv.budget.free == srv.budget.total and srv.budget.resident == 0 and srv.budget.reserve() == 0
+    assert srv.budget.free == srv.budget.total and srv.budget.resident == 0 and srv.budget.largest_reserve() == 0
 
 
 def test_bench_exact_kemeny_closed_forms(gen):
