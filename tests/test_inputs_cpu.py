@@ -35,6 +35,31 @@ def test_social_graph_shape(gen):
     assert gen.is_connected(g)
 
 
+def test_dense_graph_shape(gen):
+    """The dense power-law workload (Chung-Lu, 3M vertices, exponent 2.0, mean
+    76, cap 30,000): its size, largest degree and int64 offsets, sampled rows
+    valid, and the exact arrays by SHA-256, so the graph the benchmark's
+    stored counter readings were taken on is the one every run generates.
+    (Connectivity is checked by kc_graph_create on every run.)"""
+    import hashlib
+    g = gen.workload("dense")
+    assert (g.n, g.two_m // 2) == (2_999_979, 113_672_771)
+    assert g.offsets.dtype == np.int64 and g.indices.dtype == np.int32
+    deg = np.diff(g.offsets)
+    assert int(deg.max()) == 27_586 and int(deg.min()) >= 1
+    rng = np.random.default_rng(0)
+    for v in rng.integers(0, g.n, 2000):
+        row = g.indices[g.offsets[v]:g.offsets[v + 1]]
+        assert np.all(np.diff(row) > 0) and not np.any(row == v)
+        for u in row[:4]:  # the reverse entry exists
+            other = g.indices[g.offsets[u]:g.offsets[u + 1]]
+            assert other[np.searchsorted(other, v)] == v
+    assert hashlib.sha256(g.offsets.tobytes()).hexdigest() == \
+        "25871c5d9ab852c3e1e8b6cacdedc66bd2c5e47cb42c74a1b41cb61a2260b682"
+    assert hashlib.sha256(g.indices.tobytes()).hexdigest() == \
+        "b29c91c9f2f2f0279a9ddcc59f29bced54a14838e7977dfab97139a0e89dca30"
+
+
 @pytest.mark.parametrize("seed", [0, 3])
 def test_serving_graphs_valid(gen, seed):
     for g in gen.serving_graphs(6, 2_000, 6_000, seed):
