@@ -91,3 +91,41 @@ def test_probe_library_exports_its_header():
     lib = ctypes.CDLL(build_lib.PROBE_LIB)
     for name in decl:
         assert hasattr(lib, name), name
+
+
+def _oracle_imports(path):
+    """(enclosing function name or None, line) of every import of the oracle in a Python file."""
+    import ast
+    tree = ast.parse(open(path).read(), filename=path)
+    found = []
+
+    def visit(node, func):
+        for child in ast.iter_child_nodes(node):
+            f = child.name if isinstance(child, (ast.FunctionDef, ast.AsyncFunctionDef)) else func
+            if isinstance(child, ast.Import) and any(a.name.split(".")[0] == "oracle" for a in child.names):
+                found.append((func, child.lineno))
+            if isinstance(child, ast.ImportFrom) and (child.module or "").split(".")[0] == "oracle":
+                found.append((func, child.lineno))
+            visit(child, f)
+
+    visit(tree, None)
+    return found
+
+
+def test_product_never_reaches_the_oracle():
+    """The product path has no route to the CPU oracle: nothing in the package
+    (Python, HIP, C++) or the public headers names it, and outside tests/ only
+    the build step and smoke check of __graft_entry__.py and the benchmark's
+    CPU-baseline leg import it."""
+    for top in ("paper_2511_16356_amd", "include", "graphgen"):
+        for dirpath, _, files in os.walk(os.path.join(ROOT, top)):
+            for name in files:
+                if not name.endswith((".py", ".hip", ".cpp", ".h", ".c")):
+                    continue
+                path = os.path.join(dirpath, name)
+                text = open(path, errors="replace").read()
+                assert not re.search(r"^\s*(import\s+oracle|from\s+oracle\b)", text, re.M), path
+                assert not re.search(r'#\s*include\s*[<"][^>"]*oracle', text), path
+                assert "kc_oracle" not in text and "orc_" not in text, path
+    assert {f for f, _ in _oracle_imports(os.path.join(ROOT, "bench.py"))} == {"cpu_baseline"}
+    assert {f for f, _ in _oracle_imports(os.path.join(ROOT, "__graft_entry__.py"))} <= {"build", "smoke"}
