@@ -129,3 +129,16 @@ def test_product_never_reaches_the_oracle():
                 assert "kc_oracle" not in text and "orc_" not in text, path
     assert {f for f, _ in _oracle_imports(os.path.join(ROOT, "bench.py"))} == {"cpu_baseline"}
     assert {f for f, _ in _oracle_imports(os.path.join(ROOT, "__graft_entry__.py"))} <= {"build", "smoke"}
+
+
+def test_oracle_never_reaches_the_product():
+    """The oracle shares no code with the HIP path: nothing under oracle/
+    imports the package, includes its headers or loads its library."""
+    for dirpath, _, files in os.walk(os.path.join(ROOT, "oracle")):
+        for name in files:
+            if not name.endswith((".py", ".c", ".h")):
+                continue
+            path = os.path.join(dirpath, name)
+            text = open(path, errors="replace").read()
+            assert "paper_2511_16356_amd" not in text and "libkc_mi355x" not in text, path
+            assert not re.search(r'#\s*include\s*[<"](kc|kc_internal|kc_host)\.h', text), path
