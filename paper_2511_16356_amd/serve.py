@@ -252,8 +252,9 @@ class Server:
         self.one_at_a_time = one_at_a_time
 
     def remove_graph(self, gid: int):
-        """Free a resident graph once its queued requests are done; its bytes
-        return to the budget and its worker ends."""
+        """Free a resident graph once every request submitted so far (on any
+        graph) is done; its bytes and its update reserve return to the budget
+        and its worker ends."""
         self.drain()
         with self.done_cv:
             q = self.queues.pop(gid)
